@@ -1,0 +1,99 @@
+"""Volume potential by direct quadrature (oracle only).
+
+V(x) = (1/2 pi) sum_B int_B log|x - y| p_B(y) dy over every leaf B with
+nonzero data, where p_B is the degree-(K-1) tensor Chebyshev interpolant of
+the leaf's K x K samples (Section 1, eqs. volpot and greenf; Section 4.1:
+the VFMM computes exactly this for the piecewise-polynomial f^e up to its
+far-field tolerance).  The double sum runs in plain C (volume.c), compiled on
+first use with gcc.
+"""
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+from . import cheb
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "volume.c")
+_LIB = os.path.join(_HERE, "_volume.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force=False):
+    """Compile volume.c into _volume.so (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            d = ctypes.POINTER(ctypes.c_double)
+            lib.oracle_volume.argtypes = [ctypes.c_int, d, d, ctypes.c_int, d, d, d, ctypes.c_int, d,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, d]
+            lib.oracle_volume.restype = ctypes.c_int
+            lib.oracle_gauss_legendre.argtypes = [ctypes.c_int, d, d]
+            lib.oracle_gauss_legendre.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gauss_legendre(q):
+    x = np.zeros(q)
+    w = np.zeros(q)
+    if _load().oracle_gauss_legendre(q, _ptr(x), _ptr(w)) != 0:
+        raise ValueError("bad order")
+    return x, w
+
+
+def leaf_coefficients(values, K):
+    """Chebyshev coefficients c[a, b] of each leaf's tensor interpolant;
+    values has shape (L, K*K) with node (a, b) at flat a*K + b."""
+    C = cheb.coef_matrix(K)
+    V = np.asarray(values, dtype=np.float64).reshape(-1, K, K)
+    return np.einsum("ai,lij,bj->lab", C, V, C)
+
+
+def potential_boxes(tx, ty, cx, cy, h, coef, K, qf=None, qn=12, M=28, far_ratio=1.0):
+    """V at targets from boxes given by centres, sides and coefficients."""
+    tx = np.ascontiguousarray(tx, dtype=np.float64).reshape(-1)
+    ty = np.ascontiguousarray(ty, dtype=np.float64).reshape(-1)
+    cx = np.ascontiguousarray(cx, dtype=np.float64).reshape(-1)
+    cy = np.ascontiguousarray(cy, dtype=np.float64).reshape(-1)
+    h = np.ascontiguousarray(np.broadcast_to(h, cx.shape), dtype=np.float64)
+    coef = np.ascontiguousarray(coef, dtype=np.float64).reshape(cx.size, K * K)
+    if qf is None:
+        qf = K + 16
+    out = np.zeros(tx.size)
+    rc = _load().oracle_volume(tx.size, _ptr(tx), _ptr(ty), cx.size, _ptr(cx), _ptr(cy), _ptr(h), K,
+                               _ptr(coef), int(qf), int(qn), int(M), float(far_ratio), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_volume: bad parameters")
+    return out
+
+
+def potential(tree, fe, K, tx, ty, sources=None, **kw):
+    """V at targets (tx, ty) from the leaves of ``tree`` carrying data fe
+    (shape (L, K*K)); leaves whose data is identically zero are skipped;
+    ``sources`` optionally restricts the source leaves."""
+    fe = np.asarray(fe, dtype=np.float64)
+    cx, cy = tree.centers()
+    h = tree.h()
+    idx = np.arange(tree.n) if sources is None else np.asarray(sources)
+    idx = idx[np.any(fe[idx] != 0.0, axis=1)]
+    coef = leaf_coefficients(fe[idx], K)
+    return potential_boxes(tx, ty, cx[idx], cy[idx], h[idx], coef, K, **kw)

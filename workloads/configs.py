@@ -1,0 +1,81 @@
+"""Named, seeded workload configurations.
+
+Each configuration fixes the root box, the leaf grid size K, the FMM order p,
+the domain, the analytic data f = Laplacian(u) and how the quad-tree is
+refined.  Tree *construction* is not done here (it belongs to the host side of
+the solver); this module only states the recipe.
+
+* ``disk_uniform3``: root [-1,1]^2, uniform depth 3 (64 leaves), K = 8,
+  disk of radius 0.6, u = exp(-((x-0.1)^2 + (y+0.2)^2)/0.05), p = 20.
+* ``starfish_adaptive``: starfish r = 0.5 + 0.15 cos(5 theta), u a sum of four
+  Gaussians with widths drawn from U[0.01, 0.1] and centres drawn uniformly in
+  the domain (seed 1), K = 16, adaptive refinement on Chebyshev tails, depth
+  at most 9; about 1e6 leaf nodes.
+* ``wedge_adaptive``: [-0.6,0.6]^2 minus the wedge |arg z| < pi/6, same kind
+  of data (seed 3), K = 16, about 4e6 leaf nodes.
+* small variants used by the tests (``disk_tiny``, ``starfish_small``,
+  ``disk_adaptive_small``).
+"""
+import math
+
+import numpy as np
+
+from .domains import Disk, Starfish, SquareMinusWedge
+from .functions import GaussianSum
+
+
+def _seeded_gaussians(domain, n, wlo, whi, seed, box=0.7):
+    rng = np.random.default_rng(seed)
+    widths = rng.uniform(wlo, whi, n)
+    centers = []
+    while len(centers) < n:
+        p = rng.uniform(-box, box, 2)
+        if domain.inside(p[0], p[1]):
+            centers.append(p)
+    return GaussianSum(np.array(centers), widths)
+
+
+def _cfg(name):
+    if name == "disk_uniform3":
+        dom = Disk(0.6)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=8, p=20, domain=dom,
+                    fun=GaussianSum([[0.1, -0.2]], [0.05]),
+                    tree=dict(kind="uniform", depth=3), seed=None)
+    if name == "disk_tiny":
+        dom = Disk(0.6)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=8, p=30, domain=dom,
+                    fun=GaussianSum([[0.1, -0.2]], [0.05]),
+                    tree=dict(kind="uniform", depth=2), seed=None)
+    if name == "disk_adaptive_small":
+        dom = Disk(0.55, 0.03, -0.02)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=8, p=40, domain=dom,
+                    fun=GaussianSum([[0.15, -0.1], [-0.2, 0.2]], [0.01, 0.05], [1.0, -0.5]),
+                    tree=dict(kind="adaptive", tol=1e-6, max_depth=6, min_cut_level=3),
+                    seed=None)
+    if name == "starfish_small":
+        dom = Starfish(0.5, 0.15, 5)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=16, p=40, domain=dom,
+                    fun=_seeded_gaussians(dom, 4, 0.01, 0.1, seed=1),
+                    tree=dict(kind="adaptive", tol=1e-6, max_depth=6, min_cut_level=4),
+                    seed=1)
+    if name == "starfish_adaptive":
+        dom = Starfish(0.5, 0.15, 5)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=16, p=40, domain=dom,
+                    fun=_seeded_gaussians(dom, 4, 0.01, 0.1, seed=1),
+                    tree=dict(kind="adaptive", tol=1e-11, max_depth=9, min_cut_level=6),
+                    seed=1)
+    if name == "wedge_adaptive":
+        dom = SquareMinusWedge(0.6, math.pi / 6)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=16, p=40, domain=dom,
+                    fun=_seeded_gaussians(dom, 4, 0.005, 0.1, seed=3),
+                    tree=dict(kind="adaptive", tol=1e-12, max_depth=10, min_cut_level=7),
+                    seed=3)
+    raise KeyError(name)
+
+
+CONFIG_NAMES = ("disk_uniform3", "disk_tiny", "disk_adaptive_small", "starfish_small",
+                "starfish_adaptive", "wedge_adaptive")
+
+
+def get_config(name):
+    return _cfg(name)
