@@ -1,0 +1,169 @@
+/*
+ * vfx: function extension from cut leaves + adaptive volume FMM, on one GPU.
+ *
+ * The method (Fryklund & Greengard, "An FMM accelerated Poisson solver for
+ * complicated geometries in the plane using function extension"):
+ *   - the source f is sampled on K x K first-kind Chebyshev grids on the
+ *     leaves of an adaptive, level-restricted quad-tree over a square root
+ *     box (Section 4);
+ *   - on every cut leaf (a leaf the boundary crosses) f is known only at the
+ *     interior points of a universal stencil X = X_S u X_Sbar u G, and is
+ *     extended by least squares through the universal interpolation matrix
+ *     A_{X,G} (Section 3.2), resampled from its total-order Chebyshev
+ *     expansion on the extension square onto every leaf of the cut leaf's
+ *     extension list (Section 4.1, eq. chebexpbarS);
+ *   - the volume potential V(x) = int (1/2pi) log|x-y| f^e(y) dy of the
+ *     extended data is evaluated at every leaf node by a volume FMM
+ *     (Section 1 eqs. volpot/greenf/volinte; Section 4, the near/far split
+ *     of the VFMM remark and the tree-levels figure).
+ *
+ * Conventions
+ *   - Root box: centre (root_cx, root_cy), side root_size.  A leaf at level
+ *     l with integer position (ix, iy), 0 <= ix, iy < 2^l, has side
+ *     h = root_size / 2^l and centre
+ *     (root_cx - root_size/2 + (ix + 1/2) h, root_cy - root_size/2 + (iy + 1/2) h).
+ *   - Leaf grid: 1D nodes t_a = -cos((2a+1) pi / (2K)), a = 0..K-1
+ *     (ascending, first kind); node (a, b) of a leaf sits at
+ *     (cx + h t_a / 2, cy + h t_b / 2) and has flat index a*K + b.
+ *   - Stencil of a cut leaf (Section 3.2), in the reference frame of its
+ *     extension square Sbar = [-1,1]^2 (side 3h, same centre), so the leaf
+ *     itself is [-1/3,1/3]^2: first the K*K leaf nodes (t_a/3, t_b/3), then
+ *     the Kbar*Kbar first-kind nodes of Sbar, then the N_G support nodes G
+ *     (Padua points of degree deg, N_G = (deg+1)(deg+2)/2), |X| points in all.
+ *     vfx_stencil_points returns their coordinates.
+ *   - Cut leaves are numbered in ascending leaf order; that order is also the
+ *     canonical order of the extension-list tie rule.
+ *
+ * Ownership and threading
+ *   - Every pointer argument is owned by the caller.  Host arrays passed to
+ *     vfx_create / vfx_plan_create are copied; device arrays passed to
+ *     vfx_execute must stay valid until the work on the stream completes.
+ *   - A context or plan must not be used from two threads at once.
+ *   - Every call returns VFX_OK (0) or a negative status; vfx_last_error()
+ *     returns a thread-local description of the last failure.  No C++
+ *     exception crosses this interface.
+ */
+#ifndef VFX_H
+#define VFX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VFX_OK 0
+#define VFX_EINVAL (-1)  /* bad argument (null pointer, size out of range)    */
+#define VFX_ETREE (-2)   /* tree not a quad-tree partition, not balanced, or  */
+                         /* extension restriction violated                    */
+#define VFX_EHIP (-4)    /* HIP runtime error                                 */
+#define VFX_ENOMEM (-5)  /* host or device allocation failed                  */
+
+typedef struct vfx_ctx vfx_ctx;
+typedef struct vfx_plan vfx_plan;
+
+typedef struct {
+  int32_t K;         /* leaf grid size, 2..16 (the paper fixes K = 8)          */
+  int32_t Kbar;      /* grid size on the extension square, 2..16 (paper: 12)  */
+  int32_t deg;       /* stencil degree; N_G = (deg+1)(deg+2)/2 (paper: 66)    */
+  int32_t p;         /* FMM expansion order: terms 0..p, 4 <= p <= 60         */
+  double root_cx, root_cy, root_size;
+} vfx_params;
+
+/* Create a context on the current HIP device: builds the universal tables
+ * (stencil matrix, near-field tables, expansion operators) on the host and
+ * uploads them.  Errors: VFX_EINVAL for parameters out of range. */
+int vfx_create(const vfx_params* prm, vfx_ctx** out);
+int vfx_destroy(vfx_ctx* ctx);
+
+/* Sizes of the stencil: |X| and N_G. */
+int vfx_stencil_size(const vfx_ctx* ctx, int32_t* n_stencil, int32_t* n_support);
+/* Stencil coordinates in the Sbar frame, xy[2*k], xy[2*k+1]; host array of
+ * 2*|X| doubles. */
+int vfx_stencil_points(const vfx_ctx* ctx, double* xy);
+/* The K 1D leaf nodes t_a (host array of K doubles). */
+int vfx_leaf_nodes(const vfx_ctx* ctx, double* t);
+
+typedef struct {
+  int32_t n_leaves;
+  const int32_t* level;    /* host, n_leaves                                  */
+  const int32_t* ix;       /* host, n_leaves                                  */
+  const int32_t* iy;       /* host, n_leaves                                  */
+  const int8_t* kind;      /* host, n_leaves: 0 exterior, 1 regular, 2 cut    */
+  const uint8_t* cut_mask; /* host, n_cut x |X| bytes: 1 = stencil point lies */
+                           /* inside the domain (cut leaves in leaf order)    */
+} vfx_tree;
+
+/* Build a plan for one tree (Section 4 data structures): the box hierarchy,
+ * the FMM interaction lists, the extension lists (closest cut centre, later
+ * cut leaf wins ties) and, per cut leaf, the pseudo-inverse of the interior
+ * rows of A_{X,G} (singular values below 1e-13 sigma_max dropped).  Errors:
+ * VFX_ETREE when the leaves do not tile the root, the tree is not level
+ * restricted, or a cut leaf would extend onto a coarser neighbour. */
+int vfx_plan_create(vfx_ctx* ctx, const vfx_tree* tree, vfx_plan** out);
+int vfx_plan_destroy(vfx_plan* plan);
+
+typedef struct {
+  int32_t n_leaves, n_boxes, n_levels, n_cut, n_ext_targets;
+  int64_t n_list1, n_list2, n_list3, n_list4;
+  int64_t pinv_doubles;    /* size of the stored per-cut-leaf operators      */
+  double plan_seconds;     /* host time spent in vfx_plan_create             */
+} vfx_plan_stats;
+int vfx_plan_stats_get(const vfx_plan* plan, vfx_plan_stats* out);
+
+/* Owner cut leaf of every leaf (host array, n_leaves int32): the cut leaf
+ * whose extension list contains it, itself for a cut leaf, -1 otherwise. */
+int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
+
+/*
+ * Run the extension and the volume FMM on `stream` (a hipStream_t; NULL for
+ * the default stream).  All four arrays are device memory, row-major:
+ *   f_leaf  n_leaves x K^2   samples of f on regular leaves (other rows
+ *                            are not read)
+ *   f_cut   n_cut x |X|      samples of f at the stencil points of each cut
+ *                            leaf (exterior entries are not read)
+ *   fe_out  n_leaves x K^2   extended data f^e (written)
+ *   V_out   n_leaves x K^2   V[f^e] at every leaf node (written)
+ * Asynchronous: returns after enqueueing.  Errors: VFX_EINVAL for null
+ * pointers, VFX_EHIP if a launch fails.
+ */
+int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
+                double* V_out, void* stream);
+
+/* Per-phase timing with HIP events recorded on the execute stream.  When
+ * enabled, every vfx_execute records events around its phases; the query
+ * synchronises on the last event and returns milliseconds of the most
+ * recent execute, in this order: extension, P2M+M2M, M2L+P2L, L2L,
+ * near field, far field (L2P+M2P), total.  n_out must be >= 7. */
+int vfx_plan_set_timing(vfx_plan* plan, int enable);
+int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
+
+/* ---- inspection (host only; for tests of the host logic) -------------- */
+/* Copy a universal table into `out` (host, exactly `count` doubles):
+ *   which 0: near-field table of configuration `index` (0..32), n x n, [j][i]
+ *              = int_{S_c} log|x_i - y| l_j(y) dy in units of the target side
+ *         1: A_{X,G}, |X| x N_G row-major
+ *         2: P2M, (p+1) x n complex (re, im) pairs, [k][j]
+ *         3: P2L of slot `index` (0..35), (p+1) x n complex, [l][j]
+ *         4: M2L of slot `index` (0..48), (p+1) x (p+1) complex, [k][l]
+ *         5: M2M of child `index` (0..3), (p+1) x (p+1) complex, [k][l]
+ *         6: L2L of child `index` (0..3), (p+1) x (p+1) complex, [k][l]
+ *         7: L2P, n x (p+1) complex, [i][l]
+ *         8: unit-square quadrature weights, n
+ * VFX_EINVAL if `which`, `index` or `count` does not match. */
+int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count);
+/* Interaction list `which` (1..4) of a plan as CSR arrays (host):
+ * lists 1 and 3 are per leaf (ptr has n_leaves+1 entries), lists 2 and 4 per
+ * box (n_boxes+1).  src: list 1 and 4 hold leaf indices, 2 and 3 box
+ * indices.  cfg: table configuration (list 1: 0..32, list 2: M2L slot,
+ * list 4: P2L slot, list 3: 0).  Sizes from vfx_plan_stats_get. */
+int vfx_plan_lists(const vfx_plan* plan, int which, int32_t* ptr, int32_t* src, int32_t* cfg);
+/* Boxes of a plan (n_boxes entries each): level, position, leaf index or -1. */
+int vfx_plan_boxes(const vfx_plan* plan, int32_t* level, int32_t* ix, int32_t* iy, int32_t* leaf);
+
+const char* vfx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

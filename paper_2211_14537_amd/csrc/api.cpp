@@ -1,0 +1,274 @@
+// C-ABI entry points of the vfx library (declared in include/vfx.h).
+#include <cstring>
+#include <exception>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+
+#include "vfx_internal.h"
+
+struct vfx_ctx {
+  vfx::Context c;
+};
+struct vfx_plan {
+  vfx::Plan p;
+};
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// Universal tables depend only on (K, Kbar, deg, p); building them costs
+// seconds at K = 16, so they are kept for the life of the process.
+std::mutex g_cache_mu;
+std::map<std::tuple<int, int, int, int>, std::shared_ptr<const vfx::Tables>> g_cache;
+
+std::shared_ptr<const vfx::Tables> cached_tables(const vfx_params& prm) {
+  auto key = std::make_tuple(prm.K, prm.Kbar, prm.deg, prm.p);
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(key);
+  if (it != g_cache.end()) return it->second;
+  auto T = std::make_shared<vfx::Tables>();
+  T->K = prm.K;
+  T->Kbar = prm.Kbar;
+  T->deg = prm.deg;
+  T->p = prm.p;
+  vfx::build_tables(*T);
+  g_cache[key] = T;
+  return T;
+}
+}  // namespace
+
+extern "C" {
+
+const char* vfx_last_error(void) { return g_err.c_str(); }
+
+int vfx_create(const vfx_params* prm, vfx_ctx** out) {
+  if (!prm || !out) return fail(VFX_EINVAL, "vfx_create: null argument");
+  *out = nullptr;
+  if (prm->K < 2 || prm->K > 16) return fail(VFX_EINVAL, "vfx_create: K must be in 2..16");
+  if (prm->Kbar < 2 || prm->Kbar > 16) return fail(VFX_EINVAL, "vfx_create: Kbar must be in 2..16");
+  if (prm->deg < 1 || prm->deg > 15) return fail(VFX_EINVAL, "vfx_create: deg must be in 1..15");
+  if (prm->p < 4 || prm->p > 60) return fail(VFX_EINVAL, "vfx_create: p must be in 4..60");
+  if (!(prm->root_size > 0)) return fail(VFX_EINVAL, "vfx_create: root_size must be positive");
+  try {
+    auto T = cached_tables(*prm);
+    std::unique_ptr<vfx_ctx> c(new vfx_ctx);
+    c->c.T = *T;
+    c->c.T.root_cx = prm->root_cx;
+    c->c.T.root_cy = prm->root_cy;
+    c->c.T.root_size = prm->root_size;
+    *out = c.release();
+    return VFX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_create: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(VFX_EINVAL, std::string("vfx_create: ") + e.what());
+  }
+}
+
+int vfx_destroy(vfx_ctx* ctx) {
+  if (!ctx) return VFX_OK;
+  vfx::free_tables_device(&ctx->c);
+  delete ctx;
+  return VFX_OK;
+}
+
+int vfx_stencil_size(const vfx_ctx* ctx, int32_t* nX, int32_t* nG) {
+  if (!ctx || !nX || !nG) return fail(VFX_EINVAL, "vfx_stencil_size: null argument");
+  *nX = ctx->c.T.nX;
+  *nG = ctx->c.T.nG;
+  return VFX_OK;
+}
+
+int vfx_stencil_points(const vfx_ctx* ctx, double* xy) {
+  if (!ctx || !xy) return fail(VFX_EINVAL, "vfx_stencil_points: null argument");
+  std::memcpy(xy, ctx->c.T.stencil_xy.data(), sizeof(double) * ctx->c.T.stencil_xy.size());
+  return VFX_OK;
+}
+
+int vfx_leaf_nodes(const vfx_ctx* ctx, double* t) {
+  if (!ctx || !t) return fail(VFX_EINVAL, "vfx_leaf_nodes: null argument");
+  std::memcpy(t, ctx->c.T.t.data(), sizeof(double) * ctx->c.T.t.size());
+  return VFX_OK;
+}
+
+int vfx_plan_create(vfx_ctx* ctx, const vfx_tree* tree, vfx_plan** out) {
+  if (!ctx || !tree || !out) return fail(VFX_EINVAL, "vfx_plan_create: null argument");
+  *out = nullptr;
+  try {
+    std::unique_ptr<vfx_plan> p(new vfx_plan);
+    p->p.ctx = &ctx->c;
+    std::string err;
+    int rc = vfx::build_host_plan(ctx->c.T, tree, p->p.H, err);
+    if (rc) return fail(rc, "vfx_plan_create: " + err);
+    *out = p.release();
+    return VFX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_plan_create: out of host memory");
+  } catch (const std::exception& e) {
+    return fail(VFX_EINVAL, std::string("vfx_plan_create: ") + e.what());
+  }
+}
+
+int vfx_plan_destroy(vfx_plan* plan) {
+  if (!plan) return VFX_OK;
+  vfx::free_plan_device(&plan->p);
+  delete plan;
+  return VFX_OK;
+}
+
+int vfx_plan_stats_get(const vfx_plan* plan, vfx_plan_stats* o) {
+  if (!plan || !o) return fail(VFX_EINVAL, "vfx_plan_stats_get: null argument");
+  const vfx::HostPlan& H = plan->p.H;
+  o->n_leaves = H.L;
+  o->n_boxes = H.B;
+  o->n_levels = H.nlev;
+  o->n_cut = H.ncut;
+  o->n_ext_targets = (int32_t)H.ext_tgt.size();
+  o->n_list1 = (int64_t)H.l1_src.size();
+  o->n_list2 = (int64_t)H.l2_src.size();
+  o->n_list3 = (int64_t)H.l3_src.size();
+  o->n_list4 = (int64_t)H.l4_src.size();
+  o->pinv_doubles = (int64_t)H.pinv_val.size();
+  o->plan_seconds = H.plan_seconds;
+  return VFX_OK;
+}
+
+int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner) {
+  if (!plan || !owner) return fail(VFX_EINVAL, "vfx_plan_ext_owner: null argument");
+  const vfx::HostPlan& H = plan->p.H;
+  for (int i = 0; i < H.L; ++i) owner[i] = H.owner[i];
+  return VFX_OK;
+}
+
+int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out, double* V_out,
+                void* stream) {
+  if (!plan || !f_leaf || !fe_out || !V_out) return fail(VFX_EINVAL, "vfx_execute: null argument");
+  if (plan->p.H.ncut > 0 && !f_cut) return fail(VFX_EINVAL, "vfx_execute: f_cut is null but the tree has cut leaves");
+  try {
+    std::string err;
+    int rc = vfx::launch_execute(&plan->p, f_leaf, f_cut, fe_out, V_out, (hipStream_t)stream, err);
+    if (rc) return fail(rc, "vfx_execute: " + err);
+    return VFX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_execute: out of host memory");
+  }
+}
+
+int vfx_plan_set_timing(vfx_plan* plan, int enable) {
+  if (!plan) return fail(VFX_EINVAL, "vfx_plan_set_timing: null argument");
+  plan->p.timing = enable != 0;
+  return VFX_OK;
+}
+
+int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
+  if (!plan || !ms || n_out < 7) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
+  vfx::Plan& p = plan->p;
+  if (!p.ev_recorded) return fail(VFX_EINVAL, "vfx_plan_timings: no timed execute recorded");
+  hipError_t e = hipEventSynchronize(p.ev[6]);
+  if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
+  for (int k = 0; k < 6; ++k) {
+    float t = 0;
+    e = hipEventElapsedTime(&t, p.ev[k], p.ev[k + 1]);
+    if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
+    ms[k] = t;
+  }
+  float tot = 0;
+  e = hipEventElapsedTime(&tot, p.ev[0], p.ev[6]);
+  if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
+  ms[6] = tot;
+  return VFX_OK;
+}
+
+int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count) {
+  if (!ctx || !out) return fail(VFX_EINVAL, "vfx_debug_table: null argument");
+  const vfx::Tables& T = ctx->c.T;
+  const int64_t n = T.n, P = T.p + 1;
+  const double* src = nullptr;
+  int64_t size = 0;
+  switch (which) {
+    case 0:
+      if (index < 0 || index >= vfx::kNearConfigs) break;
+      src = T.near.data() + (size_t)index * n * n;
+      size = n * n;
+      break;
+    case 1:
+      src = T.A.data();
+      size = (int64_t)T.A.size();
+      break;
+    case 2:
+      src = T.p2m.data();
+      size = (int64_t)T.p2m.size();
+      break;
+    case 3:
+      if (index < 0 || index >= vfx::kP2LSlots) break;
+      src = T.p2l.data() + (size_t)index * P * n * 2;
+      size = P * n * 2;
+      break;
+    case 4:
+      if (index < 0 || index >= vfx::kM2LSlots) break;
+      src = T.m2l.data() + (size_t)index * P * P * 2;
+      size = P * P * 2;
+      break;
+    case 5:
+    case 6:
+      if (index < 0 || index >= 4) break;
+      src = (which == 5 ? T.m2m : T.l2l).data() + (size_t)index * P * P * 2;
+      size = P * P * 2;
+      break;
+    case 7:
+      src = T.l2p.data();
+      size = (int64_t)T.l2p.size();
+      break;
+    case 8:
+      src = T.w2.data();
+      size = (int64_t)T.w2.size();
+      break;
+    default:
+      break;
+  }
+  if (!src || size != count) return fail(VFX_EINVAL, "vfx_debug_table: bad table, index or count");
+  std::memcpy(out, src, sizeof(double) * size);
+  return VFX_OK;
+}
+
+int vfx_plan_lists(const vfx_plan* plan, int which, int32_t* ptr, int32_t* src, int32_t* cfg) {
+  if (!plan || !ptr || !src || !cfg) return fail(VFX_EINVAL, "vfx_plan_lists: null argument");
+  const vfx::HostPlan& H = plan->p.H;
+  const std::vector<int>*P = nullptr, *S = nullptr, *C = nullptr;
+  switch (which) {
+    case 1: P = &H.l1_ptr; S = &H.l1_src; C = &H.l1_cfg; break;
+    case 2: P = &H.l2_ptr; S = &H.l2_src; C = &H.l2_off; break;
+    case 3: P = &H.l3_ptr; S = &H.l3_src; break;
+    case 4: P = &H.l4_ptr; S = &H.l4_src; C = &H.l4_cfg; break;
+    default: return fail(VFX_EINVAL, "vfx_plan_lists: which must be 1..4");
+  }
+  for (size_t i = 0; i < P->size(); ++i) ptr[i] = (*P)[i];
+  for (size_t i = 0; i < S->size(); ++i) {
+    src[i] = (*S)[i];
+    cfg[i] = C ? (*C)[i] : 0;
+  }
+  return VFX_OK;
+}
+
+int vfx_plan_boxes(const vfx_plan* plan, int32_t* level, int32_t* ix, int32_t* iy, int32_t* leaf) {
+  if (!plan || !level || !ix || !iy || !leaf) return fail(VFX_EINVAL, "vfx_plan_boxes: null argument");
+  const vfx::HostPlan& H = plan->p.H;
+  for (int b = 0; b < H.B; ++b) {
+    level[b] = H.box_level[b];
+    ix[b] = H.box_ix[b];
+    iy[b] = H.box_iy[b];
+    leaf[b] = H.box_leaf[b];
+  }
+  return VFX_OK;
+}
+
+}  // extern "C"

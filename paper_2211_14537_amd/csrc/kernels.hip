@@ -1,0 +1,579 @@
+// Device side of the extension + volume FMM path (gfx950, FP64).
+//
+// Execution order on one stream (every output element has one writer, so no
+// atomics are needed and results are bitwise reproducible):
+//   fe_init      f^e = f on regular leaves, 0 elsewhere
+//   extension    per cut leaf: f_G = P_i f_{X^I}; values on the Kbar grid of
+//                Sbar (given data where interior); total-order Chebyshev
+//                expansion; evaluation on every leaf of its extension list
+//                (Sections 3.2 and 4.1)
+//   p2m, m2m     multipole expansions, leaves then upward
+//   m2l          local expansions from list 2 (M2L) and list 4 (P2L)
+//   l2l          locals downward
+//   near         list 1 by the precomputed tables
+//   far          L2P of the local expansion and M2P of list 3
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "vfx_internal.h"
+
+namespace vfx {
+
+#define VFX_HIP(call)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (call);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      err = std::string(#call) + ": " + hipGetErrorString(e_);                 \
+      return VFX_EHIP;                                                         \
+    }                                                                          \
+  } while (0)
+
+constexpr int kMaxX = 648;   // |X| for K, Kbar <= 16, deg <= 15
+constexpr int kMaxG = 136;
+constexpr int kMaxK = 16;
+constexpr int kMaxKb = 16;
+constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double box_side(double root, int level) { return ldexp(root, -level); }
+
+// -------------------------------------------------------------------------
+__global__ void k_fe_init(int n, int L, const int8_t* __restrict__ kind, const double* __restrict__ f_leaf,
+                          double* __restrict__ fe) {
+  const long total = (long)L * n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const int leaf = (int)(e / n);
+    fe[e] = (kind[leaf] == 1) ? f_leaf[e] : 0.0;
+  }
+}
+
+// -------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_extension(
+    int K, int Kb, int nX, int nG, double root_size, const int* __restrict__ cut_leaf,
+    const int* __restrict__ pinv_ptr, const uint16_t* __restrict__ pinv_idx, const double* __restrict__ pinv_val,
+    const uint8_t* __restrict__ sbar_given, const int* __restrict__ ext_ptr, const int* __restrict__ ext_tgt,
+    const double* __restrict__ t, const double* __restrict__ AbarT, const double* __restrict__ cbar,
+    const int* __restrict__ leaf_box, const double* __restrict__ box_cx, const double* __restrict__ box_cy,
+    const int* __restrict__ box_level, const double* __restrict__ f_cut, double* __restrict__ fe) {
+  __shared__ double s_fI[kMaxX];
+  __shared__ double s_fG[kMaxG];
+  __shared__ double s_g[kMaxKb * kMaxKb];
+  __shared__ double s_tmp[kMaxKb * kMaxKb];
+  __shared__ double s_coef[kMaxKb * kMaxKb];
+  __shared__ double s_Ex[kMaxK * kMaxKb];
+  __shared__ double s_Ey[kMaxK * kMaxKb];
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = K * K, Kb2 = Kb * Kb;
+  const int off = pinv_ptr[c], ni = pinv_ptr[c + 1] - off;
+  const double* fc = f_cut + (size_t)c * nX;
+  for (int q = tid; q < ni; q += blockDim.x) s_fI[q] = fc[pinv_idx[off + q]];
+  __syncthreads();
+  // f_G = P_i f_I  (P_i: nG x ni row-major)
+  const double* P = pinv_val + (size_t)off * nG;
+  for (int r = wave; r < nG; r += blockDim.x / 64) {
+    double acc = 0.0;
+    const double* pr = P + (size_t)r * ni;
+    for (int q = lane; q < ni; q += 64) acc += pr[q] * s_fI[q];
+    acc = wave_sum(acc);
+    if (lane == 0) s_fG[r] = acc;
+  }
+  __syncthreads();
+  // values on the Kbar x Kbar grid of Sbar
+  for (int a = tid; a < Kb2; a += blockDim.x) {
+    double v;
+    if (sbar_given[(size_t)c * Kb2 + a]) {
+      v = fc[n + a];
+    } else {
+      v = 0.0;
+      for (int r = 0; r < nG; ++r) v += AbarT[(size_t)r * Kb2 + a] * s_fG[r];
+    }
+    s_g[a] = v;
+  }
+  __syncthreads();
+  // coefficients c = C g C^T, truncated to total order < Kbar
+  for (int e = tid; e < Kb2; e += blockDim.x) {
+    const int m = e / Kb, j = e % Kb;
+    double acc = 0.0;
+    for (int i = 0; i < Kb; ++i) acc += cbar[m * Kb + i] * s_g[i * Kb + j];
+    s_tmp[e] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < Kb2; e += blockDim.x) {
+    const int m = e / Kb, nn = e % Kb;
+    double acc = 0.0;
+    if (m + nn < Kb)
+      for (int j = 0; j < Kb; ++j) acc += s_tmp[m * Kb + j] * cbar[nn * Kb + j];
+    s_coef[e] = acc;
+  }
+  __syncthreads();
+  const int bS = leaf_box[cut_leaf[c]];
+  const double cxS = box_cx[bS], cyS = box_cy[bS];
+  const double hS = box_side(root_size, box_level[bS]);
+  for (int e = ext_ptr[c]; e < ext_ptr[c + 1]; ++e) {
+    const int j = ext_tgt[e];
+    const int bj = leaf_box[j];
+    const double cxj = box_cx[bj], cyj = box_cy[bj];
+    const double hj = box_side(root_size, box_level[bj]);
+    if (tid < 2 * K) {
+      const int a = tid % K;
+      const bool isy = tid >= K;
+      const double X = (isy ? cyj : cxj) + 0.5 * hj * t[a];
+      const double xi = (X - (isy ? cyS : cxS)) / (1.5 * hS);
+      double* dst = (isy ? s_Ey : s_Ex) + a * Kb;
+      double t0 = 1.0, t1 = xi;
+      dst[0] = 1.0;
+      if (Kb > 1) dst[1] = xi;
+      for (int m = 2; m < Kb; ++m) {
+        const double t2 = 2.0 * xi * t1 - t0;
+        dst[m] = t2;
+        t0 = t1;
+        t1 = t2;
+      }
+    }
+    __syncthreads();
+    for (int idx = tid; idx < Kb * K; idx += blockDim.x) {
+      const int m = idx / K, b = idx % K;
+      double acc = 0.0;
+      for (int nn = 0; nn < Kb - m; ++nn) acc += s_coef[m * Kb + nn] * s_Ey[b * Kb + nn];
+      s_tmp[idx] = acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n; idx += blockDim.x) {
+      const int a = idx / K, b = idx % K;
+      double acc = 0.0;
+      for (int m = 0; m < Kb; ++m) acc += s_Ex[a * Kb + m] * s_tmp[m * K + b];
+      fe[(size_t)j * n + idx] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------------------------------------
+// P2M on every leaf: a = h^2 * P2M f  (p2m stored [j][k])
+__global__ void __launch_bounds__(64) k_p2m(int n, int P, double root_size, const int* __restrict__ leaf_box,
+                                            const int* __restrict__ box_level, const double2* __restrict__ p2m,
+                                            const double* __restrict__ fe, double2* __restrict__ mpole) {
+  __shared__ double s_f[kMaxK * kMaxK];
+  const int leaf = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int j = lane; j < n; j += 64) s_f[j] = fe[(size_t)leaf * n + j];
+  __syncthreads();
+  const int b = leaf_box[leaf];
+  const double h = box_side(root_size, box_level[b]);
+  const double h2 = h * h;
+  for (int k = lane; k < P; k += 64) {
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double2 m = p2m[(size_t)j * P + k];
+      re += m.x * s_f[j];
+      im += m.y * s_f[j];
+    }
+    mpole[(size_t)b * P + k] = make_double2(h2 * re, h2 * im);
+  }
+}
+
+// M2M for the non-leaf boxes of one level (m2m stored [q][k][l])
+__global__ void __launch_bounds__(64) k_m2m(int P, int first, const int* __restrict__ box_child0,
+                                            const double2* __restrict__ m2m, double2* __restrict__ mpole) {
+  __shared__ double2 s_a[4 * 64];
+  const int b = first + blockIdx.x;
+  const int c0 = box_child0[b];
+  if (c0 < 0) return;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < 4 * P; e += 64) s_a[e] = mpole[(size_t)c0 * P + e];
+  __syncthreads();
+  if (lane >= P) return;
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < 4; ++q)
+    for (int k = 0; k <= lane; ++k) {
+      const double2 m = m2m[((size_t)q * P + k) * P + lane];
+      const double2 a = s_a[q * P + k];
+      re += m.x * a.x - m.y * a.y;
+      im += m.x * a.y + m.y * a.x;
+    }
+  mpole[(size_t)b * P + lane] = make_double2(re, im);
+}
+
+// Local expansions from list 2 (M2L) and list 4 (P2L) for boxes at level >= 2
+// (m2l stored [o][k][l], p2l stored [c][j][l])
+__global__ void __launch_bounds__(64) k_m2l(int n, int P, int first, double root_size,
+                                            const int* __restrict__ box_level, const int* __restrict__ l2_ptr,
+                                            const int* __restrict__ l2_src, const int* __restrict__ l2_off,
+                                            const int* __restrict__ l4_ptr, const int* __restrict__ l4_src,
+                                            const int* __restrict__ l4_cfg, const double2* __restrict__ m2l,
+                                            const double2* __restrict__ p2l, const double* __restrict__ w2,
+                                            const double* __restrict__ p2l_area, const double2* __restrict__ mpole,
+                                            const double* __restrict__ fe, double2* __restrict__ local) {
+  __shared__ double2 s_a[64];
+  __shared__ double s_f[kMaxK * kMaxK];
+  const int b = first + blockIdx.x;
+  const int lane = threadIdx.x;
+  const double h = box_side(root_size, box_level[b]);
+  const double logh = log(h);
+  double re = 0.0, im = 0.0;
+  for (int e = l2_ptr[b]; e < l2_ptr[b + 1]; ++e) {
+    const int s = l2_src[e];
+    const double2* M = m2l + (size_t)l2_off[e] * P * P;
+    __syncthreads();
+    if (lane < P) s_a[lane] = mpole[(size_t)s * P + lane];
+    __syncthreads();
+    if (lane < P) {
+      for (int k = 0; k < P; ++k) {
+        const double2 m = M[(size_t)k * P + lane];
+        const double2 a = s_a[k];
+        re += m.x * a.x - m.y * a.y;
+        im += m.x * a.y + m.y * a.x;
+      }
+      if (lane == 0) re += s_a[0].x * logh;
+    }
+  }
+  const double h2 = h * h;
+  for (int e = l4_ptr[b]; e < l4_ptr[b + 1]; ++e) {
+    const int src = l4_src[e];
+    const int cfg = l4_cfg[e];
+    __syncthreads();
+    for (int j = lane; j < n; j += 64) s_f[j] = fe[(size_t)src * n + j];
+    __syncthreads();
+    if (lane < P) {
+      double r2 = 0.0, i2 = 0.0;
+      const double2* Q = p2l + (size_t)cfg * n * P;
+      for (int j = 0; j < n; ++j) {
+        const double2 q = Q[(size_t)j * P + lane];
+        r2 += q.x * s_f[j];
+        i2 += q.y * s_f[j];
+      }
+      re += h2 * r2;
+      im += h2 * i2;
+      if (lane == 0) {
+        double ch = 0.0;
+        for (int j = 0; j < n; ++j) ch += w2[j] * s_f[j];
+        re += h2 * logh * p2l_area[cfg] * ch;
+      }
+    }
+  }
+  if (lane < P) local[(size_t)b * P + lane] = make_double2(re, im);
+}
+
+// L2L into the boxes of one level (l2l stored [q][k][l])
+__global__ void __launch_bounds__(64) k_l2l(int P, int first, const int* __restrict__ box_parent,
+                                            const int* __restrict__ box_child0, const double2* __restrict__ l2l,
+                                            double2* __restrict__ local) {
+  __shared__ double2 s_b[64];
+  const int b = first + blockIdx.x;
+  const int lane = threadIdx.x;
+  const int par = box_parent[b];
+  const int q = b - box_child0[par];
+  if (lane < P) s_b[lane] = local[(size_t)par * P + lane];
+  __syncthreads();
+  if (lane >= P) return;
+  double re = 0.0, im = 0.0;
+  for (int k = lane; k < P; ++k) {
+    const double2 m = l2l[((size_t)q * P + k) * P + lane];
+    const double2 a = s_b[k];
+    re += m.x * a.x - m.y * a.y;
+    im += m.x * a.y + m.y * a.x;
+  }
+  double2 o = local[(size_t)b * P + lane];
+  o.x += re;
+  o.y += im;
+  local[(size_t)b * P + lane] = o;
+}
+
+// -------------------------------------------------------------------------
+// Near field: V_i = (1/2pi) sum_{S in list 1} [ h^2 (T_c f_S)_i + log(h) a_0(S) ]
+__global__ void __launch_bounds__(256) k_near(int n, int P, double root_size, const int* __restrict__ leaf_box,
+                                              const int* __restrict__ box_level, const int* __restrict__ l1_ptr,
+                                              const int* __restrict__ l1_src, const int* __restrict__ l1_cfg,
+                                              const double* __restrict__ near, const double2* __restrict__ mpole,
+                                              const double* __restrict__ fe, double* __restrict__ V) {
+  __shared__ double s_f[kMaxK * kMaxK];
+  const int leaf = blockIdx.x;
+  const int i = threadIdx.x;
+  const int b = leaf_box[leaf];
+  const double h = box_side(root_size, box_level[b]);
+  const double logh = log(h);
+  double acc = 0.0, lg = 0.0;
+  for (int e = l1_ptr[leaf]; e < l1_ptr[leaf + 1]; ++e) {
+    const int s = l1_src[e];
+    const int c = l1_cfg[e];
+    __syncthreads();
+    if (i < n) s_f[i] = fe[(size_t)s * n + i];
+    __syncthreads();
+    if (i < n) {
+      const double* T = near + (size_t)c * n * n;
+      double a = 0.0;
+      for (int j = 0; j < n; ++j) a += T[(size_t)j * n + i] * s_f[j];
+      acc += a;
+      lg += mpole[(size_t)leaf_box[s] * P].x;
+    }
+  }
+  if (i < n) V[(size_t)leaf * n + i] = kInv2Pi * (h * h * acc + logh * lg);
+}
+
+// Far field: L2P of the local expansion and M2P of list 3 (l2p stored [l][i])
+__global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, const int* __restrict__ leaf_box,
+                                             const int* __restrict__ box_level, const double* __restrict__ box_cx,
+                                             const double* __restrict__ box_cy, const double* __restrict__ t,
+                                             const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
+                                             const double2* __restrict__ l2p, const double2* __restrict__ local,
+                                             const double2* __restrict__ mpole, double* __restrict__ V) {
+  __shared__ double2 s_a[64];
+  const int n = K * K;
+  const int leaf = blockIdx.x;
+  const int i = threadIdx.x;
+  const int b = leaf_box[leaf];
+  const int lev = box_level[b];
+  const double h = box_side(root_size, lev);
+  double acc = 0.0;
+  if (lev >= 2) {
+    if (i < P) s_a[i] = local[(size_t)b * P + i];
+    __syncthreads();
+    if (i < n)
+      for (int l = 0; l < P; ++l) {
+        const double2 z = l2p[(size_t)l * n + i];
+        acc += z.x * s_a[l].x - z.y * s_a[l].y;
+      }
+  }
+  const double xi = box_cx[b] + 0.5 * h * t[(i < n ? i : 0) / K];
+  const double yi = box_cy[b] + 0.5 * h * t[(i < n ? i : 0) % K];
+  for (int e = l3_ptr[leaf]; e < l3_ptr[leaf + 1]; ++e) {
+    const int w = l3_src[e];
+    __syncthreads();
+    if (i < P) s_a[i] = mpole[(size_t)w * P + i];
+    __syncthreads();
+    if (i < n) {
+      const double hw = box_side(root_size, box_level[w]);
+      const double zx = xi - box_cx[w], zy = yi - box_cy[w];
+      const double r2 = zx * zx + zy * zy;
+      // zeta = hw / z
+      const double zr = hw * zx / r2, zi = -hw * zy / r2;
+      double sr = 0.0, si = 0.0;  // Horner: sum_{k>=1} a_k zeta^k
+      for (int k = P - 1; k >= 1; --k) {
+        const double ar = sr + s_a[k].x, ai = si + s_a[k].y;
+        sr = ar * zr - ai * zi;
+        si = ar * zi + ai * zr;
+      }
+      acc += s_a[0].x * 0.5 * log(r2) + sr;
+    }
+  }
+  if (i < n) V[(size_t)leaf * n + i] += kInv2Pi * acc;
+}
+
+// -------------------------------------------------------------------------
+template <typename T>
+static int upload(T** dst, const T* src, size_t count, std::string& err) {
+  *dst = nullptr;
+  if (count == 0) return VFX_OK;
+  VFX_HIP(hipMalloc((void**)dst, count * sizeof(T)));
+  VFX_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return VFX_OK;
+}
+
+#define UP(dst, vec)                                                       \
+  do {                                                                     \
+    int rc_ = upload(&(dst), (vec).data(), (vec).size(), err);             \
+    if (rc_) return rc_;                                                   \
+  } while (0)
+
+int upload_tables(Context* c, std::string& err) {
+  const Tables& T = c->T;
+  DeviceTables& D = c->D;
+  const int n = T.n, P = T.p + 1;
+  UP(D.t, T.t);
+  UP(D.tbar, T.tbar);
+  UP(D.w2, T.w2);
+  UP(D.AbarT, T.AbarT);
+  UP(D.cbar, T.cbar);
+  UP(D.near, T.near);
+  UP(D.near_s2, T.near_s2);
+  UP(D.p2l_area, T.p2l_area);
+  std::vector<double2> v;
+  // p2m [k][j] -> [j][k]
+  v.assign((size_t)n * P, make_double2(0, 0));
+  for (int k = 0; k < P; ++k)
+    for (int j = 0; j < n; ++j)
+      v[(size_t)j * P + k] = make_double2(T.p2m[2 * ((size_t)k * n + j)], T.p2m[2 * ((size_t)k * n + j) + 1]);
+  UP(D.p2m, v);
+  // l2p [i][l] -> [l][i]
+  v.assign((size_t)n * P, make_double2(0, 0));
+  for (int i = 0; i < n; ++i)
+    for (int l = 0; l < P; ++l)
+      v[(size_t)l * n + i] = make_double2(T.l2p[2 * ((size_t)i * P + l)], T.l2p[2 * ((size_t)i * P + l) + 1]);
+  UP(D.l2p, v);
+  auto cplx_copy = [&](const std::vector<double>& src) {
+    std::vector<double2> o(src.size() / 2);
+    for (size_t i = 0; i < o.size(); ++i) o[i] = make_double2(src[2 * i], src[2 * i + 1]);
+    return o;
+  };
+  v = cplx_copy(T.m2m);
+  UP(D.m2m, v);
+  v = cplx_copy(T.l2l);
+  UP(D.l2l, v);
+  v = cplx_copy(T.m2l);
+  UP(D.m2l, v);
+  // p2l [c][l][j] -> [c][j][l]
+  v.assign((size_t)kP2LSlots * n * P, make_double2(0, 0));
+  for (int s = 0; s < kP2LSlots; ++s)
+    for (int l = 0; l < P; ++l)
+      for (int j = 0; j < n; ++j) {
+        const size_t src = 2 * (((size_t)s * P + l) * n + j);
+        v[((size_t)s * n + j) * P + l] = make_double2(T.p2l[src], T.p2l[src + 1]);
+      }
+  UP(D.p2l, v);
+  VFX_HIP(hipGetDevice(&D.device));
+  D.ready = true;
+  return VFX_OK;
+}
+
+void free_tables_device(Context* c) {
+  DeviceTables& D = c->D;
+  void* ptrs[] = {D.t, D.tbar, D.w2, D.AbarT, D.cbar, D.near, D.near_s2, D.p2m, D.l2p, D.m2m, D.l2l, D.m2l, D.p2l,
+                  D.p2l_area};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  D = DeviceTables();
+}
+
+int upload_plan(Plan* p, std::string& err) {
+  const HostPlan& H = p->H;
+  DevicePlan& D = p->D;
+  const int P = p->ctx->T.p + 1;
+  UP(D.box_level, H.box_level);
+  UP(D.box_child0, H.box_child0);
+  UP(D.box_leaf, H.box_leaf);
+  UP(D.box_parent, H.box_parent);
+  UP(D.box_cx, H.box_cx);
+  UP(D.box_cy, H.box_cy);
+  UP(D.leaf_box, H.leaf_box);
+  UP(D.kind, H.kind);
+  UP(D.l1_ptr, H.l1_ptr);
+  UP(D.l1_src, H.l1_src);
+  UP(D.l1_cfg, H.l1_cfg);
+  UP(D.l2_ptr, H.l2_ptr);
+  UP(D.l2_src, H.l2_src);
+  UP(D.l2_off, H.l2_off);
+  UP(D.l3_ptr, H.l3_ptr);
+  UP(D.l3_src, H.l3_src);
+  UP(D.l4_ptr, H.l4_ptr);
+  UP(D.l4_src, H.l4_src);
+  UP(D.l4_cfg, H.l4_cfg);
+  UP(D.cut_leaf, H.cut_leaf);
+  UP(D.ext_ptr, H.ext_ptr);
+  UP(D.ext_tgt, H.ext_tgt);
+  UP(D.pinv_ptr, H.pinv_ptr);
+  UP(D.pinv_idx, H.pinv_idx);
+  UP(D.pinv_val, H.pinv_val);
+  UP(D.sbar_given, H.sbar_given);
+  VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P));
+  VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P));
+  VFX_HIP(hipMemset(D.local, 0, sizeof(double2) * (size_t)H.B * P));
+  D.ready = true;
+  return VFX_OK;
+}
+
+void free_plan_device(Plan* p) {
+  DevicePlan& D = p->D;
+  void* ptrs[] = {D.box_level, D.box_child0, D.box_leaf, D.box_parent, D.box_cx, D.box_cy, D.leaf_box, D.kind,
+                  D.l1_ptr, D.l1_src, D.l1_cfg, D.l2_ptr, D.l2_src, D.l2_off, D.l3_ptr, D.l3_src,
+                  D.l4_ptr, D.l4_src, D.l4_cfg, D.cut_leaf, D.ext_ptr, D.ext_tgt, D.pinv_ptr, D.pinv_idx,
+                  D.pinv_val, D.sbar_given, D.mpole, D.local};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  D = DevicePlan();
+  for (auto& e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : p->ev) e = nullptr;
+  p->ev_ready = false;
+}
+
+int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V, hipStream_t s,
+                   std::string& err) {
+  Context* c = p->ctx;
+  const Tables& T = c->T;
+  if (!c->D.ready) {
+    int rc = upload_tables(c, err);
+    if (rc) return rc;
+  }
+  if (!p->D.ready) {
+    int rc = upload_plan(p, err);
+    if (rc) return rc;
+  }
+  const HostPlan& H = p->H;
+  const DeviceTables& DT = c->D;
+  const DevicePlan& D = p->D;
+  const int n = T.n, P = T.p + 1, L = H.L;
+  if (p->timing && !p->ev_ready) {
+    for (auto& e : p->ev) VFX_HIP(hipEventCreate(&e));
+    p->ev_ready = true;
+  }
+  auto mark = [&](int k) -> int {
+    if (p->timing) {
+      hipError_t e = hipEventRecord(p->ev[k], s);
+      if (e != hipSuccess) {
+        err = std::string("hipEventRecord: ") + hipGetErrorString(e);
+        return VFX_EHIP;
+      }
+    }
+    return VFX_OK;
+  };
+#define MARK(k)             \
+  do {                      \
+    int rc_ = mark(k);      \
+    if (rc_) return rc_;    \
+  } while (0)
+  MARK(0);
+  {
+    const long total = (long)L * n;
+    int blocks = (int)std::min<long>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fe_init, dim3(blocks), dim3(256), 0, s, n, L, D.kind, f_leaf, fe);
+  }
+  if (H.ncut > 0)
+    hipLaunchKernelGGL(k_extension, dim3(H.ncut), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, T.root_size,
+                       D.cut_leaf, D.pinv_ptr, D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt,
+                       DT.t, DT.AbarT, DT.cbar, D.leaf_box, D.box_cx, D.box_cy, D.box_level, f_cut, fe);
+  VFX_HIP(hipGetLastError());
+  MARK(1);
+  hipLaunchKernelGGL(k_p2m, dim3(L), dim3(64), 0, s, n, P, T.root_size, D.leaf_box, D.box_level, DT.p2m, fe,
+                     D.mpole);
+  for (int l = H.nlev - 2; l >= 2; --l) {
+    const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
+    if (cnt > 0) hipLaunchKernelGGL(k_m2m, dim3(cnt), dim3(64), 0, s, P, first, D.box_child0, DT.m2m, D.mpole);
+  }
+  VFX_HIP(hipGetLastError());
+  MARK(2);
+  if (H.nlev > 2) {
+    const int first = H.level_start[2], cnt = H.B - first;
+    hipLaunchKernelGGL(k_m2l, dim3(cnt), dim3(64), 0, s, n, P, first, T.root_size, D.box_level, D.l2_ptr,
+                       D.l2_src, D.l2_off, D.l4_ptr, D.l4_src, D.l4_cfg, DT.m2l, DT.p2l, DT.w2, DT.p2l_area,
+                       D.mpole, fe, D.local);
+  }
+  VFX_HIP(hipGetLastError());
+  MARK(3);
+  for (int l = 3; l < H.nlev; ++l) {
+    const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
+    if (cnt > 0)
+      hipLaunchKernelGGL(k_l2l, dim3(cnt), dim3(64), 0, s, P, first, D.box_parent, D.box_child0, DT.l2l, D.local);
+  }
+  VFX_HIP(hipGetLastError());
+  MARK(4);
+  hipLaunchKernelGGL(k_near, dim3(L), dim3(n < 64 ? 64 : n), 0, s, n, P, T.root_size, D.leaf_box, D.box_level,
+                     D.l1_ptr, D.l1_src, D.l1_cfg, DT.near, D.mpole, fe, V);
+  VFX_HIP(hipGetLastError());
+  MARK(5);
+  hipLaunchKernelGGL(k_far, dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box, D.box_level,
+                     D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.l2p, D.local, D.mpole, V);
+  VFX_HIP(hipGetLastError());
+  MARK(6);
+  p->ev_recorded = p->timing;
+  return VFX_OK;
+}
+
+}  // namespace vfx

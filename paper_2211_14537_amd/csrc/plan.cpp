@@ -1,0 +1,381 @@
+// Host side of a plan: the box hierarchy over the caller's leaves, the VFMM
+// interaction lists, the extension lists and the per-cut-leaf operators.
+//
+// Section 4 (data structures): a level-restricted quad-tree; colleagues,
+// coarse and fine neighbours; the lists of the adaptive VFMM shown in the
+// tree-levels figure: n/n+/n- (list 1, near field by tables), i (list 2,
+// M2L), i- (list 3: children of colleagues that do not touch a leaf,
+// multipole evaluated at its targets) and i+ (list 4: a coarse leaf that is a
+// colleague of the parent but does not touch the box, turned into a local
+// expansion).  Extension lists: for a cut square S, the exterior leaves that
+// Sbar overlaps and whose closest cut-square centre is that of S, the later
+// cut square taking precedence on ties; the extension restriction forbids a
+// coarser leaf in such a list.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <unordered_map>
+
+#include "vfx_internal.h"
+
+namespace vfx {
+
+namespace {
+
+inline uint64_t key(int l, int x, int y) {
+  return ((uint64_t)l << 58) | ((uint64_t)(uint32_t)x << 29) | (uint64_t)(uint32_t)y;
+}
+
+inline uint64_t morton(uint32_t x, uint32_t y) {
+  uint64_t r = 0;
+  for (int b = 0; b < 30; ++b) {
+    r |= (uint64_t)((x >> b) & 1u) << (2 * b);
+    r |= (uint64_t)((y >> b) & 1u) << (2 * b + 1);
+  }
+  return r;
+}
+
+struct Node {
+  int l, x, y, leaf;
+};
+
+// closed boxes (la,ax,ay) and (lb,bx,by) touch or overlap
+inline bool touch(int la, int ax, int ay, int lb, int bx, int by) {
+  const int L = std::max(la, lb);
+  const int64_t sa = 1LL << (L - la), sb = 1LL << (L - lb);
+  const int64_t ax0 = ax * sa, ax1 = ax0 + sa, ay0 = ay * sa, ay1 = ay0 + sa;
+  const int64_t bx0 = bx * sb, bx1 = bx0 + sb, by0 = by * sb, by1 = by0 + sb;
+  return ax0 <= bx1 && bx0 <= ax1 && ay0 <= by1 && by0 <= ay1;
+}
+
+}  // namespace
+
+int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int L = tree->n_leaves;
+  if (L <= 0 || !tree->level || !tree->ix || !tree->iy || !tree->kind) {
+    err = "tree: empty or null arrays";
+    return VFX_EINVAL;
+  }
+  H = HostPlan();
+  H.L = L;
+  std::unordered_map<uint64_t, int> idx;  // key -> node id (before sorting)
+  std::vector<Node> nodes;
+  nodes.reserve(2 * L);
+  int lmax = 0;
+  for (int i = 0; i < L; ++i) {
+    const int l = tree->level[i], x = tree->ix[i], y = tree->iy[i];
+    if (l < 0 || l > 28 || x < 0 || y < 0 || x >= (1 << l) || y >= (1 << l)) {
+      err = "tree: leaf " + std::to_string(i) + " has level/position out of range";
+      return VFX_EINVAL;
+    }
+    const int k = tree->kind[i];
+    if (k < 0 || k > 2) {
+      err = "tree: leaf " + std::to_string(i) + " has an invalid kind";
+      return VFX_EINVAL;
+    }
+    if (!idx.emplace(key(l, x, y), (int)nodes.size()).second) {
+      err = "tree: duplicate leaf " + std::to_string(i);
+      return VFX_ETREE;
+    }
+    nodes.push_back({l, x, y, i});
+    lmax = std::max(lmax, l);
+  }
+  // ancestors
+  for (int i = 0; i < L; ++i) {
+    int l = tree->level[i], x = tree->ix[i], y = tree->iy[i];
+    while (l > 0) {
+      --l;
+      x >>= 1;
+      y >>= 1;
+      auto it = idx.find(key(l, x, y));
+      if (it != idx.end()) {
+        if (nodes[it->second].leaf >= 0) {
+          err = "tree: leaf " + std::to_string(nodes[it->second].leaf) + " contains another leaf";
+          return VFX_ETREE;
+        }
+        break;  // this ancestor and all above already present
+      }
+      idx.emplace(key(l, x, y), (int)nodes.size());
+      nodes.push_back({l, x, y, -1});
+    }
+  }
+  // every internal node has its four children
+  for (const Node& nd : nodes) {
+    if (nd.leaf >= 0) continue;
+    for (int c = 0; c < 4; ++c)
+      if (!idx.count(key(nd.l + 1, 2 * nd.x + c / 2, 2 * nd.y + c % 2))) {
+        err = "tree: leaves do not tile the root box (box at level " + std::to_string(nd.l) +
+              " misses a child)";
+        return VFX_ETREE;
+      }
+  }
+  if (!idx.count(key(0, 0, 0))) {
+    err = "tree: no root";
+    return VFX_ETREE;
+  }
+  // order: level-major, Morton within a level
+  std::vector<int> order(nodes.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    if (nodes[a].l != nodes[b].l) return nodes[a].l < nodes[b].l;
+    return morton(nodes[a].x, nodes[a].y) < morton(nodes[b].x, nodes[b].y);
+  });
+  const int B = (int)nodes.size();
+  H.B = B;
+  H.nlev = lmax + 1;
+  std::vector<int> newid(B);
+  for (int i = 0; i < B; ++i) newid[order[i]] = i;
+  for (auto& kv : idx) kv.second = newid[kv.second];
+  H.box_level.resize(B);
+  H.box_ix.resize(B);
+  H.box_iy.resize(B);
+  H.box_leaf.resize(B);
+  H.box_parent.assign(B, -1);
+  H.box_child0.assign(B, -1);
+  H.box_cx.resize(B);
+  H.box_cy.resize(B);
+  H.level_start.assign(H.nlev + 1, 0);
+  H.leaf_box.assign(L, -1);
+  for (int i = 0; i < B; ++i) {
+    const Node& nd = nodes[order[i]];
+    H.box_level[i] = nd.l;
+    H.box_ix[i] = nd.x;
+    H.box_iy[i] = nd.y;
+    H.box_leaf[i] = nd.leaf;
+    const double h = std::ldexp(T.root_size, -nd.l);
+    H.box_cx[i] = T.root_cx - 0.5 * T.root_size + (nd.x + 0.5) * h;
+    H.box_cy[i] = T.root_cy - 0.5 * T.root_size + (nd.y + 0.5) * h;
+    H.level_start[nd.l + 1]++;
+    if (nd.leaf >= 0) H.leaf_box[nd.leaf] = i;
+  }
+  for (int l = 0; l < H.nlev; ++l) H.level_start[l + 1] += H.level_start[l];
+  auto find = [&](int l, int x, int y) -> int {
+    if (l < 0 || x < 0 || y < 0 || x >= (1 << l) || y >= (1 << l)) return -1;
+    auto it = idx.find(key(l, x, y));
+    return it == idx.end() ? -1 : it->second;
+  };
+  for (int i = 0; i < B; ++i) {
+    const int l = H.box_level[i];
+    if (l > 0) H.box_parent[i] = find(l - 1, H.box_ix[i] >> 1, H.box_iy[i] >> 1);
+    if (H.box_leaf[i] < 0) H.box_child0[i] = find(l + 1, 2 * H.box_ix[i], 2 * H.box_iy[i]);
+  }
+  // children of a box are contiguous in the Morton order of the next level
+  for (int i = 0; i < B; ++i)
+    if (H.box_child0[i] >= 0)
+      for (int c = 0; c < 4; ++c) {
+        const int ch = H.box_child0[i] + c;
+        if (ch >= B || H.box_parent[ch] != i) {
+          err = "internal: children not contiguous";
+          return VFX_EINVAL;
+        }
+      }
+  H.kind.assign(tree->kind, tree->kind + L);
+
+  // ---- lists 1 and 3 (per leaf), balance check -------------------------
+  H.l1_ptr.assign(L + 1, 0);
+  H.l3_ptr.assign(L + 1, 0);
+  std::vector<std::vector<std::pair<int, int>>> l1(L);
+  std::vector<std::vector<int>> l3(L);
+  for (int leaf = 0; leaf < L; ++leaf) {
+    const int b = H.leaf_box[leaf];
+    const int l = H.box_level[b], x = H.box_ix[b], y = H.box_iy[b];
+    std::vector<int> coarse_seen;
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int cx = x + dx, cy = y + dy;
+        if (cx < 0 || cy < 0 || cx >= (1 << l) || cy >= (1 << l)) continue;
+        const int c = find(l, cx, cy);
+        if (c >= 0) {
+          if (H.box_leaf[c] >= 0) {
+            l1[leaf].push_back({H.box_leaf[c], (dx + 1) * 3 + (dy + 1)});
+          } else {
+            for (int q = 0; q < 4; ++q) {
+              const int ch = H.box_child0[c] + q;
+              const int kx = H.box_ix[ch], ky = H.box_iy[ch];
+              if (touch(l, x, y, l + 1, kx, ky)) {
+                if (H.box_leaf[ch] < 0) {
+                  err = "tree: not level-restricted (leaf " + std::to_string(leaf) +
+                        " touches a box two levels finer)";
+                  return VFX_ETREE;
+                }
+                const int ox4 = (2 * kx + 1) - 2 * (2 * x + 1), oy4 = (2 * ky + 1) - 2 * (2 * y + 1);
+                l1[leaf].push_back({H.box_leaf[ch], 21 + near_config_fine_index(ox4, oy4)});
+              } else {
+                l3[leaf].push_back(ch);
+              }
+            }
+          }
+        } else {
+          const int p = find(l - 1, cx >> 1, cy >> 1);
+          if (p < 0 || H.box_leaf[p] < 0) {
+            err = "tree: not level-restricted (leaf " + std::to_string(leaf) +
+                  " touches a leaf two levels coarser)";
+            return VFX_ETREE;
+          }
+          if (std::find(coarse_seen.begin(), coarse_seen.end(), p) != coarse_seen.end()) continue;
+          coarse_seen.push_back(p);
+          const int ox2 = (4 * H.box_ix[p] + 2) - (2 * x + 1), oy2 = (4 * H.box_iy[p] + 2) - (2 * y + 1);
+          const int ci = near_config_coarse_index(ox2, oy2);
+          if (ci < 0) {
+            err = "internal: bad coarse configuration";
+            return VFX_EINVAL;
+          }
+          l1[leaf].push_back({H.box_leaf[p], 9 + ci});
+        }
+      }
+  }
+  for (int leaf = 0; leaf < L; ++leaf) {
+    H.l1_ptr[leaf + 1] = H.l1_ptr[leaf] + (int)l1[leaf].size();
+    for (auto& pr : l1[leaf]) {
+      H.l1_src.push_back(pr.first);
+      H.l1_cfg.push_back(pr.second);
+    }
+    H.l3_ptr[leaf + 1] = H.l3_ptr[leaf] + (int)l3[leaf].size();
+    for (int s : l3[leaf]) H.l3_src.push_back(s);
+  }
+  // ---- lists 2 and 4 (per box, level >= 2) ------------------------------
+  H.l2_ptr.assign(B + 1, 0);
+  H.l4_ptr.assign(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    const int l = H.box_level[b];
+    int n2 = 0, n4 = 0;
+    if (l >= 2) {
+      const int x = H.box_ix[b], y = H.box_iy[b];
+      const int px = x >> 1, py = y >> 1;
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy) {
+          const int c = find(l - 1, px + dx, py + dy);
+          if (c < 0) continue;
+          if (H.box_leaf[c] < 0) {
+            for (int q = 0; q < 4; ++q) {
+              const int ch = H.box_child0[c] + q;
+              const int kx = H.box_ix[ch], ky = H.box_iy[ch];
+              if (touch(l, x, y, l, kx, ky)) continue;
+              H.l2_src.push_back(ch);
+              H.l2_off.push_back((kx - x + 3) * 7 + (ky - y + 3));
+              ++n2;
+            }
+          } else if (!touch(l, x, y, l - 1, px + dx, py + dy)) {
+            const int ox2 = (4 * (px + dx) + 2) - (2 * x + 1), oy2 = (4 * (py + dy) + 2) - (2 * y + 1);
+            H.l4_src.push_back(H.box_leaf[c]);
+            H.l4_cfg.push_back(((ox2 + 5) / 2) * 6 + (oy2 + 5) / 2);
+            ++n4;
+          }
+        }
+    }
+    H.l2_ptr[b + 1] = H.l2_ptr[b] + n2;
+    H.l4_ptr[b + 1] = H.l4_ptr[b] + n4;
+  }
+
+  // ---- extension lists ---------------------------------------------------
+  H.owner.assign(L, -1);
+  std::vector<int64_t> best(L, -1);
+  const int sh = lmax;  // centres in units of root/2^(lmax+1): (2x+1) << (lmax-l)
+  auto cen = [&](int b, int64_t* cx, int64_t* cy) {
+    *cx = (int64_t)(2 * H.box_ix[b] + 1) << (sh - H.box_level[b]);
+    *cy = (int64_t)(2 * H.box_iy[b] + 1) << (sh - H.box_level[b]);
+  };
+  std::vector<int> stack, cand;
+  for (int leaf = 0; leaf < L; ++leaf) {
+    if (H.kind[leaf] != 2) continue;
+    H.cut_leaf.push_back(leaf);
+    H.owner[leaf] = leaf;
+    const int b = H.leaf_box[leaf];
+    const int l = H.box_level[b], x = H.box_ix[b], y = H.box_iy[b];
+    int64_t scx, scy;
+    cen(b, &scx, &scy);
+    cand.clear();
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (dx == 0 && dy == 0) continue;
+        const int cx = x + dx, cy = y + dy;
+        if (cx < 0 || cy < 0 || cx >= (1 << l) || cy >= (1 << l)) continue;
+        const int c = find(l, cx, cy);
+        if (c >= 0) {
+          stack.assign(1, c);
+          while (!stack.empty()) {
+            const int u = stack.back();
+            stack.pop_back();
+            if (H.box_leaf[u] >= 0)
+              cand.push_back(H.box_leaf[u]);
+            else
+              for (int q = 0; q < 4; ++q) stack.push_back(H.box_child0[u] + q);
+          }
+        } else {
+          const int p = find(l - 1, cx >> 1, cy >> 1);
+          if (p >= 0 && H.box_leaf[p] >= 0) cand.push_back(H.box_leaf[p]);
+        }
+      }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int j : cand) {
+      if (H.kind[j] != 0) continue;
+      int64_t jx, jy;
+      cen(H.leaf_box[j], &jx, &jy);
+      const int64_t d2 = (jx - scx) * (jx - scx) + (jy - scy) * (jy - scy);
+      if (best[j] < 0 || d2 <= best[j]) {
+        best[j] = d2;
+        H.owner[j] = leaf;
+      }
+    }
+  }
+  H.ncut = (int)H.cut_leaf.size();
+  std::vector<int> cutpos(L, -1);
+  for (int c = 0; c < H.ncut; ++c) cutpos[H.cut_leaf[c]] = c;
+  std::vector<std::vector<int>> tg(H.ncut);
+  for (int c = 0; c < H.ncut; ++c) tg[c].push_back(H.cut_leaf[c]);
+  for (int j = 0; j < L; ++j) {
+    if (H.kind[j] != 0 || H.owner[j] < 0) continue;
+    const int s = H.owner[j];
+    if (H.box_level[H.leaf_box[s]] > H.box_level[H.leaf_box[j]]) {
+      err = "tree: extension restriction violated (cut leaf " + std::to_string(s) +
+            " would extend onto the coarser leaf " + std::to_string(j) + ")";
+      return VFX_ETREE;
+    }
+    tg[cutpos[s]].push_back(j);
+  }
+  H.ext_ptr.assign(H.ncut + 1, 0);
+  for (int c = 0; c < H.ncut; ++c) {
+    H.ext_ptr[c + 1] = H.ext_ptr[c] + (int)tg[c].size();
+    H.ext_tgt.insert(H.ext_tgt.end(), tg[c].begin(), tg[c].end());
+  }
+
+  // ---- per-cut-leaf pseudo-inverses --------------------------------------
+  const int nX = T.nX, nG = T.nG, Kb2 = T.Kbar * T.Kbar;
+  if (H.ncut > 0 && !tree->cut_mask) {
+    err = "tree: cut leaves present but no cut_mask";
+    return VFX_EINVAL;
+  }
+  H.pinv_ptr.assign(H.ncut + 1, 0);
+  H.sbar_given.assign((size_t)H.ncut * Kb2, 0);
+  for (int c = 0; c < H.ncut; ++c) {
+    const uint8_t* m = tree->cut_mask + (size_t)c * nX;
+    int ni = 0;
+    for (int k = 0; k < nX; ++k) ni += m[k] ? 1 : 0;
+    H.pinv_ptr[c + 1] = H.pinv_ptr[c] + ni;
+    for (int a = 0; a < Kb2; ++a) H.sbar_given[(size_t)c * Kb2 + a] = m[T.n + a] ? 1 : 0;
+  }
+  H.pinv_idx.resize(H.pinv_ptr[H.ncut]);
+  H.pinv_val.assign((size_t)H.pinv_ptr[H.ncut] * nG, 0.0);
+  for (int c = 0; c < H.ncut; ++c) {
+    const uint8_t* m = tree->cut_mask + (size_t)c * nX;
+    int q = H.pinv_ptr[c];
+    for (int k = 0; k < nX; ++k)
+      if (m[k]) H.pinv_idx[q++] = (uint16_t)k;
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int c = 0; c < H.ncut; ++c) {
+    const int off = H.pinv_ptr[c], ni = H.pinv_ptr[c + 1] - off;
+    if (ni == 0) continue;
+    std::vector<double> AI((size_t)ni * nG);
+    for (int r = 0; r < ni; ++r)
+      std::memcpy(&AI[(size_t)r * nG], &T.A[(size_t)H.pinv_idx[off + r] * nG], sizeof(double) * nG);
+    // P (nG x ni) stored row-major at pinv_val + off*nG
+    pinv_jacobi(AI.data(), ni, nG, 1e-13, &H.pinv_val[(size_t)off * nG]);
+  }
+  H.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return VFX_OK;
+}
+
+}  // namespace vfx

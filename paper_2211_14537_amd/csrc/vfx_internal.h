@@ -1,0 +1,139 @@
+// Internal declarations of the vfx library (host precompute, plan, kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vfx.h"
+
+namespace vfx {
+
+// Table indexing ------------------------------------------------------------
+// Near field (list 1) configurations of a source leaf relative to a target
+// leaf of side h (33 in a level-restricted tree):
+//   0..8    same level, offset (dx, dy) in [-1,1]^2 -> (dx+1)*3 + (dy+1)
+//   9..20   one level coarser, centre offset (ox, oy) in units h/2, odd
+//           values in {-3,-1,1,3} with max(|ox|,|oy|) = 3
+//   21..32  one level finer, centre offset in units h/4, same value set
+constexpr int kNearConfigs = 33;
+// M2L (list 2): centre offset (dx, dy) in units h, |dx|,|dy| <= 3, index
+// (dx+3)*7 + (dy+3); only max(|dx|,|dy|) >= 2 occurs.
+constexpr int kM2LSlots = 49;
+// P2L (list 4): a leaf one level coarser than the target box, centre offset
+// in units h/2, odd values in {-5..5} with max(|ox|,|oy|) = 5; index
+// ((ox+5)/2)*6 + (oy+5)/2.
+constexpr int kP2LSlots = 36;
+
+int near_config_coarse_index(int ox2, int oy2);  // -1 if invalid
+int near_config_fine_index(int ox4, int oy4);
+void near_config_geometry(int c, double* ox, double* oy, double* side);
+
+struct Tables {
+  int K = 0, n = 0, Kbar = 0, deg = 0, nG = 0, nX = 0, p = 0;
+  double root_cx = 0, root_cy = 0, root_size = 0;
+  std::vector<double> t, tbar;         // 1D first-kind nodes (ascending)
+  std::vector<double> w2;              // n weights of the unit square, sum 1
+  std::vector<double> stencil_xy;      // nX x 2 (Sbar frame)
+  std::vector<double> A;               // nX x nG, row-major
+  std::vector<double> AbarT;           // nG x Kbar^2 (transposed Sbar rows)
+  std::vector<double> cbar;            // Kbar x Kbar values -> coefficients
+  std::vector<double> near;            // 33 x n x n, [c][j][i]
+  std::vector<double> near_s2;         // 33: (source side / target side)^2
+  std::vector<double> p2m;             // (p+1) x n complex, [k][j] (re,im)
+  std::vector<double> l2p;             // n x (p+1) complex, [i][l]
+  std::vector<double> m2m;             // 4 x (p+1) x (p+1) complex, [q][k][l]
+  std::vector<double> l2l;             // 4 x (p+1) x (p+1) complex, [q][k][l]
+  std::vector<double> m2l;             // 49 x (p+1) x (p+1) complex, [o][k][l]
+  std::vector<double> p2l;             // 36 x (p+1) x n complex, [c][l][j]
+  std::vector<double> p2l_area;        // 36: source area in units h^2 (0 if unused)
+};
+
+// Host precompute (quadrature.cpp, stencil.cpp)
+void build_tables(Tables& T);
+void gauss_legendre(int q, double* x, double* w);
+void log_product_rule(int N, double* r, double* w, double* wl);
+void padua_points(int deg, std::vector<double>& xy);
+void build_stencil(Tables& T);
+// pseudo-inverse of the m x n row-major matrix A (n x m row-major result),
+// singular values below rel_cut * sigma_max dropped; returns the rank.
+int pinv_jacobi(const double* A, int m, int n, double rel_cut, double* P);
+
+// Device copy of the universal tables
+struct DeviceTables {
+  bool ready = false;
+  int device = -1;
+  double *t = nullptr, *tbar = nullptr, *w2 = nullptr, *AbarT = nullptr, *cbar = nullptr;
+  double *near = nullptr, *near_s2 = nullptr;
+  double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
+  double* p2l_area = nullptr;
+};
+
+struct Context {
+  Tables T;
+  DeviceTables D;
+};
+
+// Host-side plan ------------------------------------------------------------
+struct HostPlan {
+  int L = 0, B = 0, nlev = 0, ncut = 0;
+  std::vector<int> box_level, box_ix, box_iy, box_parent, box_child0, box_leaf;
+  std::vector<double> box_cx, box_cy;
+  std::vector<int> level_start;              // nlev + 1
+  std::vector<int> leaf_box;                 // L
+  std::vector<int8_t> kind;                  // L
+  std::vector<int> l1_ptr, l1_src, l1_cfg;   // per leaf
+  std::vector<int> l2_ptr, l2_src, l2_off;   // per box
+  std::vector<int> l3_ptr, l3_src;           // per leaf (source boxes)
+  std::vector<int> l4_ptr, l4_src, l4_cfg;   // per box (source leaves)
+  std::vector<int> cut_leaf;                 // ncut
+  std::vector<int> owner;                    // L
+  std::vector<int> ext_ptr, ext_tgt;         // per cut leaf (targets, itself first)
+  std::vector<int> pinv_ptr;                 // ncut + 1 (in interior points)
+  std::vector<uint16_t> pinv_idx;            // interior stencil indices
+  std::vector<double> pinv_val;              // per cut: nG x N_I row-major
+  std::vector<uint8_t> sbar_given;           // ncut x Kbar^2
+  double plan_seconds = 0;
+};
+
+struct DevicePlan {
+  bool ready = false;
+  int *box_level = nullptr, *box_child0 = nullptr, *box_leaf = nullptr, *box_parent = nullptr;
+  double *box_cx = nullptr, *box_cy = nullptr;
+  int* leaf_box = nullptr;
+  int8_t* kind = nullptr;
+  int *l1_ptr = nullptr, *l1_src = nullptr, *l1_cfg = nullptr;
+  int *l2_ptr = nullptr, *l2_src = nullptr, *l2_off = nullptr;
+  int *l3_ptr = nullptr, *l3_src = nullptr;
+  int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
+  int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
+  uint16_t* pinv_idx = nullptr;
+  double* pinv_val = nullptr;
+  uint8_t* sbar_given = nullptr;
+  double2 *mpole = nullptr, *local = nullptr;
+};
+
+struct Plan {
+  Context* ctx = nullptr;
+  HostPlan H;
+  DevicePlan D;
+  bool timing = false;
+  hipEvent_t ev[8] = {};
+  bool ev_ready = false;
+  bool ev_recorded = false;
+};
+
+// plan.cpp
+int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err);
+
+// kernels.hip
+int upload_tables(Context* c, std::string& err);
+int upload_plan(Plan* p, std::string& err);
+void free_plan_device(Plan* p);
+void free_tables_device(Context* c);
+int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V,
+                   hipStream_t s, std::string& err);
+
+}  // namespace vfx

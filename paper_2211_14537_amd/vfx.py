@@ -1,0 +1,229 @@
+"""Python binding of the vfx C-ABI library (argument marshalling only).
+
+Every step of the extension and the volume FMM runs in the HIP library
+``lib/libvfx.so``; this module converts arguments and raises on errors.  If
+the library has not been built the import of the binding fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libvfx.so")
+
+VFX_OK = 0
+VFX_EINVAL = -1
+VFX_ETREE = -2
+VFX_EHIP = -4
+VFX_ENOMEM = -5
+
+
+class VfxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("Kbar", ctypes.c_int32), ("deg", ctypes.c_int32),
+                ("p", ctypes.c_int32), ("root_cx", ctypes.c_double), ("root_cy", ctypes.c_double),
+                ("root_size", ctypes.c_double)]
+
+
+class _Tree(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int32),
+                ("level", ctypes.POINTER(ctypes.c_int32)),
+                ("ix", ctypes.POINTER(ctypes.c_int32)),
+                ("iy", ctypes.POINTER(ctypes.c_int32)),
+                ("kind", ctypes.POINTER(ctypes.c_int8)),
+                ("cut_mask", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int32), ("n_boxes", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("n_cut", ctypes.c_int32), ("n_ext_targets", ctypes.c_int32),
+                ("n_list1", ctypes.c_int64), ("n_list2", ctypes.c_int64), ("n_list3", ctypes.c_int64),
+                ("n_list4", ctypes.c_int64), ("pinv_doubles", ctypes.c_int64),
+                ("plan_seconds", ctypes.c_double)]
+
+
+_lib = None
+
+EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points", "vfx_leaf_nodes",
+            "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
+            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_last_error",
+            "vfx_debug_table", "vfx_plan_lists", "vfx_plan_boxes")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"vfx: HIP library not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.vfx_create.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(vp)]
+        L.vfx_destroy.argtypes = [vp]
+        L.vfx_stencil_size.argtypes = [vp, i32p, i32p]
+        L.vfx_stencil_points.argtypes = [vp, dp]
+        L.vfx_leaf_nodes.argtypes = [vp, dp]
+        L.vfx_plan_create.argtypes = [vp, ctypes.POINTER(_Tree), ctypes.POINTER(vp)]
+        L.vfx_plan_destroy.argtypes = [vp]
+        L.vfx_plan_stats_get.argtypes = [vp, ctypes.POINTER(_Stats)]
+        L.vfx_plan_ext_owner.argtypes = [vp, i32p]
+        L.vfx_execute.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.vfx_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.vfx_plan_timings.argtypes = [vp, dp, ctypes.c_int]
+        L.vfx_last_error.restype = ctypes.c_char_p
+        L.vfx_debug_table.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int64]
+        L.vfx_plan_lists.argtypes = [vp, ctypes.c_int, i32p, i32p, i32p]
+        L.vfx_plan_boxes.argtypes = [vp, i32p, i32p, i32p, i32p]
+        for name in EXPORTED:
+            if name != "vfx_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != VFX_OK:
+        raise VfxError(rc, lib().vfx_last_error().decode())
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+class Context:
+    """Universal tables for (K, Kbar, deg, p) over one root box."""
+
+    def __init__(self, K, p, Kbar=12, deg=10, root=(0.0, 0.0, 2.0)):
+        prm = _Params(K, Kbar, deg, p, float(root[0]), float(root[1]), float(root[2]))
+        h = ctypes.c_void_p()
+        _check(lib().vfx_create(ctypes.byref(prm), ctypes.byref(h)))
+        self._h = h
+        self.K, self.p, self.Kbar, self.deg, self.root = K, p, Kbar, deg, tuple(root)
+        nx = ctypes.c_int32()
+        ng = ctypes.c_int32()
+        _check(lib().vfx_stencil_size(self._h, ctypes.byref(nx), ctypes.byref(ng)))
+        self.n_stencil, self.n_support = nx.value, ng.value
+
+    def stencil_points(self):
+        xy = np.zeros(2 * self.n_stencil)
+        _check(lib().vfx_stencil_points(self._h, _ptr(xy, ctypes.c_double)))
+        return xy.reshape(-1, 2)
+
+    def leaf_nodes(self):
+        t = np.zeros(self.K)
+        _check(lib().vfx_leaf_nodes(self._h, _ptr(t, ctypes.c_double)))
+        return t
+
+    def debug_table(self, which, index, count):
+        out = np.zeros(count)
+        _check(lib().vfx_debug_table(self._h, which, index, _ptr(out, ctypes.c_double), count))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vfx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A tree prepared for repeated execution (lists, extension operators)."""
+
+    def __init__(self, ctx, level, ix, iy, kind, cut_mask=None):
+        self.ctx = ctx
+        self._level = np.ascontiguousarray(level, dtype=np.int32)
+        self._ix = np.ascontiguousarray(ix, dtype=np.int32)
+        self._iy = np.ascontiguousarray(iy, dtype=np.int32)
+        self._kind = np.ascontiguousarray(kind, dtype=np.int8)
+        ncut = int((self._kind == 2).sum())
+        if cut_mask is None:
+            cut_mask = np.zeros((ncut, ctx.n_stencil), dtype=np.uint8)
+        self._mask = np.ascontiguousarray(cut_mask, dtype=np.uint8).reshape(ncut, ctx.n_stencil)
+        tr = _Tree(self._level.size, _ptr(self._level, ctypes.c_int32), _ptr(self._ix, ctypes.c_int32),
+                   _ptr(self._iy, ctypes.c_int32), _ptr(self._kind, ctypes.c_int8),
+                   _ptr(self._mask, ctypes.c_uint8))
+        h = ctypes.c_void_p()
+        _check(lib().vfx_plan_create(ctx._h, ctypes.byref(tr), ctypes.byref(h)))
+        self._h = h
+        self.n_leaves = self._level.size
+        self.n_cut = ncut
+
+    def stats(self):
+        s = _Stats()
+        _check(lib().vfx_plan_stats_get(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in _Stats._fields_}
+
+    def ext_owner(self):
+        o = np.zeros(self.n_leaves, dtype=np.int32)
+        _check(lib().vfx_plan_ext_owner(self._h, _ptr(o, ctypes.c_int32)))
+        return o
+
+    def lists(self, which):
+        """Interaction list `which` (1..4) as (ptr, src, cfg) arrays."""
+        st = self.stats()
+        nb = st["n_leaves"] if which in (1, 3) else st["n_boxes"]
+        cnt = st[f"n_list{which}"]
+        ptr = np.zeros(nb + 1, dtype=np.int32)
+        src = np.zeros(max(cnt, 1), dtype=np.int32)
+        cfg = np.zeros(max(cnt, 1), dtype=np.int32)
+        _check(lib().vfx_plan_lists(self._h, which, _ptr(ptr, ctypes.c_int32), _ptr(src, ctypes.c_int32),
+                                    _ptr(cfg, ctypes.c_int32)))
+        return ptr, src[:cnt], cfg[:cnt]
+
+    def boxes(self):
+        nb = self.stats()["n_boxes"]
+        a = [np.zeros(nb, dtype=np.int32) for _ in range(4)]
+        _check(lib().vfx_plan_boxes(self._h, *[_ptr(x, ctypes.c_int32) for x in a]))
+        return dict(zip(("level", "ix", "iy", "leaf"), a))
+
+    def execute(self, f_leaf, f_cut, fe_out, V_out, stream=None):
+        """Enqueue the extension + FMM on `stream` (torch CUDA tensors, float64)."""
+        import torch
+        n = self.ctx.K * self.ctx.K
+        for name, t, shape in (("f_leaf", f_leaf, (self.n_leaves, n)), ("fe_out", fe_out, (self.n_leaves, n)),
+                               ("V_out", V_out, (self.n_leaves, n))):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == shape):
+                raise ValueError(f"{name}: expected contiguous float64 CUDA tensor of shape {shape}")
+        fc = 0
+        if self.n_cut:
+            if not (f_cut.is_cuda and f_cut.dtype == torch.float64 and f_cut.is_contiguous()
+                    and tuple(f_cut.shape) == (self.n_cut, self.ctx.n_stencil)):
+                raise ValueError("f_cut: expected contiguous float64 CUDA tensor (n_cut, |X|)")
+            fc = f_cut.data_ptr()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().vfx_execute(self._h, f_leaf.data_ptr(), fc, fe_out.data_ptr(), V_out.data_ptr(),
+                                 ctypes.c_void_p(stream.cuda_stream)))
+
+    def set_timing(self, on=True):
+        _check(lib().vfx_plan_set_timing(self._h, 1 if on else 0))
+
+    PHASES = ("extension", "p2m_m2m", "m2l_p2l", "l2l", "near", "far", "total")
+
+    def timings(self):
+        ms = np.zeros(7)
+        _check(lib().vfx_plan_timings(self._h, _ptr(ms, ctypes.c_double), 7))
+        return dict(zip(self.PHASES, ms.tolist()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().vfx_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,194 @@
+"""Host-side checks of the HIP library (CPU only, no kernel launches).
+
+* the shared library loads and exports every function declared in
+  include/vfx.h;
+* its stencil and interpolation matrix equal the oracle's;
+* its near-field tables reproduce the oracle's direct quadrature for all 33
+  list-1 configurations;
+* its interaction lists partition the source leaves for every target leaf
+  (every source reached exactly once, through the near field or exactly one
+  far-field path);
+* its extension lists equal the oracle's;
+* invalid input is rejected with the documented status codes.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import cheb, geometry, stencil, volume
+from paper_2211_14537_amd import tree as T
+from paper_2211_14537_amd import vfx
+from workloads import get_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "vfx.h")).read()
+    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(vfx_\w+)\s*\(", hdr, flags=re.M))
+    assert len(names) >= 15
+    L = vfx.lib()
+    for nm in sorted(names):
+        assert hasattr(L, nm), nm
+    assert set(vfx.EXPORTED) == names
+
+
+@pytest.mark.parametrize("K", [8, 16])
+def test_stencil_and_matrix_match_oracle(K):
+    ctx = vfx.Context(K, 20)
+    P = ctx.stencil_points()
+    Po = stencil.stencil_points(K)
+    assert P.shape == Po.shape
+    assert np.abs(P - Po).max() < 1e-15
+    A = ctx.debug_table(1, 0, P.shape[0] * 66).reshape(-1, 66)
+    Ao = stencil.interp_matrix(K)
+    assert np.abs(A - Ao).max() < 1e-12
+    assert np.allclose(ctx.leaf_nodes(), cheb.nodes(K), atol=1e-16, rtol=0)
+
+
+def _near_geometry(c):
+    if c < 9:
+        return c // 3 - 1, c % 3 - 1, 1.0
+    cells = [(a, b) for a in range(4) for b in range(4) if not (a in (1, 2) and b in (1, 2))]
+    a, b = cells[(c - 9) if c < 21 else (c - 21)]
+    if c < 21:
+        return (2 * a - 3) / 2, (2 * b - 3) / 2, 2.0
+    return (2 * a - 3) / 4, (2 * b - 3) / 4, 0.5
+
+
+@pytest.mark.parametrize("K", [8])
+def test_near_tables_match_oracle_quadrature(K):
+    n = K * K
+    ctx = vfx.Context(K, 20)
+    t = cheb.nodes(K)
+    tx = (0.5 * t[:, None] + 0 * t[None, :]).ravel()
+    ty = (0 * t[:, None] + 0.5 * t[None, :]).ravel()
+    rng = np.random.default_rng(0)
+    for c in range(33):
+        Tc = ctx.debug_table(0, c, n * n).reshape(n, n)
+        ox, oy, s = _near_geometry(c)
+        f = rng.standard_normal(n)
+        vo = volume.potential_boxes(tx, ty, [ox], [oy], [s], volume.leaf_coefficients(f[None], K), K)
+        err = np.abs(f @ Tc - 2 * np.pi * vo).max()
+        assert err < 2e-14, (c, err)
+
+
+def _plan_for(name, all_regular=False):
+    cfg = get_config(name)
+    ctx = vfx.Context(cfg["K"], cfg["p"], root=cfg["root"])
+    tr = T.build_tree(cfg, ctx.stencil_points())
+    kind = np.ones_like(tr["kind"]) if all_regular else tr["kind"]
+    return cfg, ctx, tr, vfx.Plan(ctx, tr["level"], tr["ix"], tr["iy"], kind, None if all_regular else tr["mask"])
+
+
+@pytest.mark.parametrize("name", ["disk_uniform3", "disk_adaptive_small", "starfish_small"])
+def test_lists_partition_sources(name):
+    cfg, ctx, tr, plan = _plan_for(name, all_regular=True)
+    bx = plan.boxes()
+    B = bx["level"].size
+    L = tr["level"].size
+    key = {(int(bx["level"][b]), int(bx["ix"][b]), int(bx["iy"][b])): b for b in range(B)}
+    parent = np.full(B, -1)
+    for b in range(B):
+        lv = bx["level"][b]
+        if lv > 0:
+            parent[b] = key[(int(lv) - 1, int(bx["ix"][b]) >> 1, int(bx["iy"][b]) >> 1)]
+    kids = {}
+    for b in range(B):
+        if parent[b] >= 0:
+            kids.setdefault(parent[b], []).append(b)
+
+    def leaves_under(b):
+        if bx["leaf"][b] >= 0:
+            return [int(bx["leaf"][b])]
+        out = []
+        for c in kids[b]:
+            out += leaves_under(c)
+        return out
+
+    p1, s1, _ = plan.lists(1)
+    p2, s2, _ = plan.lists(2)
+    p3, s3, _ = plan.lists(3)
+    p4, s4, _ = plan.lists(4)
+    leaf_box = {int(bx["leaf"][b]): b for b in range(B) if bx["leaf"][b] >= 0}
+    for leaf in range(L):
+        got = list(s1[p1[leaf]:p1[leaf + 1]])
+        for w in s3[p3[leaf]:p3[leaf + 1]]:
+            got += leaves_under(w)
+        b = leaf_box[leaf]
+        while b >= 0:
+            for s in s2[p2[b]:p2[b + 1]]:
+                got += leaves_under(s)
+            got += list(s4[p4[b]:p4[b + 1]])
+            b = parent[b]
+        assert sorted(got) == list(range(L)), leaf
+
+
+@pytest.mark.parametrize("name", ["disk_uniform3", "disk_adaptive_small", "starfish_small"])
+def test_extension_owner_matches_oracle(name):
+    cfg, ctx, tr, plan = _plan_for(name)
+    ot = geometry.Tree(tr["level"], tr["ix"], tr["iy"], cfg["root"])
+    assert ot.check_partition() and ot.is_balanced()
+    own, viol = geometry.extension_owner(ot, tr["kind"])
+    assert not viol
+    assert np.array_equal(plan.ext_owner(), own)
+    m = geometry.cut_masks(ot, list(tr["cut_ids"]), cfg["domain"], cfg["K"])
+    assert np.array_equal(m, tr["mask"].astype(bool))
+    st = plan.stats()
+    assert st["n_cut"] == tr["cut_ids"].size
+    assert st["pinv_doubles"] == 66 * int(tr["mask"].sum())
+
+
+def test_rejects_invalid_input():
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Context(1, 20)
+    assert e.value.code == vfx.VFX_EINVAL
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Context(8, 100)
+    assert e.value.code == vfx.VFX_EINVAL
+    ctx = vfx.Context(8, 20)
+    # leaves that do not tile the root
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Plan(ctx, [1, 1, 1], [0, 1, 0], [0, 0, 1], [1, 1, 1])
+    assert e.value.code == vfx.VFX_ETREE
+    # duplicate leaf
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Plan(ctx, [1, 1, 1, 1, 1], [0, 1, 0, 1, 1], [0, 0, 1, 1, 1], [1] * 5)
+    assert e.value.code == vfx.VFX_ETREE
+    # not level-restricted: level 3 leaves next to a level 1 leaf
+    lv, ix, iy = [1, 1, 1], [1, 0, 1], [0, 1, 1]
+    for a in range(2):
+        for b in range(2):
+            if (a, b) == (1, 1):
+                for c in range(2):
+                    for d in range(2):
+                        lv.append(3), ix.append(2 * a + c), iy.append(2 * b + d)
+            else:
+                lv.append(2), ix.append(a), iy.append(b)
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Plan(ctx, lv, ix, iy, [1] * len(lv))
+    assert e.value.code == vfx.VFX_ETREE
+    # extension restriction: fine cut leaf closest to a coarse exterior leaf
+    lv, ix, iy = [], [], []
+    for a in range(4):
+        for b in range(4):
+            if (a, b) == (1, 1):
+                for c in range(2):
+                    for d in range(2):
+                        lv.append(3), ix.append(2 * a + c), iy.append(2 * b + d)
+            else:
+                lv.append(2), ix.append(a), iy.append(b)
+    kind = [1] * len(lv)
+    cut = [i for i in range(len(lv)) if (lv[i], ix[i], iy[i]) == (3, 2, 2)][0]
+    ext = [i for i in range(len(lv)) if (lv[i], ix[i], iy[i]) == (2, 0, 0)][0]
+    kind[cut], kind[ext] = 2, 0
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Plan(ctx, lv, ix, iy, kind, np.ones((1, ctx.n_stencil), dtype=np.uint8))
+    assert e.value.code == vfx.VFX_ETREE
+    assert "extension restriction" in str(e.value)
+    # kinds out of range
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Plan(ctx, [0], [0], [0], [5])
+    assert e.value.code == vfx.VFX_EINVAL
