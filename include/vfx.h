@@ -130,11 +130,14 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
 int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
                 double* V_out, void* stream);
 
-/* Per-phase timing with HIP events recorded on the execute stream.  When
- * enabled, every vfx_execute records events around its phases; the query
- * synchronises on the last event and returns milliseconds of the most
- * recent execute, in this order: extension, P2M+M2M, M2L+P2L, L2L,
- * near field, far field (L2P+M2P), total.  n_out must be >= 7. */
+/* Per-phase timing with HIP events recorded on the execute stream.  While
+ * enabled, every vfx_execute records 7 events around its phases (at most
+ * 4096 executes are recorded; enabling again restarts the count).  The
+ * query synchronises on the last recorded event and returns, averaged over
+ * the recorded executes, the milliseconds of: extension (f^e assembly and
+ * the cut-leaf kernel), P2M+M2M, M2L+P2L, L2L, near field, far field
+ * (L2P+M2P), total; ms[7] (if n_out >= 8) receives the number of executes
+ * averaged.  n_out must be >= 7. */
 int vfx_plan_set_timing(vfx_plan* plan, int enable);
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
 

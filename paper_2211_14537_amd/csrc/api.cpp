@@ -166,25 +166,28 @@ int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, doubl
 int vfx_plan_set_timing(vfx_plan* plan, int enable) {
   if (!plan) return fail(VFX_EINVAL, "vfx_plan_set_timing: null argument");
   plan->p.timing = enable != 0;
+  plan->p.n_timed = 0;
   return VFX_OK;
 }
 
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
   if (!plan || !ms || n_out < 7) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
   vfx::Plan& p = plan->p;
-  if (!p.ev_recorded) return fail(VFX_EINVAL, "vfx_plan_timings: no timed execute recorded");
-  hipError_t e = hipEventSynchronize(p.ev[6]);
+  if (p.n_timed == 0) return fail(VFX_EINVAL, "vfx_plan_timings: no timed execute recorded");
+  hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * 7 + 6]);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
-  for (int k = 0; k < 6; ++k) {
-    float t = 0;
-    e = hipEventElapsedTime(&t, p.ev[k], p.ev[k + 1]);
-    if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
-    ms[k] = t;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int r = 0; r < p.n_timed; ++r) {
+    const hipEvent_t* ev = &p.ev[(size_t)r * 7];
+    for (int k = 0; k < 7; ++k) {
+      float t = 0;
+      e = hipEventElapsedTime(&t, ev[k == 6 ? 0 : k], ev[k == 6 ? 6 : k + 1]);
+      if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
+      acc[k] += t;
+    }
   }
-  float tot = 0;
-  e = hipEventElapsedTime(&tot, p.ev[0], p.ev[6]);
-  if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
-  ms[6] = tot;
+  for (int k = 0; k < 7; ++k) ms[k] = acc[k] / p.n_timed;
+  if (n_out >= 8) ms[7] = p.n_timed;
   return VFX_OK;
 }
 

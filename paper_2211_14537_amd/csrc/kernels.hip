@@ -490,8 +490,8 @@ void free_plan_device(Plan* p) {
   D = DevicePlan();
   for (auto& e : p->ev)
     if (e) (void)hipEventDestroy(e);
-  for (auto& e : p->ev) e = nullptr;
-  p->ev_ready = false;
+  p->ev.clear();
+  p->n_timed = 0;
 }
 
 int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V, hipStream_t s,
@@ -510,13 +510,19 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   const DeviceTables& DT = c->D;
   const DevicePlan& D = p->D;
   const int n = T.n, P = T.p + 1, L = H.L;
-  if (p->timing && !p->ev_ready) {
-    for (auto& e : p->ev) VFX_HIP(hipEventCreate(&e));
-    p->ev_ready = true;
+  constexpr int kMaxTimed = 4096;
+  const bool timed = p->timing && p->n_timed < kMaxTimed;
+  const size_t ev0 = (size_t)p->n_timed * 7;
+  if (timed && p->ev.size() < ev0 + 7) {
+    for (int k = 0; k < 7; ++k) {
+      hipEvent_t e;
+      VFX_HIP(hipEventCreate(&e));
+      p->ev.push_back(e);
+    }
   }
   auto mark = [&](int k) -> int {
-    if (p->timing) {
-      hipError_t e = hipEventRecord(p->ev[k], s);
+    if (timed) {
+      hipError_t e = hipEventRecord(p->ev[ev0 + k], s);
       if (e != hipSuccess) {
         err = std::string("hipEventRecord: ") + hipGetErrorString(e);
         return VFX_EHIP;
@@ -572,7 +578,7 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
                      D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.l2p, D.local, D.mpole, V);
   VFX_HIP(hipGetLastError());
   MARK(6);
-  p->ev_recorded = p->timing;
+  if (timed) p->n_timed++;
   return VFX_OK;
 }
 

@@ -119,10 +119,10 @@ struct Plan {
   Context* ctx = nullptr;
   HostPlan H;
   DevicePlan D;
+  // per-phase timing: one set of 7 events per timed execute
   bool timing = false;
-  hipEvent_t ev[8] = {};
-  bool ev_ready = false;
-  bool ev_recorded = false;
+  std::vector<hipEvent_t> ev;   // 7 * capacity
+  int n_timed = 0;
 };
 
 // plan.cpp

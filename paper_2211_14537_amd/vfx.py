@@ -213,9 +213,13 @@ class Plan:
     PHASES = ("extension", "p2m_m2m", "m2l_p2l", "l2l", "near", "far", "total")
 
     def timings(self):
-        ms = np.zeros(7)
-        _check(lib().vfx_plan_timings(self._h, _ptr(ms, ctypes.c_double), 7))
-        return dict(zip(self.PHASES, ms.tolist()))
+        """Per-phase milliseconds averaged over the executes recorded since
+        set_timing(True), plus their count."""
+        ms = np.zeros(8)
+        _check(lib().vfx_plan_timings(self._h, _ptr(ms, ctypes.c_double), 8))
+        out = dict(zip(self.PHASES, ms[:7].tolist()))
+        out["count"] = int(ms[7])
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
