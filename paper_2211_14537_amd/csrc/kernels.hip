@@ -318,13 +318,89 @@ __global__ void __launch_bounds__(256) k_near(int n, int P, double root_size, co
   if (i < n) V[(size_t)leaf * n + i] = kInv2Pi * (h * h * acc + logh * lg);
 }
 
+// Near field as batched GEMMs on the FP64 matrix cores.  List-1 pairs are
+// grouped by table configuration c; a work-group takes a tile of <= 32 pairs
+// of one configuration and computes Y[pair] = T_c f_src for all n rows:
+// C (n x 32) = T_c (n x n) * F (n x 32).  F is staged in LDS; each wave owns
+// n/4 rows, reads the table's A fragments from L2 (the configuration's table
+// is shared by every tile of it) and keeps RT x 2 16x16 accumulators.
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and the
+// outputs D[(l/16) + 4r][l%16], r = 0..3 (lane layout checked on gfx950).
+typedef double vfx_d4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+__global__ void __launch_bounds__(256) k_near_mfma(const int* __restrict__ nt_cfg, const int* __restrict__ nt_first,
+                                                   const int* __restrict__ nt_count, const int* __restrict__ np_src,
+                                                   const double* __restrict__ near, const double* __restrict__ fe,
+                                                   double* __restrict__ Y) {
+  constexpr int RT = N / 64;      // row tiles of 16 per wave (4 waves x RT x 16 = N rows)
+  constexpr int LD = N + 1;       // padded LDS row (bank spread for the B fragments)
+  __shared__ double sF[32 * LD];
+  // XCD-aware order: consecutive tiles (same configuration, same table) go to
+  // the same XCD, whose L2 then serves the table to all of them
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, rr = nb & 7, x = b & 7, i8 = b >> 3;
+  const int tile = x * q + min(x, rr) + i8;
+  const int c = nt_cfg[tile], p0 = nt_first[tile], np = nt_count[tile];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < 32 * N; e += 256) {
+    const int j = e / N, k = e - j * N;
+    sF[j * LD + k] = (j < np) ? fe[(size_t)np_src[p0 + j] * N + k] : 0.0;
+  }
+  __syncthreads();
+  vfx_d4 acc[RT][2];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    acc[r][0] = vfx_d4{0, 0, 0, 0};
+    acc[r][1] = vfx_d4{0, 0, 0, 0};
+  }
+  const double* Tc = near + (size_t)c * N * N;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row0 = w * (N / 4) + li;
+  double a_cur[RT], a_nxt[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) a_cur[r] = Tc[(size_t)lk * N + row0 + 16 * r];
+  for (int ks = 0; ks < N / 4; ++ks) {
+    const int k = 4 * ks + lk;
+    if (ks + 1 < N / 4) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r) a_nxt[r] = Tc[(size_t)(k + 4) * N + row0 + 16 * r];
+    }
+    const double b0 = sF[li * LD + k];
+    const double b1 = sF[(16 + li) * LD + k];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      acc[r][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b0, acc[r][0], 0, 0, 0);
+      acc[r][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b1, acc[r][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r) a_cur[r] = a_nxt[r];
+  }
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int pr = 16 * ct + li;
+      if (pr < np) {
+        double* y = Y + (size_t)(p0 + pr) * N + w * (N / 4) + 16 * r + lk;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) y[4 * e] = acc[r][ct][e];
+      }
+    }
+}
+
 // Far field: L2P of the local expansion and M2P of list 3 (l2p stored [l][i])
+// With Y given, the near field is also finished here: the per-pair partials
+// of the leaf's list-1 entries are summed in list order (deterministic) and
+// the log(h) a_0 term added; V is then written, else it is accumulated.
 __global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, const int* __restrict__ leaf_box,
                                              const int* __restrict__ box_level, const double* __restrict__ box_cx,
                                              const double* __restrict__ box_cy, const double* __restrict__ t,
                                              const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
                                              const double2* __restrict__ l2p, const double2* __restrict__ local,
-                                             const double2* __restrict__ mpole, double* __restrict__ V) {
+                                             const double2* __restrict__ mpole, const int* __restrict__ l1_ptr,
+                                             const int* __restrict__ l1_src, const int* __restrict__ l1_slot,
+                                             const double* __restrict__ Y, double* __restrict__ V) {
   __shared__ double2 s_a[64];
   const int n = K * K;
   const int leaf = blockIdx.x;
@@ -333,6 +409,14 @@ __global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, con
   const int lev = box_level[b];
   const double h = box_side(root_size, lev);
   double acc = 0.0;
+  if (Y != nullptr && i < n) {
+    double yn = 0.0, lg = 0.0;
+    for (int e = l1_ptr[leaf]; e < l1_ptr[leaf + 1]; ++e) {
+      yn += Y[(size_t)l1_slot[e] * n + i];
+      lg += mpole[(size_t)leaf_box[l1_src[e]] * P].x;
+    }
+    acc = h * h * yn + log(h) * lg;
+  }
   if (lev >= 2) {
     if (i < P) s_a[i] = local[(size_t)b * P + i];
     __syncthreads();
@@ -364,10 +448,18 @@ __global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, con
       acc += s_a[0].x * 0.5 * log(r2) + sr;
     }
   }
-  if (i < n) V[(size_t)leaf * n + i] += kInv2Pi * acc;
+  if (i < n) {
+    if (Y != nullptr)
+      V[(size_t)leaf * n + i] = kInv2Pi * acc;
+    else
+      V[(size_t)leaf * n + i] += kInv2Pi * acc;
+  }
 }
 
 // -------------------------------------------------------------------------
+// The MFMA near-field path needs n a multiple of 64 (K = 8, 16).
+static bool use_mfma_near(const Tables& T) { return T.n == 64 || T.n == 256; }
+
 template <typename T>
 static int upload(T** dst, const T* src, size_t count, std::string& err) {
   *dst = nullptr;
@@ -465,6 +557,13 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.l4_ptr, H.l4_ptr);
   UP(D.l4_src, H.l4_src);
   UP(D.l4_cfg, H.l4_cfg);
+  UP(D.np_src, H.np_src);
+  UP(D.l1_slot, H.l1_slot);
+  UP(D.nt_cfg, H.nt_cfg);
+  UP(D.nt_first, H.nt_first);
+  UP(D.nt_count, H.nt_count);
+  if (use_mfma_near(p->ctx->T) && !H.np_src.empty())
+    VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * p->ctx->T.n));
   UP(D.cut_leaf, H.cut_leaf);
   UP(D.ext_ptr, H.ext_ptr);
   UP(D.ext_tgt, H.ext_tgt);
@@ -483,7 +582,8 @@ void free_plan_device(Plan* p) {
   DevicePlan& D = p->D;
   void* ptrs[] = {D.box_level, D.box_child0, D.box_leaf, D.box_parent, D.box_cx, D.box_cy, D.leaf_box, D.kind,
                   D.l1_ptr, D.l1_src, D.l1_cfg, D.l2_ptr, D.l2_src, D.l2_off, D.l3_ptr, D.l3_src,
-                  D.l4_ptr, D.l4_src, D.l4_cfg, D.cut_leaf, D.ext_ptr, D.ext_tgt, D.pinv_ptr, D.pinv_idx,
+                  D.l4_ptr, D.l4_src, D.l4_cfg, D.np_src, D.l1_slot, D.nt_cfg, D.nt_first, D.nt_count,
+                  D.near_y, D.cut_leaf, D.ext_ptr, D.ext_tgt, D.pinv_ptr, D.pinv_idx,
                   D.pinv_val, D.sbar_given, D.mpole, D.local};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -570,12 +670,24 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   }
   VFX_HIP(hipGetLastError());
   MARK(4);
-  hipLaunchKernelGGL(k_near, dim3(L), dim3(n < 64 ? 64 : n), 0, s, n, P, T.root_size, D.leaf_box, D.box_level,
-                     D.l1_ptr, D.l1_src, D.l1_cfg, DT.near, D.mpole, fe, V);
+  const bool mfma = D.near_y != nullptr;
+  if (mfma) {
+    const int ntiles = (int)H.nt_cfg.size();
+    if (n == 256)
+      hipLaunchKernelGGL(k_near_mfma<256>, dim3(ntiles), dim3(256), 0, s, D.nt_cfg, D.nt_first, D.nt_count,
+                         D.np_src, DT.near, fe, D.near_y);
+    else
+      hipLaunchKernelGGL(k_near_mfma<64>, dim3(ntiles), dim3(256), 0, s, D.nt_cfg, D.nt_first, D.nt_count,
+                         D.np_src, DT.near, fe, D.near_y);
+  } else {
+    hipLaunchKernelGGL(k_near, dim3(L), dim3(n < 64 ? 64 : n), 0, s, n, P, T.root_size, D.leaf_box, D.box_level,
+                       D.l1_ptr, D.l1_src, D.l1_cfg, DT.near, D.mpole, fe, V);
+  }
   VFX_HIP(hipGetLastError());
   MARK(5);
   hipLaunchKernelGGL(k_far, dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box, D.box_level,
-                     D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.l2p, D.local, D.mpole, V);
+                     D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.l2p, D.local, D.mpole, D.l1_ptr, D.l1_src,
+                     D.l1_slot, mfma ? D.near_y : nullptr, V);
   VFX_HIP(hipGetLastError());
   MARK(6);
   if (timed) p->n_timed++;

@@ -234,6 +234,31 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     H.l3_ptr[leaf + 1] = H.l3_ptr[leaf] + (int)l3[leaf].size();
     for (int s : l3[leaf]) H.l3_src.push_back(s);
   }
+  // ---- list-1 pairs grouped by configuration -----------------------------
+  {
+    const int N1 = H.l1_ptr[L];
+    std::vector<int> cnt(kNearConfigs + 1, 0);
+    for (int e = 0; e < N1; ++e) cnt[H.l1_cfg[e] + 1]++;
+    for (int c = 0; c < kNearConfigs; ++c) cnt[c + 1] += cnt[c];
+    H.np_src.assign(N1, 0);
+    H.np_tgt.assign(N1, 0);
+    H.l1_slot.assign(N1, 0);
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (int leaf = 0; leaf < L; ++leaf)  // targets ascending inside each configuration
+      for (int e = H.l1_ptr[leaf]; e < H.l1_ptr[leaf + 1]; ++e) {
+        const int s = pos[H.l1_cfg[e]]++;
+        H.np_src[s] = H.l1_src[e];
+        H.np_tgt[s] = leaf;
+        H.l1_slot[e] = s;
+      }
+    constexpr int kTile = 32;
+    for (int c = 0; c < kNearConfigs; ++c)
+      for (int f = cnt[c]; f < cnt[c + 1]; f += kTile) {
+        H.nt_cfg.push_back(c);
+        H.nt_first.push_back(f);
+        H.nt_count.push_back(std::min(kTile, cnt[c + 1] - f));
+      }
+  }
   // ---- lists 2 and 4 (per box, level >= 2) ------------------------------
   H.l2_ptr.assign(B + 1, 0);
   H.l4_ptr.assign(B + 1, 0);

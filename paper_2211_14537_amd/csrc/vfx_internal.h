@@ -88,6 +88,11 @@ struct HostPlan {
   std::vector<int> l2_ptr, l2_src, l2_off;   // per box
   std::vector<int> l3_ptr, l3_src;           // per leaf (source boxes)
   std::vector<int> l4_ptr, l4_src, l4_cfg;   // per box (source leaves)
+  // list-1 pairs regrouped by table configuration (config-major, targets
+  // ascending inside a configuration) for the batched near-field GEMM;
+  // l1_slot maps each per-target list-1 entry to its pair index
+  std::vector<int> np_src, np_tgt, l1_slot;
+  std::vector<int> nt_cfg, nt_first, nt_count;  // GEMM tiles of <= 32 pairs
   std::vector<int> cut_leaf;                 // ncut
   std::vector<int> owner;                    // L
   std::vector<int> ext_ptr, ext_tgt;         // per cut leaf (targets, itself first)
@@ -108,6 +113,8 @@ struct DevicePlan {
   int *l2_ptr = nullptr, *l2_src = nullptr, *l2_off = nullptr;
   int *l3_ptr = nullptr, *l3_src = nullptr;
   int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
+  int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;
+  double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
   uint16_t* pinv_idx = nullptr;
   double* pinv_val = nullptr;
