@@ -63,7 +63,7 @@ typedef struct vfx_ctx vfx_ctx;
 typedef struct vfx_plan vfx_plan;
 
 typedef struct {
-  int32_t K;         /* leaf grid size, 2..16 (the paper fixes K = 8)          */
+  int32_t K;         /* leaf grid size: 4, 8, 12 or 16 (the paper fixes 8)   */
   int32_t Kbar;      /* grid size on the extension square, 2..16 (paper: 12)  */
   int32_t deg;       /* stencil degree; N_G = (deg+1)(deg+2)/2 (paper: 66)    */
   int32_t p;         /* FMM expansion order: terms 0..p, 4 <= p <= 60         */
@@ -130,14 +130,18 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
 int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
                 double* V_out, void* stream);
 
-/* Per-phase timing with HIP events recorded on the execute stream.  While
- * enabled, every vfx_execute records 7 events around its phases (at most
- * 4096 executes are recorded; enabling again restarts the count).  The
- * query synchronises on the last recorded event and returns, averaged over
- * the recorded executes, the milliseconds of: extension (f^e assembly and
- * the cut-leaf kernel), P2M+M2M, M2L+P2L, L2L, near field, far field
- * (L2P+M2P), total; ms[7] (if n_out >= 8) receives the number of executes
- * averaged.  n_out must be >= 7. */
+/* Per-phase timing with HIP events.  The near-field GEMM runs on a side
+ * stream of the plan (default priority), forked from `stream` after the
+ * extension and joined before the far-field kernel; its phase is timed with
+ * events on that side stream, the others on `stream`.  While enabled, every
+ * vfx_execute records its events (at most 4096 executes are recorded;
+ * enabling again restarts the count).  The query synchronises on the last
+ * recorded event and returns, averaged over the recorded executes, the
+ * milliseconds of: extension (f^e assembly and the cut-leaf kernel),
+ * P2M+M2M, M2L+P2L, L2L, near field, far field (near-field reduction,
+ * L2P, M2P), total; ms[7] (if n_out >= 8) receives the number of executes
+ * averaged.  Phases on the two streams overlap, so they do not add up to the
+ * total.  n_out must be >= 7. */
 int vfx_plan_set_timing(vfx_plan* plan, int enable);
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
 
@@ -153,6 +157,12 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
  *         6: L2L of child `index` (0..3), (p+1) x (p+1) complex, [k][l]
  *         7: L2P, n x (p+1) complex, [i][l]
  *         8: unit-square quadrature weights, n
+ *         9..19 (whole arrays, `index` ignored): the scaled-Pascal translation
+ *           operands - 9 C(k+l-1,l) [k][l], 10 t^l and 11 (-t)^k per M2L slot
+ *           (49 x (p+1) complex), 12 log|d/h| per M2L slot, 13 C(l-1,k-1),
+ *           14 (2w)^-k and 15 w^l per child (4 x (p+1) complex), 16 C(k,l),
+ *           17 w^k and 18 (2w)^-l per child, 19 the P2L GEMM operand
+ *           (36 x n x rows, rows = 16 ceil(2(p+1)/16))
  * VFX_EINVAL if `which`, `index` or `count` does not match. */
 int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count);
 /* Interaction list `which` (1..4) of a plan as CSR arrays (host):

@@ -53,7 +53,8 @@ const char* vfx_last_error(void) { return g_err.c_str(); }
 int vfx_create(const vfx_params* prm, vfx_ctx** out) {
   if (!prm || !out) return fail(VFX_EINVAL, "vfx_create: null argument");
   *out = nullptr;
-  if (prm->K < 2 || prm->K > 16) return fail(VFX_EINVAL, "vfx_create: K must be in 2..16");
+  if (prm->K != 4 && prm->K != 8 && prm->K != 12 && prm->K != 16)
+    return fail(VFX_EINVAL, "vfx_create: K must be 4, 8, 12 or 16");
   if (prm->Kbar < 2 || prm->Kbar > 16) return fail(VFX_EINVAL, "vfx_create: Kbar must be in 2..16");
   if (prm->deg < 1 || prm->deg > 15) return fail(VFX_EINVAL, "vfx_create: deg must be in 1..15");
   if (prm->p < 4 || prm->p > 60) return fail(VFX_EINVAL, "vfx_create: p must be in 4..60");
@@ -173,15 +174,19 @@ int vfx_plan_set_timing(vfx_plan* plan, int enable) {
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
   if (!plan || !ms || n_out < 7) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
   vfx::Plan& p = plan->p;
+  constexpr int NE = vfx::Plan::kEvents;
   if (p.n_timed == 0) return fail(VFX_EINVAL, "vfx_plan_timings: no timed execute recorded");
-  hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * 7 + 6]);
+  hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * NE + 8]);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
+  // phase k runs from event a[k] to event b[k]
+  static const int a_[7] = {0, 1, 2, 3, 5, 7, 0};
+  static const int b_[7] = {1, 2, 3, 4, 6, 8, 8};
   double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < p.n_timed; ++r) {
-    const hipEvent_t* ev = &p.ev[(size_t)r * 7];
+    const hipEvent_t* ev = &p.ev[(size_t)r * NE];
     for (int k = 0; k < 7; ++k) {
       float t = 0;
-      e = hipEventElapsedTime(&t, ev[k == 6 ? 0 : k], ev[k == 6 ? 6 : k + 1]);
+      e = hipEventElapsedTime(&t, ev[a_[k]], ev[b_[k]]);
       if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
       acc[k] += t;
     }
@@ -235,6 +240,14 @@ int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64
       src = T.w2.data();
       size = (int64_t)T.w2.size();
       break;
+    case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17: case 18: case 19: {
+      const std::vector<double>* v[] = {&T.pas_m2l, &T.m2l_tpow, &T.m2l_tneg, &T.m2l_logd, &T.pas_m2m,
+                                        &T.m2m_in,  &T.m2m_out,  &T.pas_l2l,  &T.l2l_in,   &T.l2l_out,
+                                        &T.p2l_gemm};
+      src = v[which - 9]->data();
+      size = (int64_t)v[which - 9]->size();
+      break;
+    }
     default:
       break;
   }

@@ -180,216 +180,242 @@ __global__ void __launch_bounds__(64) k_p2m(int n, int P, double root_size, cons
   }
 }
 
-// M2M for the non-leaf boxes of one level (m2m stored [q][k][l])
+typedef double vfx_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Upward pass for the non-leaf boxes of one level, in the scaled-Pascal form
+//   b_l = sum_q w_q^l [ sum_{1<=k<=l} C(l-1,k-1) (2 w_q)^-k a_{q,k} - a_{q,0}/l ],
+//   b_0 = sum_q a_{q,0}   (w_q: child centre offset / parent side)
+// One wave per box, lane l = output coefficient; the lane's Pascal row is
+// held in registers.
+template <int PM>
 __global__ void __launch_bounds__(64) k_m2m(int P, int first, const int* __restrict__ box_child0,
-                                            const double2* __restrict__ m2m, double2* __restrict__ mpole) {
-  __shared__ double2 s_a[4 * 64];
+                                            const double* __restrict__ pas, const double2* __restrict__ sin,
+                                            const double2* __restrict__ sout, double2* __restrict__ mpole) {
+  __shared__ double2 s_s[4][PM];
   const int b = first + blockIdx.x;
   const int c0 = box_child0[b];
   if (c0 < 0) return;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < 4 * P; e += 64) s_a[e] = mpole[(size_t)c0 * P + e];
-  __syncthreads();
-  if (lane >= P) return;
-  double re = 0.0, im = 0.0;
-  for (int q = 0; q < 4; ++q)
-    for (int k = 0; k <= lane; ++k) {
-      const double2 m = m2m[((size_t)q * P + k) * P + lane];
-      const double2 a = s_a[q * P + k];
-      re += m.x * a.x - m.y * a.y;
-      im += m.x * a.y + m.y * a.x;
+  const int l = threadIdx.x;
+  double prow[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k) prow[k] = (k < P && l < P) ? pas[(size_t)k * P + l] : 0.0;
+  for (int q = 0; q < 4; ++q) {
+    double2 v = make_double2(0.0, 0.0);
+    if (l < P) {
+      const double2 a = mpole[(size_t)(c0 + q) * P + l];
+      v = (l == 0) ? a : cmul(sin[q * P + l], a);
     }
-  mpole[(size_t)b * P + lane] = make_double2(re, im);
+    if (l < PM) s_s[q][l] = v;
+  }
+  __syncthreads();
+  if (l >= P) return;
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    if (l == 0) {
+      re += s_s[q][0].x;
+      im += s_s[q][0].y;
+      continue;
+    }
+    double ur = 0.0, ui = 0.0;
+#pragma unroll
+    for (int k = 1; k < PM; ++k) {
+      ur += prow[k] * s_s[q][k].x;
+      ui += prow[k] * s_s[q][k].y;
+    }
+    ur -= s_s[q][0].x / l;
+    ui -= s_s[q][0].y / l;
+    const double2 w = sout[q * P + l];
+    re += w.x * ur - w.y * ui;
+    im += w.x * ui + w.y * ur;
+  }
+  mpole[(size_t)b * P + l] = make_double2(re, im);
 }
 
-// Local expansions from list 2 (M2L) and list 4 (P2L) for boxes at level >= 2
-// (m2l stored [o][k][l], p2l stored [c][j][l])
-__global__ void __launch_bounds__(64) k_m2l(int n, int P, int first, double root_size,
-                                            const int* __restrict__ box_level, const int* __restrict__ l2_ptr,
-                                            const int* __restrict__ l2_src, const int* __restrict__ l2_off,
-                                            const int* __restrict__ l4_ptr, const int* __restrict__ l4_src,
-                                            const int* __restrict__ l4_cfg, const double2* __restrict__ m2l,
-                                            const double2* __restrict__ p2l, const double* __restrict__ w2,
-                                            const double* __restrict__ p2l_area, const double2* __restrict__ mpole,
-                                            const double* __restrict__ fe, double2* __restrict__ local) {
-  __shared__ double2 s_a[64];
-  __shared__ double s_f[kMaxK * kMaxK];
+// Local expansions of the boxes at levels >= 2: M2L from list 2 in the
+// scaled-Pascal form (t = h/d for the source offset d)
+//   b_l += t^l sum_{k>=1} C(k+l-1,l) (-t)^k a_k - a_0 t^l / l  (l >= 1),
+//   b_0 += sum_{k>=1} (-t)^k a_k + a_0 (log|d/h| + log h),
+// plus the list-4 contributions h^2 (Q_c f_C) computed by the P2L GEMM and the
+// P2L log term log(h) a_0(C).
+template <int PM>
+__global__ void __launch_bounds__(64) k_m2l(int P, int first, double root_size, const int* __restrict__ box_level,
+                                            const int* __restrict__ l2_ptr, const int* __restrict__ l2_src,
+                                            const int* __restrict__ l2_off, const int* __restrict__ l4_ptr,
+                                            const int* __restrict__ l4_src, const int* __restrict__ l4_slot,
+                                            const int* __restrict__ leaf_box, int p2l_rows,
+                                            const double* __restrict__ pas, const double2* __restrict__ tpow,
+                                            const double2* __restrict__ tneg, const double* __restrict__ logd,
+                                            const double2* __restrict__ mpole, const double* __restrict__ p2l_y,
+                                            double2* __restrict__ local) {
+  __shared__ double2 s_s[PM];
   const int b = first + blockIdx.x;
-  const int lane = threadIdx.x;
+  const int l = threadIdx.x;
+  double prow[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k) prow[k] = (k < P && l < P) ? pas[(size_t)k * P + l] : 0.0;
+  if (l < PM) s_s[l] = make_double2(0.0, 0.0);
   const double h = box_side(root_size, box_level[b]);
   const double logh = log(h);
   double re = 0.0, im = 0.0;
   for (int e = l2_ptr[b]; e < l2_ptr[b + 1]; ++e) {
-    const int s = l2_src[e];
-    const double2* M = m2l + (size_t)l2_off[e] * P * P;
+    const int s = l2_src[e], o = l2_off[e];
     __syncthreads();
-    if (lane < P) s_a[lane] = mpole[(size_t)s * P + lane];
-    __syncthreads();
-    if (lane < P) {
-      for (int k = 0; k < P; ++k) {
-        const double2 m = M[(size_t)k * P + lane];
-        const double2 a = s_a[k];
-        re += m.x * a.x - m.y * a.y;
-        im += m.x * a.y + m.y * a.x;
-      }
-      if (lane == 0) re += s_a[0].x * logh;
+    if (l < P) {
+      const double2 a = mpole[(size_t)s * P + l];
+      s_s[l] = (l == 0) ? a : cmul(tneg[o * P + l], a);
     }
-  }
-  const double h2 = h * h;
-  for (int e = l4_ptr[b]; e < l4_ptr[b + 1]; ++e) {
-    const int src = l4_src[e];
-    const int cfg = l4_cfg[e];
     __syncthreads();
-    for (int j = lane; j < n; j += 64) s_f[j] = fe[(size_t)src * n + j];
-    __syncthreads();
-    if (lane < P) {
-      double r2 = 0.0, i2 = 0.0;
-      const double2* Q = p2l + (size_t)cfg * n * P;
-      for (int j = 0; j < n; ++j) {
-        const double2 q = Q[(size_t)j * P + lane];
-        r2 += q.x * s_f[j];
-        i2 += q.y * s_f[j];
+    if (l < P) {
+      double ur = 0.0, ui = 0.0;
+#pragma unroll
+      for (int k = 1; k < PM; ++k) {
+        ur += prow[k] * s_s[k].x;
+        ui += prow[k] * s_s[k].y;
       }
-      re += h2 * r2;
-      im += h2 * i2;
-      if (lane == 0) {
-        double ch = 0.0;
-        for (int j = 0; j < n; ++j) ch += w2[j] * s_f[j];
-        re += h2 * logh * p2l_area[cfg] * ch;
+      const double2 tp = tpow[o * P + l];
+      re += tp.x * ur - tp.y * ui;
+      im += tp.x * ui + tp.y * ur;
+      const double a0 = s_s[0].x;
+      if (l == 0) {
+        re += a0 * (logd[o] + logh);
+      } else {
+        re -= a0 * tp.x / l;
+        im -= a0 * tp.y / l;
       }
     }
   }
-  if (lane < P) local[(size_t)b * P + lane] = make_double2(re, im);
+  if (l < P) {
+    const double h2 = h * h;
+    for (int e = l4_ptr[b]; e < l4_ptr[b + 1]; ++e) {
+      const double* y = p2l_y + (size_t)l4_slot[e] * p2l_rows + 2 * l;
+      re += h2 * y[0];
+      im += h2 * y[1];
+      if (l == 0) re += logh * mpole[(size_t)leaf_box[l4_src[e]] * P].x;
+    }
+    local[(size_t)b * P + l] = make_double2(re, im);
+  }
 }
 
-// L2L into the boxes of one level (l2l stored [q][k][l])
+// Downward pass into the boxes of one level:
+//   c_l += (2w)^-l sum_{k>=l} C(k,l) w^k b_k(parent)
+template <int PM>
 __global__ void __launch_bounds__(64) k_l2l(int P, int first, const int* __restrict__ box_parent,
-                                            const int* __restrict__ box_child0, const double2* __restrict__ l2l,
+                                            const int* __restrict__ box_child0, const double* __restrict__ pas,
+                                            const double2* __restrict__ sin, const double2* __restrict__ sout,
                                             double2* __restrict__ local) {
-  __shared__ double2 s_b[64];
+  __shared__ double2 s_s[PM];
   const int b = first + blockIdx.x;
-  const int lane = threadIdx.x;
+  const int l = threadIdx.x;
   const int par = box_parent[b];
   const int q = b - box_child0[par];
-  if (lane < P) s_b[lane] = local[(size_t)par * P + lane];
+  double prow[PM];
+#pragma unroll
+  for (int k = 0; k < PM; ++k) prow[k] = (k < P && l < P) ? pas[(size_t)k * P + l] : 0.0;
+  double2 v = make_double2(0.0, 0.0);
+  if (l < P) v = cmul(sin[q * P + l], local[(size_t)par * P + l]);
+  if (l < PM) s_s[l] = v;
   __syncthreads();
-  if (lane >= P) return;
-  double re = 0.0, im = 0.0;
-  for (int k = lane; k < P; ++k) {
-    const double2 m = l2l[((size_t)q * P + k) * P + lane];
-    const double2 a = s_b[k];
-    re += m.x * a.x - m.y * a.y;
-    im += m.x * a.y + m.y * a.x;
+  if (l >= P) return;
+  double ur = 0.0, ui = 0.0;
+#pragma unroll
+  for (int k = 0; k < PM; ++k) {
+    ur += prow[k] * s_s[k].x;
+    ui += prow[k] * s_s[k].y;
   }
-  double2 o = local[(size_t)b * P + lane];
-  o.x += re;
-  o.y += im;
-  local[(size_t)b * P + lane] = o;
+  const double2 g = cmul(sout[q * P + l], make_double2(ur, ui));
+  double2 o = local[(size_t)b * P + l];
+  o.x += g.x;
+  o.y += g.y;
+  local[(size_t)b * P + l] = o;
 }
 
 // -------------------------------------------------------------------------
-// Near field: V_i = (1/2pi) sum_{S in list 1} [ h^2 (T_c f_S)_i + log(h) a_0(S) ]
-__global__ void __launch_bounds__(256) k_near(int n, int P, double root_size, const int* __restrict__ leaf_box,
-                                              const int* __restrict__ box_level, const int* __restrict__ l1_ptr,
-                                              const int* __restrict__ l1_src, const int* __restrict__ l1_cfg,
-                                              const double* __restrict__ near, const double2* __restrict__ mpole,
-                                              const double* __restrict__ fe, double* __restrict__ V) {
-  __shared__ double s_f[kMaxK * kMaxK];
-  const int leaf = blockIdx.x;
-  const int i = threadIdx.x;
-  const int b = leaf_box[leaf];
-  const double h = box_side(root_size, box_level[b]);
-  const double logh = log(h);
-  double acc = 0.0, lg = 0.0;
-  for (int e = l1_ptr[leaf]; e < l1_ptr[leaf + 1]; ++e) {
-    const int s = l1_src[e];
-    const int c = l1_cfg[e];
-    __syncthreads();
-    if (i < n) s_f[i] = fe[(size_t)s * n + i];
-    __syncthreads();
-    if (i < n) {
-      const double* T = near + (size_t)c * n * n;
-      double a = 0.0;
-      for (int j = 0; j < n; ++j) a += T[(size_t)j * n + i] * s_f[j];
-      acc += a;
-      lg += mpole[(size_t)leaf_box[s] * P].x;
-    }
-  }
-  if (i < n) V[(size_t)leaf * n + i] = kInv2Pi * (h * h * acc + logh * lg);
-}
-
-// Near field as batched GEMMs on the FP64 matrix cores.  List-1 pairs are
-// grouped by table configuration c; a work-group takes a tile of <= 32 pairs
-// of one configuration and computes Y[pair] = T_c f_src for all n rows:
-// C (n x 32) = T_c (n x n) * F (n x 32).  F is staged in LDS; each wave owns
-// n/4 rows, reads the table's A fragments from L2 (the configuration's table
-// is shared by every tile of it) and keeps RT x 2 16x16 accumulators.
-// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and the
-// outputs D[(l/16) + 4r][l%16], r = 0..3 (lane layout checked on gfx950).
-typedef double vfx_d4 __attribute__((ext_vector_type(4)));
-
-template <int N>
-__global__ void __launch_bounds__(256) k_near_mfma(const int* __restrict__ nt_cfg, const int* __restrict__ nt_first,
-                                                   const int* __restrict__ nt_count, const int* __restrict__ np_src,
-                                                   const double* __restrict__ near, const double* __restrict__ fe,
-                                                   double* __restrict__ Y) {
-  constexpr int RT = N / 64;      // row tiles of 16 per wave (4 waves x RT x 16 = N rows)
-  constexpr int LD = N + 1;       // padded LDS row (bank spread for the B fragments)
-  __shared__ double sF[32 * LD];
-  // XCD-aware order: consecutive tiles (same configuration, same table) go to
-  // the same XCD, whose L2 then serves the table to all of them
-  const int nb = gridDim.x, b = blockIdx.x;
-  const int q = nb >> 3, rr = nb & 7, x = b & 7, i8 = b >> 3;
+// Batched table GEMMs on the FP64 matrix cores (near field and P2L).
+// Entries are grouped by table configuration c; a work-group takes a tile of
+// <= 32 entries of one configuration and computes Y[e] = A_c x[src(e)] for
+// all R = 16*MT rows:  C (R x 32) = A_c (R x KD) * X (KD x 32).
+// A is stored [c][k][row] (rows fastest), X is staged in LDS, each wave owns
+// row tiles w, w+4, ... and reads its A fragments from L2 (every tile of a
+// configuration shares the table).  v_mfma_f64_16x16x4f64: lane l holds
+// A[l%16][l/16], B[l/16][l%16] and the outputs D[(l/16) + 4r][l%16],
+// r = 0..3 (lane layout checked on gfx950).
+template <int KD>
+__global__ void __launch_bounds__(256) k_tile_gemm(int MT, const int* __restrict__ t_cfg,
+                                                   const int* __restrict__ t_first, const int* __restrict__ t_count,
+                                                   const int* __restrict__ src, const double* __restrict__ A,
+                                                   const double* __restrict__ X, double* __restrict__ Y) {
+  constexpr int LD = KD + 1;  // padded LDS row (bank spread for the B fragments)
+  __shared__ double sX[32 * LD];
+  // XCD-aware order: consecutive tiles (same configuration, same table) go
+  // to the same XCD, whose L2 then serves the table to all of them
+  const int nb = gridDim.x, bb = blockIdx.x;
+  const int q = nb >> 3, rr = nb & 7, x = bb & 7, i8 = bb >> 3;
   const int tile = x * q + min(x, rr) + i8;
-  const int c = nt_cfg[tile], p0 = nt_first[tile], np = nt_count[tile];
+  const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
+  const int R = 16 * MT;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < 32 * N; e += 256) {
-    const int j = e / N, k = e - j * N;
-    sF[j * LD + k] = (j < np) ? fe[(size_t)np_src[p0 + j] * N + k] : 0.0;
+  for (int e = tid; e < 32 * KD; e += 256) {
+    const int j = e / KD, k = e - j * KD;
+    sX[j * LD + k] = (j < np) ? X[(size_t)src[p0 + j] * KD + k] : 0.0;
   }
   __syncthreads();
-  vfx_d4 acc[RT][2];
+  vfx_d4 acc[4][2];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
+  for (int r = 0; r < 4; ++r) {
     acc[r][0] = vfx_d4{0, 0, 0, 0};
     acc[r][1] = vfx_d4{0, 0, 0, 0};
   }
-  const double* Tc = near + (size_t)c * N * N;
+  const double* Ac = A + (size_t)c * KD * R;
   const int li = lane & 15, lk = lane >> 4;
-  const int row0 = w * (N / 4) + li;
-  double a_cur[RT], a_nxt[RT];
+  double a_cur[4], a_nxt[4];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) a_cur[r] = Tc[(size_t)lk * N + row0 + 16 * r];
-  for (int ks = 0; ks < N / 4; ++ks) {
+  for (int r = 0; r < 4; ++r) {
+    const int rt = w + 4 * r;
+    a_cur[r] = (rt < MT) ? Ac[(size_t)lk * R + 16 * rt + li] : 0.0;
+    a_nxt[r] = 0.0;
+  }
+  for (int ks = 0; ks < KD / 4; ++ks) {
     const int k = 4 * ks + lk;
-    if (ks + 1 < N / 4) {
+    if (ks + 1 < KD / 4) {
 #pragma unroll
-      for (int r = 0; r < RT; ++r) a_nxt[r] = Tc[(size_t)(k + 4) * N + row0 + 16 * r];
+      for (int r = 0; r < 4; ++r) {
+        const int rt = w + 4 * r;
+        if (rt < MT) a_nxt[r] = Ac[(size_t)(k + 4) * R + 16 * rt + li];
+      }
     }
-    const double b0 = sF[li * LD + k];
-    const double b1 = sF[(16 + li) * LD + k];
+    const double b0 = sX[li * LD + k];
+    const double b1 = sX[(16 + li) * LD + k];
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      acc[r][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b0, acc[r][0], 0, 0, 0);
-      acc[r][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b1, acc[r][1], 0, 0, 0);
+    for (int r = 0; r < 4; ++r) {
+      if (w + 4 * r < MT) {
+        acc[r][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b0, acc[r][0], 0, 0, 0);
+        acc[r][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b1, acc[r][1], 0, 0, 0);
+      }
     }
 #pragma unroll
-    for (int r = 0; r < RT; ++r) a_cur[r] = a_nxt[r];
+    for (int r = 0; r < 4; ++r) a_cur[r] = a_nxt[r];
   }
 #pragma unroll
-  for (int r = 0; r < RT; ++r)
+  for (int r = 0; r < 4; ++r) {
+    const int rt = w + 4 * r;
+    if (rt >= MT) continue;
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
       const int pr = 16 * ct + li;
       if (pr < np) {
-        double* y = Y + (size_t)(p0 + pr) * N + w * (N / 4) + 16 * r + lk;
+        double* y = Y + (size_t)(p0 + pr) * R + 16 * rt + lk;
 #pragma unroll
         for (int e = 0; e < 4; ++e) y[4 * e] = acc[r][ct][e];
       }
     }
+  }
 }
 
-// Far field: L2P of the local expansion and M2P of list 3 (l2p stored [l][i])
+// Far field: L2P of the local expansion and M2P of list 3 (l2p stored [l][i]).
 // With Y given, the near field is also finished here: the per-pair partials
 // of the leaf's list-1 entries are summed in list order (deterministic) and
 // the log(h) a_0 term added; V is then written, else it is accumulated.
@@ -457,9 +483,6 @@ __global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, con
 }
 
 // -------------------------------------------------------------------------
-// The MFMA near-field path needs n a multiple of 64 (K = 8, 16).
-static bool use_mfma_near(const Tables& T) { return T.n == 64 || T.n == 256; }
-
 template <typename T>
 static int upload(T** dst, const T* src, size_t count, std::string& err) {
   *dst = nullptr;
@@ -475,6 +498,12 @@ static int upload(T** dst, const T* src, size_t count, std::string& err) {
     if (rc_) return rc_;                                                   \
   } while (0)
 
+static std::vector<double2> as_complex(const std::vector<double>& src) {
+  std::vector<double2> o(src.size() / 2);
+  for (size_t i = 0; i < o.size(); ++i) o[i] = make_double2(src[2 * i], src[2 * i + 1]);
+  return o;
+}
+
 int upload_tables(Context* c, std::string& err) {
   const Tables& T = c->T;
   DeviceTables& D = c->D;
@@ -485,8 +514,11 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.AbarT, T.AbarT);
   UP(D.cbar, T.cbar);
   UP(D.near, T.near);
-  UP(D.near_s2, T.near_s2);
-  UP(D.p2l_area, T.p2l_area);
+  UP(D.p2l_gemm, T.p2l_gemm);
+  UP(D.pas_m2l, T.pas_m2l);
+  UP(D.pas_m2m, T.pas_m2m);
+  UP(D.pas_l2l, T.pas_l2l);
+  UP(D.m2l_logd, T.m2l_logd);
   std::vector<double2> v;
   // p2m [k][j] -> [j][k]
   v.assign((size_t)n * P, make_double2(0, 0));
@@ -500,26 +532,18 @@ int upload_tables(Context* c, std::string& err) {
     for (int l = 0; l < P; ++l)
       v[(size_t)l * n + i] = make_double2(T.l2p[2 * ((size_t)i * P + l)], T.l2p[2 * ((size_t)i * P + l) + 1]);
   UP(D.l2p, v);
-  auto cplx_copy = [&](const std::vector<double>& src) {
-    std::vector<double2> o(src.size() / 2);
-    for (size_t i = 0; i < o.size(); ++i) o[i] = make_double2(src[2 * i], src[2 * i + 1]);
-    return o;
-  };
-  v = cplx_copy(T.m2m);
-  UP(D.m2m, v);
-  v = cplx_copy(T.l2l);
-  UP(D.l2l, v);
-  v = cplx_copy(T.m2l);
-  UP(D.m2l, v);
-  // p2l [c][l][j] -> [c][j][l]
-  v.assign((size_t)kP2LSlots * n * P, make_double2(0, 0));
-  for (int s = 0; s < kP2LSlots; ++s)
-    for (int l = 0; l < P; ++l)
-      for (int j = 0; j < n; ++j) {
-        const size_t src = 2 * (((size_t)s * P + l) * n + j);
-        v[((size_t)s * n + j) * P + l] = make_double2(T.p2l[src], T.p2l[src + 1]);
-      }
-  UP(D.p2l, v);
+  v = as_complex(T.m2l_tpow);
+  UP(D.m2l_tpow, v);
+  v = as_complex(T.m2l_tneg);
+  UP(D.m2l_tneg, v);
+  v = as_complex(T.m2m_in);
+  UP(D.m2m_in, v);
+  v = as_complex(T.m2m_out);
+  UP(D.m2m_out, v);
+  v = as_complex(T.l2l_in);
+  UP(D.l2l_in, v);
+  v = as_complex(T.l2l_out);
+  UP(D.l2l_out, v);
   VFX_HIP(hipGetDevice(&D.device));
   D.ready = true;
   return VFX_OK;
@@ -527,8 +551,10 @@ int upload_tables(Context* c, std::string& err) {
 
 void free_tables_device(Context* c) {
   DeviceTables& D = c->D;
-  void* ptrs[] = {D.t, D.tbar, D.w2, D.AbarT, D.cbar, D.near, D.near_s2, D.p2m, D.l2p, D.m2m, D.l2l, D.m2l, D.p2l,
-                  D.p2l_area};
+  void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,
+                  D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
+                  D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg,
+                  D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   D = DeviceTables();
@@ -537,7 +563,8 @@ void free_tables_device(Context* c) {
 int upload_plan(Plan* p, std::string& err) {
   const HostPlan& H = p->H;
   DevicePlan& D = p->D;
-  const int P = p->ctx->T.p + 1;
+  const Tables& T = p->ctx->T;
+  const int P = T.p + 1;
   UP(D.box_level, H.box_level);
   UP(D.box_child0, H.box_child0);
   UP(D.box_leaf, H.box_leaf);
@@ -562,8 +589,13 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.nt_cfg, H.nt_cfg);
   UP(D.nt_first, H.nt_first);
   UP(D.nt_count, H.nt_count);
-  if (use_mfma_near(p->ctx->T) && !H.np_src.empty())
-    VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * p->ctx->T.n));
+  UP(D.p4_src, H.p4_src);
+  UP(D.l4_slot, H.l4_slot);
+  UP(D.t4_cfg, H.t4_cfg);
+  UP(D.t4_first, H.t4_first);
+  UP(D.t4_count, H.t4_count);
+  if (!H.np_src.empty()) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n));
+  if (!H.p4_src.empty()) VFX_HIP(hipMalloc((void**)&D.p2l_y, sizeof(double) * H.p4_src.size() * T.p2l_rows));
   UP(D.cut_leaf, H.cut_leaf);
   UP(D.ext_ptr, H.ext_ptr);
   UP(D.ext_tgt, H.ext_tgt);
@@ -574,17 +606,21 @@ int upload_plan(Plan* p, std::string& err) {
   VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P));
   VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P));
   VFX_HIP(hipMemset(D.local, 0, sizeof(double2) * (size_t)H.B * P));
+  VFX_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  VFX_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
+  VFX_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
   D.ready = true;
   return VFX_OK;
 }
 
 void free_plan_device(Plan* p) {
   DevicePlan& D = p->D;
-  void* ptrs[] = {D.box_level, D.box_child0, D.box_leaf, D.box_parent, D.box_cx, D.box_cy, D.leaf_box, D.kind,
-                  D.l1_ptr, D.l1_src, D.l1_cfg, D.l2_ptr, D.l2_src, D.l2_off, D.l3_ptr, D.l3_src,
-                  D.l4_ptr, D.l4_src, D.l4_cfg, D.np_src, D.l1_slot, D.nt_cfg, D.nt_first, D.nt_count,
-                  D.near_y, D.cut_leaf, D.ext_ptr, D.ext_tgt, D.pinv_ptr, D.pinv_idx,
-                  D.pinv_val, D.sbar_given, D.mpole, D.local};
+  void* ptrs[] = {D.box_level, D.box_child0, D.box_leaf, D.box_parent, D.box_cx,   D.box_cy,   D.leaf_box,
+                  D.kind,      D.l1_ptr,     D.l1_src,   D.l1_cfg,     D.l2_ptr,   D.l2_src,   D.l2_off,
+                  D.l3_ptr,    D.l3_src,     D.l4_ptr,   D.l4_src,     D.l4_cfg,   D.np_src,   D.l1_slot,
+                  D.nt_cfg,    D.nt_first,   D.nt_count, D.near_y,     D.p4_src,   D.l4_slot,  D.t4_cfg,
+                  D.t4_first,  D.t4_count,   D.p2l_y,    D.cut_leaf,   D.ext_ptr,  D.ext_tgt,  D.pinv_ptr,
+                  D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -592,6 +628,29 @@ void free_plan_device(Plan* p) {
     if (e) (void)hipEventDestroy(e);
   p->ev.clear();
   p->n_timed = 0;
+  if (p->side) (void)hipStreamSynchronize(p->side);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->join_ev) (void)hipEventDestroy(p->join_ev);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  p->fork_ev = p->join_ev = nullptr;
+  p->side = nullptr;
+}
+
+template <int KD>
+static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
+                        const double* A, const double* X, double* Y, hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_gemm<KD>, dim3(ntiles), dim3(256), 0, s, MT, cfg, first, count, src, A, X, Y);
+}
+
+static void gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
+                 const double* A, const double* X, double* Y, hipStream_t s) {
+  if (ntiles <= 0) return;
+  switch (n) {
+    case 16: launch_gemm<16>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
+    case 64: launch_gemm<64>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
+    case 144: launch_gemm<144>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
+    default: launch_gemm<256>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
+  }
 }
 
 int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V, hipStream_t s,
@@ -610,19 +669,24 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   const DeviceTables& DT = c->D;
   const DevicePlan& D = p->D;
   const int n = T.n, P = T.p + 1, L = H.L;
+  const bool big = P > 32;
   constexpr int kMaxTimed = 4096;
+  constexpr int NE = Plan::kEvents;
   const bool timed = p->timing && p->n_timed < kMaxTimed;
-  const size_t ev0 = (size_t)p->n_timed * 7;
-  if (timed && p->ev.size() < ev0 + 7) {
-    for (int k = 0; k < 7; ++k) {
+  const size_t ev0 = (size_t)p->n_timed * NE;
+  if (timed && p->ev.size() < ev0 + NE) {
+    for (int k = 0; k < NE; ++k) {
       hipEvent_t e;
       VFX_HIP(hipEventCreate(&e));
       p->ev.push_back(e);
     }
   }
-  auto mark = [&](int k) -> int {
+  // events on the caller's stream: 0 start, 1 after the extension, 2 after
+  // P2M+M2M, 3 after M2L+P2L, 4 after L2L, 7 after the join, 8 end; on the
+  // side stream: 5 and 6 around the near-field GEMM
+  auto mark = [&](int k, hipStream_t st) -> int {
     if (timed) {
-      hipError_t e = hipEventRecord(p->ev[ev0 + k], s);
+      hipError_t e = hipEventRecord(p->ev[ev0 + k], st);
       if (e != hipSuccess) {
         err = std::string("hipEventRecord: ") + hipGetErrorString(e);
         return VFX_EHIP;
@@ -630,12 +694,12 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
     }
     return VFX_OK;
   };
-#define MARK(k)             \
-  do {                      \
-    int rc_ = mark(k);      \
-    if (rc_) return rc_;    \
+#define MARK(k, st)          \
+  do {                       \
+    int rc_ = mark(k, st);   \
+    if (rc_) return rc_;     \
   } while (0)
-  MARK(0);
+  MARK(0, s);
   {
     const long total = (long)L * n;
     int blocks = (int)std::min<long>((total + 255) / 256, 65536);
@@ -646,50 +710,65 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
                        D.cut_leaf, D.pinv_ptr, D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt,
                        DT.t, DT.AbarT, DT.cbar, D.leaf_box, D.box_cx, D.box_cy, D.box_level, f_cut, fe);
   VFX_HIP(hipGetLastError());
-  MARK(1);
+  MARK(1, s);
+  // fork: near field on the side stream, concurrent with the upward pass,
+  // M2L/P2L and the downward pass on the caller's stream
+  VFX_HIP(hipEventRecord(p->fork_ev, s));
+  VFX_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
+  MARK(5, p->side);
+  gemm(n, (int)H.nt_cfg.size(), n / 16, D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y,
+       p->side);
+  VFX_HIP(hipGetLastError());
+  MARK(6, p->side);
+  VFX_HIP(hipEventRecord(p->join_ev, p->side));
   hipLaunchKernelGGL(k_p2m, dim3(L), dim3(64), 0, s, n, P, T.root_size, D.leaf_box, D.box_level, DT.p2m, fe,
                      D.mpole);
   for (int l = H.nlev - 2; l >= 2; --l) {
     const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
-    if (cnt > 0) hipLaunchKernelGGL(k_m2m, dim3(cnt), dim3(64), 0, s, P, first, D.box_child0, DT.m2m, D.mpole);
+    if (cnt <= 0) continue;
+    if (big)
+      hipLaunchKernelGGL(k_m2m<64>, dim3(cnt), dim3(64), 0, s, P, first, D.box_child0, DT.pas_m2m, DT.m2m_in,
+                         DT.m2m_out, D.mpole);
+    else
+      hipLaunchKernelGGL(k_m2m<32>, dim3(cnt), dim3(64), 0, s, P, first, D.box_child0, DT.pas_m2m, DT.m2m_in,
+                         DT.m2m_out, D.mpole);
   }
   VFX_HIP(hipGetLastError());
-  MARK(2);
+  MARK(2, s);
   if (H.nlev > 2) {
+    gemm(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src, DT.p2l_gemm, fe,
+         D.p2l_y, s);
     const int first = H.level_start[2], cnt = H.B - first;
-    hipLaunchKernelGGL(k_m2l, dim3(cnt), dim3(64), 0, s, n, P, first, T.root_size, D.box_level, D.l2_ptr,
-                       D.l2_src, D.l2_off, D.l4_ptr, D.l4_src, D.l4_cfg, DT.m2l, DT.p2l, DT.w2, DT.p2l_area,
-                       D.mpole, fe, D.local);
+    if (big)
+      hipLaunchKernelGGL(k_m2l<64>, dim3(cnt), dim3(64), 0, s, P, first, T.root_size, D.box_level, D.l2_ptr,
+                         D.l2_src, D.l2_off, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows, DT.pas_m2l,
+                         DT.m2l_tpow, DT.m2l_tneg, DT.m2l_logd, D.mpole, D.p2l_y, D.local);
+    else
+      hipLaunchKernelGGL(k_m2l<32>, dim3(cnt), dim3(64), 0, s, P, first, T.root_size, D.box_level, D.l2_ptr,
+                         D.l2_src, D.l2_off, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows, DT.pas_m2l,
+                         DT.m2l_tpow, DT.m2l_tneg, DT.m2l_logd, D.mpole, D.p2l_y, D.local);
   }
   VFX_HIP(hipGetLastError());
-  MARK(3);
+  MARK(3, s);
   for (int l = 3; l < H.nlev; ++l) {
     const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
-    if (cnt > 0)
-      hipLaunchKernelGGL(k_l2l, dim3(cnt), dim3(64), 0, s, P, first, D.box_parent, D.box_child0, DT.l2l, D.local);
-  }
-  VFX_HIP(hipGetLastError());
-  MARK(4);
-  const bool mfma = D.near_y != nullptr;
-  if (mfma) {
-    const int ntiles = (int)H.nt_cfg.size();
-    if (n == 256)
-      hipLaunchKernelGGL(k_near_mfma<256>, dim3(ntiles), dim3(256), 0, s, D.nt_cfg, D.nt_first, D.nt_count,
-                         D.np_src, DT.near, fe, D.near_y);
+    if (cnt <= 0) continue;
+    if (big)
+      hipLaunchKernelGGL(k_l2l<64>, dim3(cnt), dim3(64), 0, s, P, first, D.box_parent, D.box_child0, DT.pas_l2l,
+                         DT.l2l_in, DT.l2l_out, D.local);
     else
-      hipLaunchKernelGGL(k_near_mfma<64>, dim3(ntiles), dim3(256), 0, s, D.nt_cfg, D.nt_first, D.nt_count,
-                         D.np_src, DT.near, fe, D.near_y);
-  } else {
-    hipLaunchKernelGGL(k_near, dim3(L), dim3(n < 64 ? 64 : n), 0, s, n, P, T.root_size, D.leaf_box, D.box_level,
-                       D.l1_ptr, D.l1_src, D.l1_cfg, DT.near, D.mpole, fe, V);
+      hipLaunchKernelGGL(k_l2l<32>, dim3(cnt), dim3(64), 0, s, P, first, D.box_parent, D.box_child0, DT.pas_l2l,
+                         DT.l2l_in, DT.l2l_out, D.local);
   }
   VFX_HIP(hipGetLastError());
-  MARK(5);
+  MARK(4, s);
+  VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
+  MARK(7, s);
   hipLaunchKernelGGL(k_far, dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box, D.box_level,
                      D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.l2p, D.local, D.mpole, D.l1_ptr, D.l1_src,
-                     D.l1_slot, mfma ? D.near_y : nullptr, V);
+                     D.l1_slot, D.near_y, V);
   VFX_HIP(hipGetLastError());
-  MARK(6);
+  MARK(8, s);
   if (timed) p->n_timed++;
   return VFX_OK;
 }

@@ -293,6 +293,29 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     H.l4_ptr[b + 1] = H.l4_ptr[b] + n4;
   }
 
+  // ---- list-4 entries grouped by P2L slot --------------------------------
+  {
+    const int N4 = H.l4_ptr[B];
+    std::vector<int> cnt(kP2LSlots + 1, 0);
+    for (int e = 0; e < N4; ++e) cnt[H.l4_cfg[e] + 1]++;
+    for (int c = 0; c < kP2LSlots; ++c) cnt[c + 1] += cnt[c];
+    H.p4_src.assign(N4, 0);
+    H.l4_slot.assign(N4, 0);
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (int b = 0; b < B; ++b)
+      for (int e = H.l4_ptr[b]; e < H.l4_ptr[b + 1]; ++e) {
+        const int s = pos[H.l4_cfg[e]]++;
+        H.p4_src[s] = H.l4_src[e];
+        H.l4_slot[e] = s;
+      }
+    for (int c = 0; c < kP2LSlots; ++c)
+      for (int f = cnt[c]; f < cnt[c + 1]; f += 32) {
+        H.t4_cfg.push_back(c);
+        H.t4_first.push_back(f);
+        H.t4_count.push_back(std::min(32, cnt[c + 1] - f));
+      }
+  }
+
   // ---- extension lists ---------------------------------------------------
   H.owner.assign(L, -1);
   std::vector<int64_t> best(L, -1);

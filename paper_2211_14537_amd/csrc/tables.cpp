@@ -555,6 +555,64 @@ static void build_expansions(Tables& T) {
   }
 }
 
+static void build_pascal(Tables& T) {
+  const int P = T.p + 1, n = T.n;
+  T.pas_m2l.assign((size_t)P * P, 0.0);
+  T.pas_m2m.assign((size_t)P * P, 0.0);
+  T.pas_l2l.assign((size_t)P * P, 0.0);
+  for (int k = 0; k < P; ++k)
+    for (int l = 0; l < P; ++l) {
+      if (k >= 1) T.pas_m2l[(size_t)k * P + l] = binom(k + l - 1, l);
+      if (k >= 1 && k <= l) T.pas_m2m[(size_t)k * P + l] = binom(l - 1, k - 1);
+      if (k >= l) T.pas_l2l[(size_t)k * P + l] = binom(k, l);
+    }
+  T.m2l_tpow.assign((size_t)kM2LSlots * P * 2, 0.0);
+  T.m2l_tneg.assign((size_t)kM2LSlots * P * 2, 0.0);
+  T.m2l_logd.assign(kM2LSlots, 0.0);
+  for (int o = 0; o < kM2LSlots; ++o) {
+    const int dx = o / 7 - 3, dy = o % 7 - 3;
+    if (std::max(std::abs(dx), std::abs(dy)) < 2) continue;
+    const cplx tt = 1.0 / cplx(dx, dy);
+    T.m2l_logd[o] = std::log(std::hypot((double)dx, (double)dy));
+    cplx a = 1.0, b = 1.0;
+    for (int l = 0; l < P; ++l) {
+      put(T.m2l_tpow, (size_t)o * P + l, a);
+      put(T.m2l_tneg, (size_t)o * P + l, b);
+      a *= tt;
+      b *= -tt;
+    }
+  }
+  T.m2m_in.assign((size_t)4 * P * 2, 0.0);
+  T.m2m_out.assign((size_t)4 * P * 2, 0.0);
+  T.l2l_in.assign((size_t)4 * P * 2, 0.0);
+  T.l2l_out.assign((size_t)4 * P * 2, 0.0);
+  for (int qd = 0; qd < 4; ++qd) {
+    const int dx = qd % 2, dy = qd / 2;
+    const cplx w(0.25 * (2 * dx - 1), 0.25 * (2 * dy - 1));
+    const cplx iw2 = 1.0 / (2.0 * w);
+    cplx wk = 1.0, iwk = 1.0;
+    for (int k = 0; k < P; ++k) {
+      put(T.m2m_in, (size_t)qd * P + k, iwk);
+      put(T.m2m_out, (size_t)qd * P + k, wk);
+      put(T.l2l_in, (size_t)qd * P + k, wk);
+      put(T.l2l_out, (size_t)qd * P + k, iwk);
+      wk *= w;
+      iwk *= iw2;
+    }
+  }
+  // P2L as a real GEMM operand
+  T.p2l_rows = 16 * ((2 * P + 15) / 16);
+  const int R = T.p2l_rows;
+  T.p2l_gemm.assign((size_t)kP2LSlots * n * R, 0.0);
+  for (int s = 0; s < kP2LSlots; ++s)
+    for (int l = 0; l < P; ++l)
+      for (int j = 0; j < n; ++j) {
+        const size_t src = 2 * (((size_t)s * P + l) * n + j);
+        T.p2l_gemm[((size_t)s * n + j) * R + 2 * l] = T.p2l[src];
+        T.p2l_gemm[((size_t)s * n + j) * R + 2 * l + 1] = T.p2l[src + 1];
+      }
+}
+
 void build_tables(Tables& T) {
   T.n = T.K * T.K;
   T.nG = (T.deg + 1) * (T.deg + 2) / 2;
@@ -582,6 +640,7 @@ void build_tables(Tables& T) {
   build_expansions(T);
   build_near(T);
   build_p2l(T);
+  build_pascal(T);
 }
 
 }  // namespace vfx

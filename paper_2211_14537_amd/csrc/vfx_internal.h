@@ -49,6 +49,22 @@ struct Tables {
   std::vector<double> m2l;             // 49 x (p+1) x (p+1) complex, [o][k][l]
   std::vector<double> p2l;             // 36 x (p+1) x n complex, [c][l][j]
   std::vector<double> p2l_area;        // 36: source area in units h^2 (0 if unused)
+  // Scaled-Pascal forms of the translations (shared real matrices plus
+  // diagonal complex scalings), used by the device kernels:
+  //   M2L: b_l += t^l sum_{k>=1} C(k+l-1,l) (-t)^k a_k - a_0 t^l/l (l>=1),
+  //        b_0 += a_0 log|d|, t = h/d
+  //   M2M: b_l += w^l [ sum_{1<=k<=l} C(l-1,k-1) (2w)^-k a_k - a_0/l ],
+  //        b_0 += a_0, w = (child - parent centre)/h_parent
+  //   L2L: c_l  = (2w)^-l sum_{k>=l} C(k,l) w^k b_k
+  std::vector<double> pas_m2l, pas_m2m, pas_l2l;  // P x P real, [k][l]
+  std::vector<double> m2l_tpow, m2l_tneg;         // 49 x P complex: t^l, (-t)^k
+  std::vector<double> m2l_logd;                   // 49: log|d/h|
+  std::vector<double> m2m_in, m2m_out;            // 4 x P complex: (2w)^-k, w^l
+  std::vector<double> l2l_in, l2l_out;            // 4 x P complex: w^k, (2w)^-l
+  // P2L tables as real GEMM operands: [slot][j][row], row = 2l (re) or
+  // 2l+1 (im), rows padded to p2l_rows (a multiple of 16)
+  int p2l_rows = 0;
+  std::vector<double> p2l_gemm;
 };
 
 // Host precompute (quadrature.cpp, stencil.cpp)
@@ -69,6 +85,9 @@ struct DeviceTables {
   double *near = nullptr, *near_s2 = nullptr;
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
+  double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
+  double2 *m2l_tpow = nullptr, *m2l_tneg = nullptr, *m2m_in = nullptr, *m2m_out = nullptr, *l2l_in = nullptr,
+          *l2l_out = nullptr;
 };
 
 struct Context {
@@ -93,6 +112,8 @@ struct HostPlan {
   // l1_slot maps each per-target list-1 entry to its pair index
   std::vector<int> np_src, np_tgt, l1_slot;
   std::vector<int> nt_cfg, nt_first, nt_count;  // GEMM tiles of <= 32 pairs
+  // list-4 entries regrouped by P2L slot, the same way
+  std::vector<int> p4_src, l4_slot, t4_cfg, t4_first, t4_count;
   std::vector<int> cut_leaf;                 // ncut
   std::vector<int> owner;                    // L
   std::vector<int> ext_ptr, ext_tgt;         // per cut leaf (targets, itself first)
@@ -115,6 +136,8 @@ struct DevicePlan {
   int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
   int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
+  int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
+  double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
   int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
   uint16_t* pinv_idx = nullptr;
   double* pinv_val = nullptr;
@@ -126,9 +149,14 @@ struct Plan {
   Context* ctx = nullptr;
   HostPlan H;
   DevicePlan D;
-  // per-phase timing: one set of 7 events per timed execute
+  // the near-field GEMM runs on a side stream (default priority), forked
+  // after the extension and joined before the far-field kernel
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // per-phase timing: one set of kEvents events per timed execute
+  static constexpr int kEvents = 9;
   bool timing = false;
-  std::vector<hipEvent_t> ev;   // 7 * capacity
+  std::vector<hipEvent_t> ev;   // kEvents * capacity
   int n_timed = 0;
 };
 
