@@ -334,88 +334,109 @@ __global__ void __launch_bounds__(64) k_l2l(int P, int first, const int* __restr
 }
 
 // -------------------------------------------------------------------------
-// Batched table GEMMs on the FP64 matrix cores (near field and P2L).
-// Entries are grouped by table configuration c; a work-group takes a tile of
-// <= 32 entries of one configuration and computes Y[e] = A_c x[src(e)] for
-// all R = 16*MT rows:  C (R x 32) = A_c (R x KD) * X (KD x 32).
-// A is stored [c][k][row] (rows fastest), X is staged in LDS, each wave owns
-// row tiles w, w+4, ... and reads its A fragments from L2 (every tile of a
-// configuration shares the table).  v_mfma_f64_16x16x4f64: lane l holds
-// A[l%16][l/16], B[l/16][l%16] and the outputs D[(l/16) + 4r][l%16],
-// r = 0..3 (lane layout checked on gfx950).
-template <int KD>
-__global__ void __launch_bounds__(256) k_tile_gemm(int MT, const int* __restrict__ t_cfg,
-                                                   const int* __restrict__ t_first, const int* __restrict__ t_count,
-                                                   const int* __restrict__ src, const double* __restrict__ A,
-                                                   const double* __restrict__ X, double* __restrict__ Y) {
-  constexpr int LD = KD + 1;  // padded LDS row (bank spread for the B fragments)
-  __shared__ double sX[32 * LD];
-  // XCD-aware order: consecutive tiles (same configuration, same table) go
-  // to the same XCD, whose L2 then serves the table to all of them
+// Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M).
+// Entries (pairs) are grouped by table configuration c; a work-group takes a
+// tile of <= 64 entries of one configuration and a block of <= 128 table rows
+// and computes, for every entry e, Y[e][row] = sum_k A_c[k][row] X[src(e)][k]
+// (the table applied to the source leaf's K^2 values).
+//   A: [c][k][row], R = 16*MT rows (rows fastest); X: [src][k]; Y: [e][row].
+// The K dimension is processed in blocks of 16 with both operands staged in
+// double-buffered LDS: the global loads of block kb+1 are in flight while the
+// waves run 4 x mtb MFMAs on block kb.  Wave w owns entries 16w..16w+15 and
+// every row tile of the block.  MFMA operands: A = entry data (16 entries x 4
+// k), B = table (4 k x 16 rows), so each output tile is (entries x rows) and
+// the stores of a 16-lane group are 128 contiguous bytes.
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and the
+// outputs D[(l/16) + 4r][l%16], r = 0..3 (lane layout checked on gfx950).
+// EPI = 1 (P2M): Y is the multipole array; rows < 2P of entry e (a leaf) are
+// scaled by h^2 of that leaf and stored as its (p+1) complex coefficients.
+template <int KD, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(int MT, const int* __restrict__ t_cfg, const int* __restrict__ t_first,
+                                              const int* __restrict__ t_count, const int* __restrict__ src,
+                                              const double* __restrict__ A, const double* __restrict__ X,
+                                              double* __restrict__ Y, int P2, double root_size,
+                                              const int* __restrict__ leaf_box, const int* __restrict__ box_level) {
+  constexpr int KB = 16;
+  constexpr int LDA = 64;   // entries per LDS row
+  constexpr int LDB = 128;  // table rows per LDS row
+  __shared__ double sA[2][KB * LDA];
+  __shared__ double sB[2][KB * LDB];
+  const int nrb = (MT + 7) / 8;  // row blocks of 8 tiles
+  // XCD-aware order: consecutive work items (same configuration, same table)
+  // go to the same XCD, whose L2 then serves the table to all of them
   const int nb = gridDim.x, bb = blockIdx.x;
   const int q = nb >> 3, rr = nb & 7, x = bb & 7, i8 = bb >> 3;
-  const int tile = x * q + min(x, rr) + i8;
+  const int item = x * q + min(x, rr) + i8;
+  const int tile = item / nrb, rb = item - tile * nrb;
   const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
   const int R = 16 * MT;
+  const int mtb = min(8, MT - 8 * rb);
+  const int row0 = 128 * rb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < 32 * KD; e += 256) {
-    const int j = e / KD, k = e - j * KD;
-    sX[j * LD + k] = (j < np) ? X[(size_t)src[p0 + j] * KD + k] : 0.0;
-  }
-  __syncthreads();
-  vfx_d4 acc[4][2];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    acc[r][0] = vfx_d4{0, 0, 0, 0};
-    acc[r][1] = vfx_d4{0, 0, 0, 0};
-  }
-  const double* Ac = A + (size_t)c * KD * R;
   const int li = lane & 15, lk = lane >> 4;
-  double a_cur[4], a_nxt[4];
+  const double* Ac = A + (size_t)c * KD * R;
+  // global -> register staging of one K block
+  const int aj = tid & 63, ak = (tid >> 6) * 4;  // entry data: entry aj, k = ak..ak+3
+  const int bk = tid >> 4, br = (tid & 15) * 8;  // table: k = bk, rows br..br+7
+  const bool a_ok = aj < np;
+  const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
+  double ra[4], rb8[8];
+  auto gload = [&](int kb) {
+    const int k0 = kb * KB;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int rt = w + 4 * r;
-    a_cur[r] = (rt < MT) ? Ac[(size_t)lk * R + 16 * rt + li] : 0.0;
-    a_nxt[r] = 0.0;
-  }
-  for (int ks = 0; ks < KD / 4; ++ks) {
-    const int k = 4 * ks + lk;
-    if (ks + 1 < KD / 4) {
+    for (int e = 0; e < 4; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
+    const bool b_ok = br < 16 * mtb;
+    const double* ar = Ac + (size_t)(k0 + bk) * R + row0 + br;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rt = w + 4 * r;
-        if (rt < MT) a_nxt[r] = Ac[(size_t)(k + 4) * R + 16 * rt + li];
-      }
+    for (int e = 0; e < 8; ++e) rb8[e] = b_ok ? ar[e] : 0.0;
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sA[buf][(ak + e) * LDA + aj] = ra[e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sB[buf][bk * LDB + br + e] = rb8[e];
+  };
+  vfx_d4 acc[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
+  constexpr int NKB = KD / KB;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kb = 0; kb < NKB; ++kb) {
+    const int buf = kb & 1;
+    if (kb + 1 < NKB) gload(kb + 1);
+#pragma unroll
+    for (int ks = 0; ks < KB / 4; ++ks) {
+      const int k = 4 * ks + lk;
+      const double a = sA[buf][k * LDA + 16 * w + li];
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (r < mtb) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[buf][k * LDB + 16 * r + li], acc[r], 0, 0, 0);
     }
-    const double b0 = sX[li * LD + k];
-    const double b1 = sX[(16 + li) * LD + k];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (w + 4 * r < MT) {
-        acc[r][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b0, acc[r][0], 0, 0, 0);
-        acc[r][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[r], b1, acc[r][1], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) a_cur[r] = a_nxt[r];
+    if (kb + 1 < NKB) lstore(buf ^ 1);
+    __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int rt = w + 4 * r;
-    if (rt >= MT) continue;
+  for (int r = 0; r < 8; ++r) {
+    if (r >= mtb) continue;
+    const int row = row0 + 16 * r + li;
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const int pr = 16 * ct + li;
-      if (pr < np) {
-        double* y = Y + (size_t)(p0 + pr) * R + 16 * rt + lk;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) y[4 * e] = acc[r][ct][e];
+    for (int e = 0; e < 4; ++e) {
+      const int ent = 16 * w + lk + 4 * e;
+      if (ent >= np) continue;
+      if (EPI == 0) {
+        Y[(size_t)(p0 + ent) * R + row] = acc[r][e];
+      } else if (row < P2) {
+        const int leaf = src[p0 + ent];
+        const int b = leaf_box[leaf];
+        const double h = box_side(root_size, box_level[b]);
+        Y[(size_t)b * P2 + row] = h * h * acc[r][e];
       }
     }
   }
 }
 
-// Far field: L2P of the local expansion and M2P of list 3 (l2p stored [l][i]).
 // With Y given, the near field is also finished here: the per-pair partials
 // of the leaf's list-1 entries are summed in list order (deterministic) and
 // the log(h) a_0 term added; V is then written, else it is accumulated.
@@ -515,6 +536,7 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.cbar, T.cbar);
   UP(D.near, T.near);
   UP(D.p2l_gemm, T.p2l_gemm);
+  UP(D.p2m_gemm, T.p2m_gemm);
   UP(D.pas_m2l, T.pas_m2l);
   UP(D.pas_m2m, T.pas_m2m);
   UP(D.pas_l2l, T.pas_l2l);
@@ -553,7 +575,7 @@ void free_tables_device(Context* c) {
   DeviceTables& D = c->D;
   void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
-                  D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg,
+                  D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -594,6 +616,10 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.t4_cfg, H.t4_cfg);
   UP(D.t4_first, H.t4_first);
   UP(D.t4_count, H.t4_count);
+  UP(D.t0_cfg, H.t0_cfg);
+  UP(D.t0_first, H.t0_first);
+  UP(D.t0_count, H.t0_count);
+  UP(D.leaf_ids, H.leaf_ids);
   if (!H.np_src.empty()) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n));
   if (!H.p4_src.empty()) VFX_HIP(hipMalloc((void**)&D.p2l_y, sizeof(double) * H.p4_src.size() * T.p2l_rows));
   UP(D.cut_leaf, H.cut_leaf);
@@ -620,7 +646,8 @@ void free_plan_device(Plan* p) {
                   D.l3_ptr,    D.l3_src,     D.l4_ptr,   D.l4_src,     D.l4_cfg,   D.np_src,   D.l1_slot,
                   D.nt_cfg,    D.nt_first,   D.nt_count, D.near_y,     D.p4_src,   D.l4_slot,  D.t4_cfg,
                   D.t4_first,  D.t4_count,   D.p2l_y,    D.cut_leaf,   D.ext_ptr,  D.ext_tgt,  D.pinv_ptr,
-                  D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local};
+                  D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local,    D.t0_cfg,   D.t0_first,
+                  D.t0_count,  D.leaf_ids};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -636,20 +663,26 @@ void free_plan_device(Plan* p) {
   p->side = nullptr;
 }
 
-template <int KD>
-static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
-                        const double* A, const double* X, double* Y, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_gemm<KD>, dim3(ntiles), dim3(256), 0, s, MT, cfg, first, count, src, A, X, Y);
+template <int KD, int EPI>
+static void launch_gemm(int items, int MT, const int* cfg, const int* first, const int* count, const int* src,
+                        const double* A, const double* X, double* Y, int P2, double root, const int* leaf_box,
+                        const int* box_level, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm<KD, EPI>), dim3(items), dim3(256), 0, s, MT, cfg, first, count, src, A, X, Y, P2, root,
+                     leaf_box, box_level);
 }
 
+// ntiles tiles of <= 64 entries; each is split into ceil(MT/8) row blocks
+template <int EPI>
 static void gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
-                 const double* A, const double* X, double* Y, hipStream_t s) {
+                 const double* A, const double* X, double* Y, hipStream_t s, int P2 = 0, double root = 0,
+                 const int* leaf_box = nullptr, const int* box_level = nullptr) {
   if (ntiles <= 0) return;
+  const int items = ntiles * ((MT + 7) / 8);
   switch (n) {
-    case 16: launch_gemm<16>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
-    case 64: launch_gemm<64>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
-    case 144: launch_gemm<144>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
-    default: launch_gemm<256>(ntiles, MT, cfg, first, count, src, A, X, Y, s); break;
+    case 16: launch_gemm<16, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
+    case 64: launch_gemm<64, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
+    case 144: launch_gemm<144, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
+    default: launch_gemm<256, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
   }
 }
 
@@ -716,13 +749,13 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipEventRecord(p->fork_ev, s));
   VFX_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
   MARK(5, p->side);
-  gemm(n, (int)H.nt_cfg.size(), n / 16, D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y,
-       p->side);
+  gemm<0>(n, (int)H.nt_cfg.size(), n / 16, D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y,
+          p->side);
   VFX_HIP(hipGetLastError());
   MARK(6, p->side);
   VFX_HIP(hipEventRecord(p->join_ev, p->side));
-  hipLaunchKernelGGL(k_p2m, dim3(L), dim3(64), 0, s, n, P, T.root_size, D.leaf_box, D.box_level, DT.p2m, fe,
-                     D.mpole);
+  gemm<1>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids, DT.p2m_gemm,
+          fe, (double*)D.mpole, s, 2 * P, T.root_size, D.leaf_box, D.box_level);
   for (int l = H.nlev - 2; l >= 2; --l) {
     const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
     if (cnt <= 0) continue;
@@ -736,8 +769,8 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipGetLastError());
   MARK(2, s);
   if (H.nlev > 2) {
-    gemm(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src, DT.p2l_gemm, fe,
-         D.p2l_y, s);
+    gemm<0>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src, DT.p2l_gemm,
+            fe, D.p2l_y, s);
     const int first = H.level_start[2], cnt = H.B - first;
     if (big)
       hipLaunchKernelGGL(k_m2l<64>, dim3(cnt), dim3(64), 0, s, P, first, T.root_size, D.box_level, D.l2_ptr,

@@ -251,7 +251,7 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         H.np_tgt[s] = leaf;
         H.l1_slot[e] = s;
       }
-    constexpr int kTile = 32;
+    constexpr int kTile = 64;
     for (int c = 0; c < kNearConfigs; ++c)
       for (int f = cnt[c]; f < cnt[c + 1]; f += kTile) {
         H.nt_cfg.push_back(c);
@@ -309,11 +309,19 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         H.l4_slot[e] = s;
       }
     for (int c = 0; c < kP2LSlots; ++c)
-      for (int f = cnt[c]; f < cnt[c + 1]; f += 32) {
+      for (int f = cnt[c]; f < cnt[c + 1]; f += 64) {
         H.t4_cfg.push_back(c);
         H.t4_first.push_back(f);
-        H.t4_count.push_back(std::min(32, cnt[c + 1] - f));
+        H.t4_count.push_back(std::min(64, cnt[c + 1] - f));
       }
+  }
+  // P2M: every leaf, one configuration
+  H.leaf_ids.resize(L);
+  for (int i = 0; i < L; ++i) H.leaf_ids[i] = i;
+  for (int f = 0; f < L; f += 64) {
+    H.t0_cfg.push_back(0);
+    H.t0_first.push_back(f);
+    H.t0_count.push_back(std::min(64, L - f));
   }
 
   // ---- extension lists ---------------------------------------------------

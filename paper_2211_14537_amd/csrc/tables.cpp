@@ -611,6 +611,12 @@ static void build_pascal(Tables& T) {
         T.p2l_gemm[((size_t)s * n + j) * R + 2 * l] = T.p2l[src];
         T.p2l_gemm[((size_t)s * n + j) * R + 2 * l + 1] = T.p2l[src + 1];
       }
+  T.p2m_gemm.assign((size_t)n * R, 0.0);
+  for (int k = 0; k < P; ++k)
+    for (int j = 0; j < n; ++j) {
+      T.p2m_gemm[(size_t)j * R + 2 * k] = T.p2m[2 * ((size_t)k * n + j)];
+      T.p2m_gemm[(size_t)j * R + 2 * k + 1] = T.p2m[2 * ((size_t)k * n + j) + 1];
+    }
 }
 
 void build_tables(Tables& T) {

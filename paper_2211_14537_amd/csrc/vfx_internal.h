@@ -65,6 +65,8 @@ struct Tables {
   // 2l+1 (im), rows padded to p2l_rows (a multiple of 16)
   int p2l_rows = 0;
   std::vector<double> p2l_gemm;
+  // P2M as a real GEMM operand: [j][row], rows as for P2L
+  std::vector<double> p2m_gemm;
 };
 
 // Host precompute (quadrature.cpp, stencil.cpp)
@@ -86,6 +88,7 @@ struct DeviceTables {
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
+  double* p2m_gemm = nullptr;
   double2 *m2l_tpow = nullptr, *m2l_tneg = nullptr, *m2m_in = nullptr, *m2m_out = nullptr, *l2l_in = nullptr,
           *l2l_out = nullptr;
 };
@@ -111,9 +114,11 @@ struct HostPlan {
   // ascending inside a configuration) for the batched near-field GEMM;
   // l1_slot maps each per-target list-1 entry to its pair index
   std::vector<int> np_src, np_tgt, l1_slot;
-  std::vector<int> nt_cfg, nt_first, nt_count;  // GEMM tiles of <= 32 pairs
+  std::vector<int> nt_cfg, nt_first, nt_count;  // GEMM tiles of <= 64 pairs
   // list-4 entries regrouped by P2L slot, the same way
   std::vector<int> p4_src, l4_slot, t4_cfg, t4_first, t4_count;
+  // P2M over all leaves as one GEMM configuration
+  std::vector<int> leaf_ids, t0_cfg, t0_first, t0_count;
   std::vector<int> cut_leaf;                 // ncut
   std::vector<int> owner;                    // L
   std::vector<int> ext_ptr, ext_tgt;         // per cut leaf (targets, itself first)
@@ -137,6 +142,7 @@ struct DevicePlan {
   int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
+  int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
   double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
   int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
   uint16_t* pinv_idx = nullptr;
