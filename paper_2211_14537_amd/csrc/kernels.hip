@@ -156,34 +156,15 @@ __global__ void __launch_bounds__(256) k_extension(
   }
 }
 
-// -------------------------------------------------------------------------
-// P2M on every leaf: a = h^2 * P2M f  (p2m stored [j][k])
-__global__ void __launch_bounds__(64) k_p2m(int n, int P, double root_size, const int* __restrict__ leaf_box,
-                                            const int* __restrict__ box_level, const double2* __restrict__ p2m,
-                                            const double* __restrict__ fe, double2* __restrict__ mpole) {
-  __shared__ double s_f[kMaxK * kMaxK];
-  const int leaf = blockIdx.x;
-  const int lane = threadIdx.x;
-  for (int j = lane; j < n; j += 64) s_f[j] = fe[(size_t)leaf * n + j];
-  __syncthreads();
-  const int b = leaf_box[leaf];
-  const double h = box_side(root_size, box_level[b]);
-  const double h2 = h * h;
-  for (int k = lane; k < P; k += 64) {
-    double re = 0.0, im = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double2 m = p2m[(size_t)j * P + k];
-      re += m.x * s_f[j];
-      im += m.y * s_f[j];
-    }
-    mpole[(size_t)b * P + k] = make_double2(h2 * re, h2 * im);
-  }
-}
-
 typedef double vfx_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
 // Upward pass for the non-leaf boxes of one level, in the scaled-Pascal form
@@ -235,68 +216,201 @@ __global__ void __launch_bounds__(64) k_m2m(int P, int first, const int* __restr
   mpole[(size_t)b * P + l] = make_double2(re, im);
 }
 
-// Local expansions of the boxes at levels >= 2: M2L from list 2 in the
-// scaled-Pascal form (t = h/d for the source offset d)
-//   b_l += t^l sum_{k>=1} C(k+l-1,l) (-t)^k a_k - a_0 t^l / l  (l >= 1),
-//   b_0 += sum_{k>=1} (-t)^k a_k + a_0 (log|d/h| + log h),
-// plus the list-4 contributions h^2 (Q_c f_C) computed by the P2L GEMM and the
-// P2L log term log(h) a_0(C).
+// M2L with one lane per list-2 entry (target box, source box), for a group
+// of consecutive target boxes with at most 64 entries and at most 8 boxes.
+// Lane e holds s_k = (-t)^k a_k of its source (registers); the shared
+// Pascal coefficients C(k+l-1,l) are wave-uniform operands.  For each output
+// l the lane forms t^l sum_k C(k+l-1,l) s_k (minus a_0 t^l/l, plus the log
+// term for l = 0); the per-target sums go through LDS in chunks of 8 outputs,
+// in entry order (deterministic), together with the P2L contributions.
 template <int PM>
-__global__ void __launch_bounds__(64) k_m2l(int P, int first, double root_size, const int* __restrict__ box_level,
-                                            const int* __restrict__ l2_ptr, const int* __restrict__ l2_src,
-                                            const int* __restrict__ l2_off, const int* __restrict__ l4_ptr,
-                                            const int* __restrict__ l4_src, const int* __restrict__ l4_slot,
-                                            const int* __restrict__ leaf_box, int p2l_rows,
-                                            const double* __restrict__ pas, const double2* __restrict__ tpow,
-                                            const double2* __restrict__ tneg, const double* __restrict__ logd,
-                                            const double2* __restrict__ mpole, const double* __restrict__ p2l_y,
-                                            double2* __restrict__ local) {
-  __shared__ double2 s_s[PM];
-  const int b = first + blockIdx.x;
-  const int l = threadIdx.x;
-  double prow[PM];
+__global__ void __launch_bounds__(64) k_m2l_pairs(int P, double root_size, const int* __restrict__ grp,
+                                                  const int* __restrict__ box_level, const int* __restrict__ l2_ptr,
+                                                  const int* __restrict__ l2_src, const int* __restrict__ l2_off,
+                                                  const int* __restrict__ l2_tgt, const int* __restrict__ l4_ptr,
+                                                  const int* __restrict__ l4_src, const int* __restrict__ l4_slot,
+                                                  const int* __restrict__ leaf_box, int p2l_rows,
+                                                  const double* __restrict__ pasT, const double* __restrict__ logd,
+                                                  const double2* __restrict__ mpole, const double* __restrict__ p2l_y,
+                                                  double2* __restrict__ local) {
+  __shared__ double2 s_o[8 * 64];
+  const int g = blockIdx.x;
+  const int b0 = grp[g], b1 = grp[g + 1];
+  const int e0 = l2_ptr[b0], e1 = l2_ptr[b1];
+  const int lane = threadIdx.x;
+  const int e = e0 + lane;
+  const bool act = e < e1;
+  const int o = act ? l2_off[e] : 0;
+  const int src = act ? l2_src[e] : 0;
+  const double dx = (o / 7) - 3, dy = (o % 7) - 3;
+  const double dd = (dx * dx + dy * dy) > 0 ? dx * dx + dy * dy : 1.0;
+  const double2 t = make_double2(dx / dd, -dy / dd);  // 1 / (dx + i dy)
+  double2 s[PM];
+  {
+    double2 pw = make_double2(1.0, 0.0);
+    const double2 mt = make_double2(-t.x, -t.y);
 #pragma unroll
-  for (int k = 0; k < PM; ++k) prow[k] = (k < P && l < P) ? pas[(size_t)k * P + l] : 0.0;
-  if (l < PM) s_s[l] = make_double2(0.0, 0.0);
-  const double h = box_side(root_size, box_level[b]);
-  const double logh = log(h);
-  double re = 0.0, im = 0.0;
-  for (int e = l2_ptr[b]; e < l2_ptr[b + 1]; ++e) {
-    const int s = l2_src[e], o = l2_off[e];
-    __syncthreads();
-    if (l < P) {
-      const double2 a = mpole[(size_t)s * P + l];
-      s_s[l] = (l == 0) ? a : cmul(tneg[o * P + l], a);
-    }
-    __syncthreads();
-    if (l < P) {
-      double ur = 0.0, ui = 0.0;
-#pragma unroll
-      for (int k = 1; k < PM; ++k) {
-        ur += prow[k] * s_s[k].x;
-        ui += prow[k] * s_s[k].y;
-      }
-      const double2 tp = tpow[o * P + l];
-      re += tp.x * ur - tp.y * ui;
-      im += tp.x * ui + tp.y * ur;
-      const double a0 = s_s[0].x;
-      if (l == 0) {
-        re += a0 * (logd[o] + logh);
-      } else {
-        re -= a0 * tp.x / l;
-        im -= a0 * tp.y / l;
-      }
+    for (int k = 0; k < PM; ++k) {
+      const double2 a = (act && k < P) ? mpole[(size_t)src * P + k] : make_double2(0.0, 0.0);
+      s[k] = cmul(pw, a);
+      pw = cmul(pw, mt);
     }
   }
-  if (l < P) {
-    const double h2 = h * h;
-    for (int e = l4_ptr[b]; e < l4_ptr[b + 1]; ++e) {
-      const double* y = p2l_y + (size_t)l4_slot[e] * p2l_rows + 2 * l;
-      re += h2 * y[0];
-      im += h2 * y[1];
-      if (l == 0) re += logh * mpole[(size_t)leaf_box[l4_src[e]] * P].x;
+  const double a0 = s[0].x;
+  const int tgt = act ? l2_tgt[e] : b0;
+  const double logh = log(box_side(root_size, box_level[tgt]));
+  const double lg0 = act ? a0 * (logd[o] + logh) : 0.0;
+  double2 tl = make_double2(1.0, 0.0);
+  const int nchunk = (P + 7) / 8;
+  for (int c = 0; c < nchunk; ++c) {
+    double2 outc[8];
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) {
+      const int l = 8 * c + lc;
+      double2 out = make_double2(0.0, 0.0);
+      if (l < P) {
+        const double* cr = pasT + (size_t)l * P;
+        double ur = 0.0, ui = 0.0;
+#pragma unroll
+        for (int k = 1; k < PM; ++k) {
+          if (k < P) {
+            const double cf = cr[k];
+            ur += cf * s[k].x;
+            ui += cf * s[k].y;
+          }
+        }
+        out = cmul(tl, make_double2(ur, ui));
+        if (l == 0) {
+          out.x += lg0;
+        } else {
+          out.x -= a0 * tl.x / l;
+          out.y -= a0 * tl.y / l;
+        }
+        tl = cmul(tl, t);
+      }
+      outc[lc] = act ? out : make_double2(0.0, 0.0);
     }
-    local[(size_t)b * P + l] = make_double2(re, im);
+    __syncthreads();
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) s_o[lc * 64 + lane] = outc[lc];
+    __syncthreads();
+    const int lc = lane & 7, seg = lane >> 3;
+    const int bb = b0 + seg, l = 8 * c + lc;
+    if (bb < b1 && l < P) {
+      double re = 0.0, im = 0.0;
+      for (int q = l2_ptr[bb]; q < l2_ptr[bb + 1]; ++q) {
+        const double2 v = s_o[lc * 64 + (q - e0)];
+        re += v.x;
+        im += v.y;
+      }
+      const double h = box_side(root_size, box_level[bb]);
+      const double h2 = h * h;
+      for (int q = l4_ptr[bb]; q < l4_ptr[bb + 1]; ++q) {
+        const double* y = p2l_y + (size_t)l4_slot[q] * p2l_rows + 2 * l;
+        re += h2 * y[0];
+        im += h2 * y[1];
+        if (l == 0) re += log(h) * mpole[(size_t)leaf_box[l4_src[q]] * P].x;
+      }
+      local[(size_t)bb * P + l] = make_double2(re, im);
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// Lane-per-translation forms, instantiated for the exact expansion length P
+// (compile-time loops, so the Pascal coefficients, read through wave-uniform
+// pointers, become scalar operands of the FMAs and need no LDS traffic).
+
+// M2L: one lane per list-2 entry (target, source), for a group of
+// consecutive target boxes with at most 64 entries and at most 8 boxes.
+// Lane e holds s_k = (-t)^k a_k of its source; for each output l it forms
+// t^l sum_k C(k+l-1,l) s_k (minus a_0 t^l/l; plus a_0 (log|d/h| + log h) for
+// l = 0).  Per-target sums go through LDS in chunks of 8 outputs, in entry
+// order (deterministic), together with the P2L contributions.
+template <int P>
+__global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* __restrict__ grp,
+                                                  const int* __restrict__ box_level, const int* __restrict__ l2_ptr,
+                                                  const int* __restrict__ l2_src, const int* __restrict__ l2_off,
+                                                  const int* __restrict__ l2_tgt, const int* __restrict__ l4_ptr,
+                                                  const int* __restrict__ l4_src, const int* __restrict__ l4_slot,
+                                                  const int* __restrict__ leaf_box, int p2l_rows,
+                                                  const double* __restrict__ pasT, const double* __restrict__ logd,
+                                                  const double2* __restrict__ mpole, const double* __restrict__ p2l_y,
+                                                  double2* __restrict__ local) {
+  __shared__ double2 s_o[8 * 64];
+  const int g = blockIdx.x;
+  const int b0 = grp[g], b1 = grp[g + 1];
+  const int e0 = l2_ptr[b0], e1 = l2_ptr[b1];
+  const int lane = threadIdx.x;
+  const int e = e0 + lane;
+  const bool act = e < e1;
+  const int o = act ? l2_off[e] : 0;
+  const int src = act ? l2_src[e] : 0;
+  const double dx = (o / 7) - 3, dy = (o % 7) - 3;
+  const double dd = dx * dx + dy * dy;
+  const double2 t = make_double2(dx / dd, -dy / dd);  // 1 / (dx + i dy)
+  double2 s[P];
+  {
+    double2 pw = make_double2(1.0, 0.0);
+    const double2 mt = make_double2(-t.x, -t.y);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const double2 a = act ? mpole[(size_t)src * P + k] : make_double2(0.0, 0.0);
+      s[k] = cmul(pw, a);
+      pw = cmul(pw, mt);
+    }
+  }
+  const double a0 = s[0].x;
+  const int tgt = act ? l2_tgt[e] : b0;
+  const double lg0 = act ? a0 * (logd[o] + log(box_side(root_size, box_level[tgt]))) : 0.0;
+  double2 tl = make_double2(1.0, 0.0);
+  constexpr int NC = (P + 7) / 8;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    __syncthreads();
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) {
+      const int l = 8 * c + lc;
+      double2 out = make_double2(0.0, 0.0);
+      if (l < P) {
+        double ur = 0.0, ui = 0.0;
+#pragma unroll
+        for (int k = 1; k < P; ++k) {
+          const double cf = pasT[l * P + k];
+          ur += cf * s[k].x;
+          ui += cf * s[k].y;
+        }
+        out = cmul(tl, make_double2(ur, ui));
+        if (l == 0) {
+          out.x += lg0;
+        } else {
+          out.x -= a0 * tl.x / l;
+          out.y -= a0 * tl.y / l;
+        }
+        tl = cmul(tl, t);
+      }
+      s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int lc = lane & 7, seg = lane >> 3;
+    const int bb = b0 + seg, l = 8 * c + lc;
+    if (bb < b1 && l < P) {
+      double re = 0.0, im = 0.0;
+      for (int q = l2_ptr[bb]; q < l2_ptr[bb + 1]; ++q) {
+        const double2 v = s_o[lc * 64 + (q - e0)];
+        re += v.x;
+        im += v.y;
+      }
+      const double h = box_side(root_size, box_level[bb]);
+      const double h2 = h * h;
+      for (int q = l4_ptr[bb]; q < l4_ptr[bb + 1]; ++q) {
+        const double* y = p2l_y + (size_t)l4_slot[q] * p2l_rows + 2 * l;
+        re += h2 * y[0];
+        im += h2 * y[1];
+        if (l == 0) re += log(h) * mpole[(size_t)leaf_box[l4_src[q]] * P].x;
+      }
+      local[(size_t)bb * P + l] = make_double2(re, im);
+    }
   }
 }
 
@@ -336,37 +450,47 @@ __global__ void __launch_bounds__(64) k_l2l(int P, int first, const int* __restr
 // -------------------------------------------------------------------------
 // Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M).
 // Entries (pairs) are grouped by table configuration c; a work-group takes a
-// tile of <= 64 entries of one configuration and a block of <= 128 table rows
+// tile of <= TE entries (64 or 16) of one configuration and a block of <= 128
+// table rows
 // and computes, for every entry e, Y[e][row] = sum_k A_c[k][row] X[src(e)][k]
 // (the table applied to the source leaf's K^2 values).
 //   A: [c][k][row], R = 16*MT rows (rows fastest); X: [src][k]; Y: [e][row].
 // The K dimension is processed in blocks of 16 with both operands staged in
 // double-buffered LDS: the global loads of block kb+1 are in flight while the
-// waves run 4 x mtb MFMAs on block kb.  Wave w owns entries 16w..16w+15 and
-// every row tile of the block.  MFMA operands: A = entry data (16 entries x 4
+// waves run their MFMAs on block kb.  With TE = 64, wave w owns entries
+// 16w..16w+15 and every row tile of the block; with TE = 16 the waves share
+// the 16 entries and split the row tiles.  MFMA operands: A = entry data (16 entries x 4
 // k), B = table (4 k x 16 rows), so each output tile is (entries x rows) and
 // the stores of a 16-lane group are 128 contiguous bytes.
 // v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and the
 // outputs D[(l/16) + 4r][l%16], r = 0..3 (lane layout checked on gfx950).
 // EPI = 1 (P2M): Y is the multipole array; rows < 2P of entry e (a leaf) are
 // scaled by h^2 of that leaf and stored as its (p+1) complex coefficients.
-template <int KD, int EPI>
-__global__ void __launch_bounds__(256) k_gemm(int MT, const int* __restrict__ t_cfg, const int* __restrict__ t_first,
+template <int KD, int EPI, int TE>
+__global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __restrict__ t_cfg,
+                                              const int* __restrict__ t_first,
                                               const int* __restrict__ t_count, const int* __restrict__ src,
                                               const double* __restrict__ A, const double* __restrict__ X,
                                               double* __restrict__ Y, int P2, double root_size,
                                               const int* __restrict__ leaf_box, const int* __restrict__ box_level) {
   constexpr int KB = 16;
-  constexpr int LDA = 64;   // entries per LDS row
+  constexpr int LDA = TE;   // entries per LDS row (tile of TE = 64 or 16 entries)
   constexpr int LDB = 128;  // table rows per LDS row
+  constexpr int NACC = (TE == 64) ? 8 : 2;  // row tiles per wave
   __shared__ double sA[2][KB * LDA];
   __shared__ double sB[2][KB * LDB];
   const int nrb = (MT + 7) / 8;  // row blocks of 8 tiles
-  // XCD-aware order: consecutive work items (same configuration, same table)
-  // go to the same XCD, whose L2 then serves the table to all of them
+  // XCD-aware, persistent order: work-groups are dispatched round-robin over
+  // the 8 XCDs, so the work-groups of XCD x (blockIdx % 8 == x) walk one
+  // contiguous range of work items; consecutive items share a configuration
+  // and hence a table, which that XCD's L2 then serves to all of them.
   const int nb = gridDim.x, bb = blockIdx.x;
-  const int q = nb >> 3, rr = nb & 7, x = bb & 7, i8 = bb >> 3;
-  const int item = x * q + min(x, rr) + i8;
+  const int x = bb & 7;
+  const int q = nitems >> 3, rr = nitems & 7;
+  const int xfirst = x * q + min(x, rr), xcount = q + (x < rr ? 1 : 0);
+  const int xwgs = (nb - x + 7) >> 3;  // work-groups on this XCD
+  for (int j = bb >> 3; j < xcount; j += xwgs) {
+  const int item = xfirst + j;
   const int tile = item / nrb, rb = item - tile * nrb;
   const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
   const int R = 16 * MT;
@@ -376,15 +500,16 @@ __global__ void __launch_bounds__(256) k_gemm(int MT, const int* __restrict__ t_
   const int li = lane & 15, lk = lane >> 4;
   const double* Ac = A + (size_t)c * KD * R;
   // global -> register staging of one K block
-  const int aj = tid & 63, ak = (tid >> 6) * 4;  // entry data: entry aj, k = ak..ak+3
-  const int bk = tid >> 4, br = (tid & 15) * 8;  // table: k = bk, rows br..br+7
+  constexpr int AE = TE * KB / 256;                  // entry values per thread (4 or 1)
+  const int aj = tid % TE, ak = (tid / TE) * AE;     // entry aj, k = ak..ak+AE-1
+  const int bk = tid >> 4, br = (tid & 15) * 8;      // table: k = bk, rows br..br+7
   const bool a_ok = aj < np;
   const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
-  double ra[4], rb8[8];
+  double ra[AE], rb8[8];
   auto gload = [&](int kb) {
     const int k0 = kb * KB;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
+    for (int e = 0; e < AE; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
     const bool b_ok = br < 16 * mtb;
     const double* ar = Ac + (size_t)(k0 + bk) * R + row0 + br;
 #pragma unroll
@@ -392,13 +517,17 @@ __global__ void __launch_bounds__(256) k_gemm(int MT, const int* __restrict__ t_
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sA[buf][(ak + e) * LDA + aj] = ra[e];
+    for (int e = 0; e < AE; ++e) sA[buf][(ak + e) * LDA + aj] = ra[e];
 #pragma unroll
     for (int e = 0; e < 8; ++e) sB[buf][bk * LDB + br + e] = rb8[e];
   };
-  vfx_d4 acc[8];
+  // wave w: TE = 64 -> entries 16w..16w+15, row tiles 0..mtb-1;
+  //         TE = 16 -> entries 0..15, row tiles w and w+4
+  const int ebase = (TE == 64) ? 16 * w : 0;
+  auto tile_of = [&](int r) { return (TE == 64) ? r : w + 4 * r; };
+  vfx_d4 acc[NACC];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
+  for (int r = 0; r < NACC; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
   constexpr int NKB = KD / KB;
   gload(0);
   lstore(0);
@@ -409,21 +538,25 @@ __global__ void __launch_bounds__(256) k_gemm(int MT, const int* __restrict__ t_
 #pragma unroll
     for (int ks = 0; ks < KB / 4; ++ks) {
       const int k = 4 * ks + lk;
-      const double a = sA[buf][k * LDA + 16 * w + li];
+      const double a = sA[buf][k * LDA + ebase + li];
 #pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < mtb) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[buf][k * LDB + 16 * r + li], acc[r], 0, 0, 0);
+      for (int r = 0; r < NACC; ++r) {
+        const int rt = tile_of(r);
+        if (rt < mtb)
+          acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[buf][k * LDB + 16 * rt + li], acc[r], 0, 0, 0);
+      }
     }
     if (kb + 1 < NKB) lstore(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    if (r >= mtb) continue;
-    const int row = row0 + 16 * r + li;
+  for (int r = 0; r < NACC; ++r) {
+    const int rt = tile_of(r);
+    if (rt >= mtb) continue;
+    const int row = row0 + 16 * rt + li;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int ent = 16 * w + lk + 4 * e;
+      const int ent = ebase + lk + 4 * e;
       if (ent >= np) continue;
       if (EPI == 0) {
         Y[(size_t)(p0 + ent) * R + row] = acc[r][e];
@@ -435,6 +568,7 @@ __global__ void __launch_bounds__(256) k_gemm(int MT, const int* __restrict__ t_
       }
     }
   }
+  }  // work items
 }
 
 // With Y given, the near field is also finished here: the per-pair partials
@@ -538,6 +672,9 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.p2l_gemm, T.p2l_gemm);
   UP(D.p2m_gemm, T.p2m_gemm);
   UP(D.pas_m2l, T.pas_m2l);
+  UP(D.pas_m2l_t, T.pas_m2l_t);
+  UP(D.pas_m2m_t, T.pas_m2m_t);
+  UP(D.pas_l2l_t, T.pas_l2l_t);
   UP(D.pas_m2m, T.pas_m2m);
   UP(D.pas_l2l, T.pas_l2l);
   UP(D.m2l_logd, T.m2l_logd);
@@ -576,7 +713,7 @@ void free_tables_device(Context* c) {
   void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
-                  D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out};
+                  D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   D = DeviceTables();
@@ -601,6 +738,8 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.l2_ptr, H.l2_ptr);
   UP(D.l2_src, H.l2_src);
   UP(D.l2_off, H.l2_off);
+  UP(D.l2_tgt, H.l2_tgt);
+  UP(D.m2l_grp, H.m2l_grp);
   UP(D.l3_ptr, H.l3_ptr);
   UP(D.l3_src, H.l3_src);
   UP(D.l4_ptr, H.l4_ptr);
@@ -647,7 +786,7 @@ void free_plan_device(Plan* p) {
                   D.nt_cfg,    D.nt_first,   D.nt_count, D.near_y,     D.p4_src,   D.l4_slot,  D.t4_cfg,
                   D.t4_first,  D.t4_count,   D.p2l_y,    D.cut_leaf,   D.ext_ptr,  D.ext_tgt,  D.pinv_ptr,
                   D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local,    D.t0_cfg,   D.t0_first,
-                  D.t0_count,  D.leaf_ids};
+                  D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -663,28 +802,36 @@ void free_plan_device(Plan* p) {
   p->side = nullptr;
 }
 
-template <int KD, int EPI>
+template <int KD, int EPI, int TE>
 static void launch_gemm(int items, int MT, const int* cfg, const int* first, const int* count, const int* src,
                         const double* A, const double* X, double* Y, int P2, double root, const int* leaf_box,
-                        const int* box_level, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm<KD, EPI>), dim3(items), dim3(256), 0, s, MT, cfg, first, count, src, A, X, Y, P2, root,
-                     leaf_box, box_level);
+                        const int* box_level, hipStream_t s, int max_wgs) {
+  const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
+  hipLaunchKernelGGL((k_gemm<KD, EPI, TE>), dim3(grid), dim3(256), 0, s, items, MT, cfg, first, count, src, A, X, Y,
+                     P2, root, leaf_box, box_level);
 }
 
-// ntiles tiles of <= 64 entries; each is split into ceil(MT/8) row blocks
-template <int EPI>
+// ntiles tiles of <= TE entries; each is split into ceil(MT/8) row blocks;
+// max_wgs > 0 bounds the grid (the work-groups then loop over the items)
+template <int EPI, int TE>
 static void gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
-                 const double* A, const double* X, double* Y, hipStream_t s, int P2 = 0, double root = 0,
-                 const int* leaf_box = nullptr, const int* box_level = nullptr) {
+                 const double* A, const double* X, double* Y, hipStream_t s, int max_wgs = 0, int P2 = 0,
+                 double root = 0, const int* leaf_box = nullptr, const int* box_level = nullptr) {
   if (ntiles <= 0) return;
   const int items = ntiles * ((MT + 7) / 8);
+#define VFX_GEMM_CASE(KDV)                                                                                   \
+  launch_gemm<KDV, EPI, TE>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, \
+                            max_wgs)
   switch (n) {
-    case 16: launch_gemm<16, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
-    case 64: launch_gemm<64, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
-    case 144: launch_gemm<144, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
-    default: launch_gemm<256, EPI>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s); break;
+    case 16: VFX_GEMM_CASE(16); break;
+    case 64: VFX_GEMM_CASE(64); break;
+    case 144: VFX_GEMM_CASE(144); break;
+    default: VFX_GEMM_CASE(256); break;
   }
+#undef VFX_GEMM_CASE
 }
+
+constexpr int kNearWgs = 512;
 
 int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V, hipStream_t s,
                    std::string& err) {
@@ -744,18 +891,21 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
                        DT.t, DT.AbarT, DT.cbar, D.leaf_box, D.box_cx, D.box_cy, D.box_level, f_cut, fe);
   VFX_HIP(hipGetLastError());
   MARK(1, s);
+  // multipoles of the leaves (start of the critical chain)
+  gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids, DT.p2m_gemm,
+              fe, (double*)D.mpole, s, 0, 2 * P, T.root_size, D.leaf_box, D.box_level);
   // fork: near field on the side stream, concurrent with the upward pass,
-  // M2L/P2L and the downward pass on the caller's stream
+  // M2L/P2L and the downward pass on the caller's stream.  Its grid is
+  // bounded (about two work-groups per CU, looping over the tiles) so the
+  // latency-bound tree kernels keep CU slots.
   VFX_HIP(hipEventRecord(p->fork_ev, s));
   VFX_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
   MARK(5, p->side);
-  gemm<0>(n, (int)H.nt_cfg.size(), n / 16, D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y,
-          p->side);
+  gemm<0, 64>(n, (int)H.nt_cfg.size(), n / 16, D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y,
+              p->side, kNearWgs);
   VFX_HIP(hipGetLastError());
   MARK(6, p->side);
   VFX_HIP(hipEventRecord(p->join_ev, p->side));
-  gemm<1>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids, DT.p2m_gemm,
-          fe, (double*)D.mpole, s, 2 * P, T.root_size, D.leaf_box, D.box_level);
   for (int l = H.nlev - 2; l >= 2; --l) {
     const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
     if (cnt <= 0) continue;
@@ -769,17 +919,33 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipGetLastError());
   MARK(2, s);
   if (H.nlev > 2) {
-    gemm<0>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src, DT.p2l_gemm,
+    gemm<0, 64>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src, DT.p2l_gemm,
             fe, D.p2l_y, s);
-    const int first = H.level_start[2], cnt = H.B - first;
-    if (big)
-      hipLaunchKernelGGL(k_m2l<64>, dim3(cnt), dim3(64), 0, s, P, first, T.root_size, D.box_level, D.l2_ptr,
-                         D.l2_src, D.l2_off, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows, DT.pas_m2l,
-                         DT.m2l_tpow, DT.m2l_tneg, DT.m2l_logd, D.mpole, D.p2l_y, D.local);
-    else
-      hipLaunchKernelGGL(k_m2l<32>, dim3(cnt), dim3(64), 0, s, P, first, T.root_size, D.box_level, D.l2_ptr,
-                         D.l2_src, D.l2_off, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows, DT.pas_m2l,
-                         DT.m2l_tpow, DT.m2l_tneg, DT.m2l_logd, D.mpole, D.p2l_y, D.local);
+    const int ng = (int)H.m2l_grp.size() - 1;
+    if (ng > 0) {
+#define VFX_M2L(PMV)                                                                                             \
+  hipLaunchKernelGGL(k_m2l_pairs<PMV>, dim3(ng), dim3(64), 0, s, P, T.root_size, D.m2l_grp, D.box_level, D.l2_ptr, \
+                     D.l2_src, D.l2_off, D.l2_tgt, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows,         \
+                     DT.pas_m2l_t, DT.m2l_logd, D.mpole, D.p2l_y, D.local)
+#define VFX_M2LL(PV)                                                                                             \
+  hipLaunchKernelGGL(k_m2l_lanes<PV>, dim3(ng), dim3(64), 0, s, T.root_size, D.m2l_grp, D.box_level, D.l2_ptr,     \
+                     D.l2_src, D.l2_off, D.l2_tgt, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows,         \
+                     DT.pas_m2l_t, DT.m2l_logd, D.mpole, D.p2l_y, D.local)
+      if (P == 21)
+        VFX_M2LL(21);
+      else if (P == 25)
+        VFX_M2LL(25);
+      else if (P == 31)
+        VFX_M2LL(31);
+      else if (P == 41)
+        VFX_M2LL(41);
+      else if (P <= 32)
+        VFX_M2L(32);
+      else
+        VFX_M2L(64);
+#undef VFX_M2L
+#undef VFX_M2LL
+    }
   }
   VFX_HIP(hipGetLastError());
   MARK(3, s);

@@ -293,6 +293,27 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     H.l4_ptr[b + 1] = H.l4_ptr[b] + n4;
   }
 
+  // ---- list-2 target per entry; groups of boxes for the M2L kernel --------
+  H.l2_tgt.resize(H.l2_src.size());
+  for (int b = 0; b < B; ++b)
+    for (int e = H.l2_ptr[b]; e < H.l2_ptr[b + 1]; ++e) H.l2_tgt[e] = b;
+  if (H.nlev > 2) {
+    int b = H.level_start[2];
+    H.m2l_grp.push_back(b);
+    while (b < B) {
+      int nb = 0, ne = 0;
+      while (b < B && nb < 8 && ne + (H.l2_ptr[b + 1] - H.l2_ptr[b]) <= 64) {
+        ne += H.l2_ptr[b + 1] - H.l2_ptr[b];
+        ++nb;
+        ++b;
+      }
+      if (nb == 0) {
+        err = "internal: list 2 longer than 64";
+        return VFX_EINVAL;
+      }
+      H.m2l_grp.push_back(b);
+    }
+  }
   // ---- list-4 entries grouped by P2L slot --------------------------------
   {
     const int N4 = H.l4_ptr[B];
@@ -318,10 +339,10 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
   // P2M: every leaf, one configuration
   H.leaf_ids.resize(L);
   for (int i = 0; i < L; ++i) H.leaf_ids[i] = i;
-  for (int f = 0; f < L; f += 64) {
+  for (int f = 0; f < L; f += 16) {
     H.t0_cfg.push_back(0);
     H.t0_first.push_back(f);
-    H.t0_count.push_back(std::min(64, L - f));
+    H.t0_count.push_back(std::min(16, L - f));
   }
 
   // ---- extension lists ---------------------------------------------------

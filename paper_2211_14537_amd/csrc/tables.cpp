@@ -566,6 +566,15 @@ static void build_pascal(Tables& T) {
       if (k >= 1 && k <= l) T.pas_m2m[(size_t)k * P + l] = binom(l - 1, k - 1);
       if (k >= l) T.pas_l2l[(size_t)k * P + l] = binom(k, l);
     }
+  T.pas_m2l_t.assign((size_t)P * P, 0.0);
+  T.pas_m2m_t.assign((size_t)P * P, 0.0);
+  T.pas_l2l_t.assign((size_t)P * P, 0.0);
+  for (int k = 0; k < P; ++k)
+    for (int l = 0; l < P; ++l) {
+      T.pas_m2l_t[(size_t)l * P + k] = T.pas_m2l[(size_t)k * P + l];
+      T.pas_m2m_t[(size_t)l * P + k] = T.pas_m2m[(size_t)k * P + l];
+      T.pas_l2l_t[(size_t)l * P + k] = T.pas_l2l[(size_t)k * P + l];
+    }
   T.m2l_tpow.assign((size_t)kM2LSlots * P * 2, 0.0);
   T.m2l_tneg.assign((size_t)kM2LSlots * P * 2, 0.0);
   T.m2l_logd.assign(kM2LSlots, 0.0);

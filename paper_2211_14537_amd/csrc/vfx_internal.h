@@ -57,6 +57,7 @@ struct Tables {
   //        b_0 += a_0, w = (child - parent centre)/h_parent
   //   L2L: c_l  = (2w)^-l sum_{k>=l} C(k,l) w^k b_k
   std::vector<double> pas_m2l, pas_m2m, pas_l2l;  // P x P real, [k][l]
+  std::vector<double> pas_m2l_t, pas_m2m_t, pas_l2l_t;  // the same, stored [l][k]
   std::vector<double> m2l_tpow, m2l_tneg;         // 49 x P complex: t^l, (-t)^k
   std::vector<double> m2l_logd;                   // 49: log|d/h|
   std::vector<double> m2m_in, m2m_out;            // 4 x P complex: (2w)^-k, w^l
@@ -89,6 +90,7 @@ struct DeviceTables {
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
   double* p2m_gemm = nullptr;
+  double *pas_m2l_t = nullptr, *pas_m2m_t = nullptr, *pas_l2l_t = nullptr;
   double2 *m2l_tpow = nullptr, *m2l_tneg = nullptr, *m2m_in = nullptr, *m2m_out = nullptr, *l2l_in = nullptr,
           *l2l_out = nullptr;
 };
@@ -108,6 +110,9 @@ struct HostPlan {
   std::vector<int8_t> kind;                  // L
   std::vector<int> l1_ptr, l1_src, l1_cfg;   // per leaf
   std::vector<int> l2_ptr, l2_src, l2_off;   // per box
+  std::vector<int> l2_tgt;                   // target box of each list-2 entry
+  std::vector<int> m2l_grp;                  // groups of consecutive boxes (level >= 2):
+                                             // <= 64 list-2 entries, <= 8 boxes
   std::vector<int> l3_ptr, l3_src;           // per leaf (source boxes)
   std::vector<int> l4_ptr, l4_src, l4_cfg;   // per box (source leaves)
   // list-1 pairs regrouped by table configuration (config-major, targets
@@ -136,7 +141,7 @@ struct DevicePlan {
   int* leaf_box = nullptr;
   int8_t* kind = nullptr;
   int *l1_ptr = nullptr, *l1_src = nullptr, *l1_cfg = nullptr;
-  int *l2_ptr = nullptr, *l2_src = nullptr, *l2_off = nullptr;
+  int *l2_ptr = nullptr, *l2_src = nullptr, *l2_off = nullptr, *l2_tgt = nullptr, *m2l_grp = nullptr;
   int *l3_ptr = nullptr, *l3_src = nullptr;
   int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
   int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;

@@ -61,6 +61,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"vfx: HIP library not built ({LIB_PATH}); run __graft_entry__.build()")
+        # PyTorch bundles a HIP runtime with the same soname as the system
+        # one the library links against; whichever is loaded first serves the
+        # whole process.  Load PyTorch first so that its device memory and
+        # streams and this library share one runtime.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp = ctypes.c_void_p
         i32p = ctypes.POINTER(ctypes.c_int32)

@@ -26,7 +26,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("name,p,tol", [("disk_uniform3", 40, 1e-10), ("disk_uniform3", 20, 1e-9),
                                         ("disk_tiny", 30, 1e-10), ("disk_adaptive_small", 40, 1e-10),
-                                        ("starfish_small", 40, 1e-10)])
+                                        ("starfish_small", 40, 1e-10), ("starfish_small", 24, 1e-11),
+                                        ("disk_adaptive_small", 16, 1e-7)])
 def test_volume_parity(gpu_device, name, p, tol):
     say(f"[volume parity] {name} p={p}")
     case = setup(name, p=p, all_regular=True)
