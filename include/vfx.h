@@ -162,7 +162,13 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
  *           (49 x (p+1) complex), 12 log|d/h| per M2L slot, 13 C(l-1,k-1),
  *           14 (2w)^-k and 15 w^l per child (4 x (p+1) complex), 16 C(k,l),
  *           17 w^k and 18 (2w)^-l per child, 19 the P2L GEMM operand
- *           (36 x n x rows, rows = 16 ceil(2(p+1)/16))
+ *           (36 x n x rows, rows = 64 ceil(2(p+1)/64))
+ *        20: low-rank factor W of near-field configuration `index`, n x 64,
+ *            [j][a]; 21: its factor Q, 64 x n, [a][i]; table 0 of the
+ *            configuration ~ sum_a Q[a][i] W[j][a] (zero padded beyond the
+ *            rank; both zero for configurations applied densely)
+ *        22 (`index` ignored): 66 values, the padded rank R (0 = dense) of
+ *            each configuration, then its rank
  * VFX_EINVAL if `which`, `index` or `count` does not match. */
 int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count);
 /* Interaction list `which` (1..4) of a plan as CSR arrays (host):

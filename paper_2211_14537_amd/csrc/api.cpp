@@ -240,6 +240,23 @@ int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64
       src = T.w2.data();
       size = (int64_t)T.w2.size();
       break;
+    case 20:
+    case 21:
+      if (index < 0 || index >= vfx::kNearConfigs) break;
+      src = (which == 20 ? T.lr_W : T.lr_Q).data() + (size_t)index * n * vfx::kNearLrMax;
+      size = n * vfx::kNearLrMax;
+      break;
+    case 22: {
+      static thread_local std::vector<double> rk;
+      rk.assign(2 * vfx::kNearConfigs, 0.0);
+      for (int c = 0; c < vfx::kNearConfigs; ++c) {
+        rk[c] = T.lr_R[c];
+        rk[vfx::kNearConfigs + c] = T.lr_rank[c];
+      }
+      src = rk.data();
+      size = (int64_t)rk.size();
+      break;
+    }
     case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17: case 18: case 19: {
       const std::vector<double>* v[] = {&T.pas_m2l, &T.m2l_tpow, &T.m2l_tneg, &T.m2l_logd, &T.pas_m2m,
                                         &T.m2m_in,  &T.m2m_out,  &T.pas_l2l,  &T.l2l_in,   &T.l2l_out,

@@ -167,53 +167,27 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-// Upward pass for the non-leaf boxes of one level, in the scaled-Pascal form
-//   b_l = sum_q w_q^l [ sum_{1<=k<=l} C(l-1,k-1) (2 w_q)^-k a_{q,k} - a_{q,0}/l ],
-//   b_0 = sum_q a_{q,0}   (w_q: child centre offset / parent side)
-// One wave per box, lane l = output coefficient; the lane's Pascal row is
-// held in registers.
-template <int PM>
-__global__ void __launch_bounds__(64) k_m2m(int P, int first, const int* __restrict__ box_child0,
-                                            const double* __restrict__ pas, const double2* __restrict__ sin,
-                                            const double2* __restrict__ sout, double2* __restrict__ mpole) {
-  __shared__ double2 s_s[4][PM];
-  const int b = first + blockIdx.x;
-  const int c0 = box_child0[b];
-  if (c0 < 0) return;
-  const int l = threadIdx.x;
-  double prow[PM];
-#pragma unroll
-  for (int k = 0; k < PM; ++k) prow[k] = (k < P && l < P) ? pas[(size_t)k * P + l] : 0.0;
-  for (int q = 0; q < 4; ++q) {
-    double2 v = make_double2(0.0, 0.0);
-    if (l < P) {
-      const double2 a = mpole[(size_t)(c0 + q) * P + l];
-      v = (l == 0) ? a : cmul(sin[q * P + l], a);
-    }
-    if (l < PM) s_s[q][l] = v;
+// Sum of s[q] over q in [q0, q1) in a fixed order with four
+// interleaved partial sums (deterministic, and the LDS loads overlap).
+__device__ __forceinline__ double2 seg_sum(const double2* s, int q0, int q1) {
+  double r0 = 0.0, i0 = 0.0, r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0, r3 = 0.0, i3 = 0.0;
+  int q = q0;
+  for (; q + 3 < q1; q += 4) {
+    const double2 v0 = s[q], v1 = s[q + 1], v2 = s[q + 2], v3 = s[q + 3];
+    r0 += v0.x;
+    i0 += v0.y;
+    r1 += v1.x;
+    i1 += v1.y;
+    r2 += v2.x;
+    i2 += v2.y;
+    r3 += v3.x;
+    i3 += v3.y;
   }
-  __syncthreads();
-  if (l >= P) return;
-  double re = 0.0, im = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    if (l == 0) {
-      re += s_s[q][0].x;
-      im += s_s[q][0].y;
-      continue;
-    }
-    double ur = 0.0, ui = 0.0;
-#pragma unroll
-    for (int k = 1; k < PM; ++k) {
-      ur += prow[k] * s_s[q][k].x;
-      ui += prow[k] * s_s[q][k].y;
-    }
-    ur -= s_s[q][0].x / l;
-    ui -= s_s[q][0].y / l;
-    const double2 w = sout[q * P + l];
-    re += w.x * ur - w.y * ui;
-    im += w.x * ui + w.y * ur;
+  for (; q < q1; ++q) {
+    r0 += s[q].x;
+    i0 += s[q].y;
   }
-  mpole[(size_t)b * P + l] = make_double2(re, im);
+  return make_double2((r0 + r1) + (r2 + r3), (i0 + i1) + (i2 + i3));
 }
 
 // M2L with one lane per list-2 entry (target box, source box), for a group
@@ -297,12 +271,8 @@ __global__ void __launch_bounds__(64) k_m2l_pairs(int P, double root_size, const
     const int lc = lane & 7, seg = lane >> 3;
     const int bb = b0 + seg, l = 8 * c + lc;
     if (bb < b1 && l < P) {
-      double re = 0.0, im = 0.0;
-      for (int q = l2_ptr[bb]; q < l2_ptr[bb + 1]; ++q) {
-        const double2 v = s_o[lc * 64 + (q - e0)];
-        re += v.x;
-        im += v.y;
-      }
+      const double2 sv = seg_sum(s_o + lc * 64, l2_ptr[bb] - e0, l2_ptr[bb + 1] - e0);
+      double re = sv.x, im = sv.y;
       const double h = box_side(root_size, box_level[bb]);
       const double h2 = h * h;
       for (int q = l4_ptr[bb]; q < l4_ptr[bb + 1]; ++q) {
@@ -368,24 +338,35 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     __syncthreads();
+    // the eight outputs of the chunk accumulate side by side (k outer), so
+    // their FMA chains interleave
+    double ur[8], ui[8];
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) ur[lc] = ui[lc] = 0.0;
+#pragma unroll
+    for (int k = 1; k < P; ++k) {
+#pragma unroll
+      for (int lc = 0; lc < 8; ++lc) {
+        const int l = 8 * c + lc;
+        if (l < P) {
+          const double cf = pasT[l * P + k];
+          ur[lc] += cf * s[k].x;
+          ui[lc] += cf * s[k].y;
+        }
+      }
+    }
 #pragma unroll
     for (int lc = 0; lc < 8; ++lc) {
       const int l = 8 * c + lc;
       double2 out = make_double2(0.0, 0.0);
       if (l < P) {
-        double ur = 0.0, ui = 0.0;
-#pragma unroll
-        for (int k = 1; k < P; ++k) {
-          const double cf = pasT[l * P + k];
-          ur += cf * s[k].x;
-          ui += cf * s[k].y;
-        }
-        out = cmul(tl, make_double2(ur, ui));
+        out = cmul(tl, make_double2(ur[lc], ui[lc]));
         if (l == 0) {
           out.x += lg0;
         } else {
-          out.x -= a0 * tl.x / l;
-          out.y -= a0 * tl.y / l;
+          const double il = 1.0 / (double)l;  // compile-time constant
+          out.x -= a0 * tl.x * il;
+          out.y -= a0 * tl.y * il;
         }
         tl = cmul(tl, t);
       }
@@ -395,12 +376,8 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
     const int lc = lane & 7, seg = lane >> 3;
     const int bb = b0 + seg, l = 8 * c + lc;
     if (bb < b1 && l < P) {
-      double re = 0.0, im = 0.0;
-      for (int q = l2_ptr[bb]; q < l2_ptr[bb + 1]; ++q) {
-        const double2 v = s_o[lc * 64 + (q - e0)];
-        re += v.x;
-        im += v.y;
-      }
+      const double2 sv = seg_sum(s_o + lc * 64, l2_ptr[bb] - e0, l2_ptr[bb + 1] - e0);
+      double re = sv.x, im = sv.y;
       const double h = box_side(root_size, box_level[bb]);
       const double h2 = h * h;
       for (int q = l4_ptr[bb]; q < l4_ptr[bb + 1]; ++q) {
@@ -414,72 +391,44 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
   }
 }
 
-// Downward pass into the boxes of one level:
-//   c_l += (2w)^-l sum_{k>=l} C(k,l) w^k b_k(parent)
-template <int PM>
-__global__ void __launch_bounds__(64) k_l2l(int P, int first, const int* __restrict__ box_parent,
-                                            const int* __restrict__ box_child0, const double* __restrict__ pas,
-                                            const double2* __restrict__ sin, const double2* __restrict__ sout,
-                                            double2* __restrict__ local) {
-  __shared__ double2 s_s[PM];
-  const int b = first + blockIdx.x;
-  const int l = threadIdx.x;
-  const int par = box_parent[b];
-  const int q = b - box_child0[par];
-  double prow[PM];
-#pragma unroll
-  for (int k = 0; k < PM; ++k) prow[k] = (k < P && l < P) ? pas[(size_t)k * P + l] : 0.0;
-  double2 v = make_double2(0.0, 0.0);
-  if (l < P) v = cmul(sin[q * P + l], local[(size_t)par * P + l]);
-  if (l < PM) s_s[l] = v;
-  __syncthreads();
-  if (l >= P) return;
-  double ur = 0.0, ui = 0.0;
-#pragma unroll
-  for (int k = 0; k < PM; ++k) {
-    ur += prow[k] * s_s[k].x;
-    ui += prow[k] * s_s[k].y;
-  }
-  const double2 g = cmul(sout[q * P + l], make_double2(ur, ui));
-  double2 o = local[(size_t)b * P + l];
-  o.x += g.x;
-  o.y += g.y;
-  local[(size_t)b * P + l] = o;
-}
-
 // -------------------------------------------------------------------------
 // Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M).
 // Entries (pairs) are grouped by table configuration c; a work-group takes a
-// tile of <= TE entries (64 or 16) of one configuration and a block of <= 128
-// table rows
-// and computes, for every entry e, Y[e][row] = sum_k A_c[k][row] X[src(e)][k]
+// tile of <= TE entries (64 or 16) of one configuration and a block of MTB
+// row tiles (16 table rows each) and computes, for every entry e,
+//   Y[e][row] = sum_k A_c[k][row] X[src(e)][k]
 // (the table applied to the source leaf's K^2 values).
-//   A: [c][k][row], R = 16*MT rows (rows fastest); X: [src][k]; Y: [e][row].
+//   A: [c][k][row], R = 16*MT rows (rows fastest, MT a multiple of MTB);
+//   X: [src][k]; Y: [e][row].
 // The K dimension is processed in blocks of 16 with both operands staged in
 // double-buffered LDS: the global loads of block kb+1 are in flight while the
 // waves run their MFMAs on block kb.  With TE = 64, wave w owns entries
 // 16w..16w+15 and every row tile of the block; with TE = 16 the waves share
-// the 16 entries and split the row tiles.  MFMA operands: A = entry data (16 entries x 4
-// k), B = table (4 k x 16 rows), so each output tile is (entries x rows) and
-// the stores of a 16-lane group are 128 contiguous bytes.
+// the 16 entries and split the row tiles (w, w+4).  Row-tile counts are
+// compile-time, so the MFMA sequence has no per-tile branches.  MFMA
+// operands: A = entry data (16 entries x 4 k), B = table (4 k x 16 rows), so
+// each output tile is (entries x rows) and the stores of a 16-lane group are
+// 128 contiguous bytes.
 // v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16], B[l/16][l%16] and the
 // outputs D[(l/16) + 4r][l%16], r = 0..3 (lane layout checked on gfx950).
 // EPI = 1 (P2M): Y is the multipole array; rows < 2P of entry e (a leaf) are
 // scaled by h^2 of that leaf and stored as its (p+1) complex coefficients.
-template <int KD, int EPI, int TE>
+template <int KD, int EPI, int TE, int MTB>
 __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __restrict__ t_cfg,
                                               const int* __restrict__ t_first,
                                               const int* __restrict__ t_count, const int* __restrict__ src,
                                               const double* __restrict__ A, const double* __restrict__ X,
                                               double* __restrict__ Y, int P2, double root_size,
                                               const int* __restrict__ leaf_box, const int* __restrict__ box_level) {
+  static_assert(TE == 64 || MTB % 4 == 0, "TE = 16 splits the row tiles over the four waves");
   constexpr int KB = 16;
-  constexpr int LDA = TE;   // entries per LDS row (tile of TE = 64 or 16 entries)
-  constexpr int LDB = 128;  // table rows per LDS row
-  constexpr int NACC = (TE == 64) ? 8 : 2;  // row tiles per wave
+  constexpr int LDA = TE;        // entries per LDS row (tile of TE = 64 or 16 entries)
+  constexpr int LDB = 16 * MTB;  // table rows per LDS row
+  constexpr int NACC = (TE == 64) ? MTB : MTB / 4;  // row tiles per wave
+  constexpr int BE = MTB;        // table values staged per thread and K block
   __shared__ double sA[2][KB * LDA];
   __shared__ double sB[2][KB * LDB];
-  const int nrb = (MT + 7) / 8;  // row blocks of 8 tiles
+  const int nrb = MT / MTB;
   // XCD-aware, persistent order: work-groups are dispatched round-robin over
   // the 8 XCDs, so the work-groups of XCD x (blockIdx % 8 == x) walk one
   // contiguous range of work items; consecutive items share a configuration
@@ -494,41 +443,40 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
   const int tile = item / nrb, rb = item - tile * nrb;
   const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
   const int R = 16 * MT;
-  const int mtb = min(8, MT - 8 * rb);
-  const int row0 = 128 * rb;
+  const int row0 = 16 * MTB * rb;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const double* Ac = A + (size_t)c * KD * R;
   // global -> register staging of one K block
   constexpr int AE = TE * KB / 256;                  // entry values per thread (4 or 1)
   const int aj = tid % TE, ak = (tid / TE) * AE;     // entry aj, k = ak..ak+AE-1
-  const int bk = tid >> 4, br = (tid & 15) * 8;      // table: k = bk, rows br..br+7
+  const int bk = tid >> 4, br = (tid & 15) * BE;     // table: k = bk, rows br..br+BE-1
   const bool a_ok = aj < np;
   const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
-  double ra[AE], rb8[8];
+  double ra[AE], rbv[BE];
   auto gload = [&](int kb) {
     const int k0 = kb * KB;
 #pragma unroll
     for (int e = 0; e < AE; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
-    const bool b_ok = br < 16 * mtb;
     const double* ar = Ac + (size_t)(k0 + bk) * R + row0 + br;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) rb8[e] = b_ok ? ar[e] : 0.0;
+    for (int e = 0; e < BE; ++e) rbv[e] = ar[e];
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < AE; ++e) sA[buf][(ak + e) * LDA + aj] = ra[e];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sB[buf][bk * LDB + br + e] = rb8[e];
+    for (int e = 0; e < BE; ++e) sB[buf][bk * LDB + br + e] = rbv[e];
   };
-  // wave w: TE = 64 -> entries 16w..16w+15, row tiles 0..mtb-1;
-  //         TE = 16 -> entries 0..15, row tiles w and w+4
+  // wave w: TE = 64 -> entries 16w..16w+15, every row tile;
+  //         TE = 16 -> entries 0..15, row tiles w, w+4
   const int ebase = (TE == 64) ? 16 * w : 0;
   auto tile_of = [&](int r) { return (TE == 64) ? r : w + 4 * r; };
   vfx_d4 acc[NACC];
 #pragma unroll
   for (int r = 0; r < NACC; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
   constexpr int NKB = KD / KB;
+  __syncthreads();  // the previous item is done with the LDS buffers
   gload(0);
   lstore(0);
   __syncthreads();
@@ -539,21 +487,18 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
     for (int ks = 0; ks < KB / 4; ++ks) {
       const int k = 4 * ks + lk;
       const double a = sA[buf][k * LDA + ebase + li];
+      double bv[NACC];
 #pragma unroll
-      for (int r = 0; r < NACC; ++r) {
-        const int rt = tile_of(r);
-        if (rt < mtb)
-          acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sB[buf][k * LDB + 16 * rt + li], acc[r], 0, 0, 0);
-      }
+      for (int r = 0; r < NACC; ++r) bv[r] = sB[buf][k * LDB + 16 * tile_of(r) + li];
+#pragma unroll
+      for (int r = 0; r < NACC; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[r], acc[r], 0, 0, 0);
     }
     if (kb + 1 < NKB) lstore(buf ^ 1);
     __syncthreads();
   }
 #pragma unroll
   for (int r = 0; r < NACC; ++r) {
-    const int rt = tile_of(r);
-    if (rt >= mtb) continue;
-    const int row = row0 + 16 * rt + li;
+    const int row = row0 + 16 * tile_of(r) + li;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ent = ebase + lk + 4 * e;
@@ -571,70 +516,473 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
   }  // work items
 }
 
-// With Y given, the near field is also finished here: the per-pair partials
-// of the leaf's list-1 entries are summed in list order (deterministic) and
-// the log(h) a_0 term added; V is then written, else it is accumulated.
+// -------------------------------------------------------------------------
+// Near field in low-rank form, for the configurations c whose operator
+// factorises as Q_c W_c (rank R_c <= 64, padded to a multiple of 16).  A
+// work item is a tile of <= 64 list-1 pairs of one configuration:
+//   Z = X W_c^T  (pairs x R_c: the source leaf values times the row factor),
+//   Y = Z Q_c^T  (pairs x n),
+// both as FP64 MFMA tile products with the operands staged through LDS in
+// double-buffered K blocks; Z stays in LDS between the two.  Wave w owns the
+// pairs 16w..16w+15 of the tile.  Persistent, XCD-aware item order as in
+// k_gemm (items are configuration-major, so an XCD's L2 holds the factors
+// of the few configurations it works on).
+constexpr int kLrLDX = 64 + 4, kLrLDW = kNearLrMax + 4, kLrLDZ = kNearLrMax + 1;
+
+// Phase 1 for MT1 = R_c/16 rank tiles (compile-time, so the MFMA sequence
+// has no per-tile branches); leaves Z in sZ[pair][rank].
+template <int KD, int MT1>
+__device__ __forceinline__ void near_lr_phase1(const double* __restrict__ xsrc, bool a_ok,
+                                               const double* __restrict__ Wc, double* sX, double* sW, double* sZ) {
+  constexpr int KB = 16, LM = kNearLrMax;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int aj = tid & 63, ak = (tid >> 6) * 4;  // entry aj, k = ak..ak+3
+  const int bk = tid >> 4, ba = (tid & 15) * 4;  // factor: k = bk, ranks ba..ba+3
+  const bool b_ok = ba < 16 * MT1;
+  double ra[4], rw[4];
+  auto gload = [&](int kb) {
+    const int k0 = kb * KB;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
+    const double* wr = Wc + (size_t)(k0 + bk) * LM + ba;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rw[e] = b_ok ? wr[e] : 0.0;
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sX[(buf * KB + ak + e) * kLrLDX + aj] = ra[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sW[(buf * KB + bk) * kLrLDW + ba + e] = rw[e];
+  };
+  vfx_d4 acc[MT1];
+#pragma unroll
+  for (int r = 0; r < MT1; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
+  constexpr int NKB = KD / KB;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kb = 0; kb < NKB; ++kb) {
+    const int buf = kb & 1;
+    if (kb + 1 < NKB) gload(kb + 1);
+#pragma unroll
+    for (int ks = 0; ks < KB / 4; ++ks) {
+      const int k = 4 * ks + lk;
+      const double a = sX[(buf * KB + k) * kLrLDX + 16 * w + li];
+      double bv[MT1];
+#pragma unroll
+      for (int r = 0; r < MT1; ++r) bv[r] = sW[(buf * KB + k) * kLrLDW + 16 * r + li];
+#pragma unroll
+      for (int r = 0; r < MT1; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[r], acc[r], 0, 0, 0);
+    }
+    if (kb + 1 < NKB) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // Z rows of this wave's pairs: D[lk + 4e][16 r + li]
+#pragma unroll
+  for (int r = 0; r < MT1; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sZ[(16 * w + lk + 4 * e) * kLrLDZ + 16 * r + li] = acc[r][e];
+}
+
+template <int KD>
+__global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __restrict__ t_cfg,
+                                                    const int* __restrict__ t_first, const int* __restrict__ t_count,
+                                                    const int* __restrict__ src, const int* __restrict__ lr_R,
+                                                    const double* __restrict__ W, const double* __restrict__ Q,
+                                                    const double* __restrict__ X, double* __restrict__ Y) {
+  constexpr int LM = kNearLrMax;  // 64
+  constexpr int KB = 16;          // source nodes per phase-1 block
+  constexpr int QB = 8;           // rank indices per phase-2 block
+  constexpr int NRT = KD / 16;    // output row tiles
+  static_assert(2 * QB * KD <= 2 * KB * (kLrLDX + kLrLDW), "phase-2 staging must fit the phase-1 buffers");
+  __shared__ double sbuf[2 * KB * (kLrLDX + kLrLDW)];
+  __shared__ double sZ[64 * kLrLDZ];
+  double* sX = sbuf;                    // [2][KB][kLrLDX]
+  double* sW = sbuf + 2 * KB * kLrLDX;  // [2][KB][kLrLDW]
+  double* sQ = sbuf;                    // [2][QB][KD] (phase 2)
+  const int nb = gridDim.x, bb = blockIdx.x;
+  const int x = bb & 7;
+  const int q = nitems >> 3, rr = nitems & 7;
+  const int xfirst = x * q + min(x, rr), xcount = q + (x < rr ? 1 : 0);
+  const int xwgs = (nb - x + 7) >> 3;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int j = bb >> 3; j < xcount; j += xwgs) {
+    const int tile = xfirst + j;
+    const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
+    const int R = lr_R[c];
+    const double* Wc = W + (size_t)c * KD * LM;
+    const double* Qc = Q + (size_t)c * LM * KD;
+    const int aj = tid & 63;
+    const bool a_ok = aj < np;
+    const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
+    __syncthreads();  // the previous item is done with sbuf and sZ
+    switch (R >> 4) {
+      case 1: near_lr_phase1<KD, 1>(xsrc, a_ok, Wc, sX, sW, sZ); break;
+      case 2: near_lr_phase1<KD, 2>(xsrc, a_ok, Wc, sX, sW, sZ); break;
+      case 3: near_lr_phase1<KD, 3>(xsrc, a_ok, Wc, sX, sW, sZ); break;
+      default: near_lr_phase1<KD, 4>(xsrc, a_ok, Wc, sX, sW, sZ); break;
+    }
+    // ---- phase 2: Y = Z Q^T
+    constexpr int QE = KD / 32;
+    const int qa = tid >> 5, qr = (tid & 31) * QE;  // rank qa, rows qr..qr+QE-1
+    double rq[QE];
+    auto gload2 = [&](int qb) {
+      const double* qrow = Qc + (size_t)(qb * QB + qa) * KD + qr;
+#pragma unroll
+      for (int e = 0; e < QE; ++e) rq[e] = qrow[e];
+    };
+    auto lstore2 = [&](int buf) {
+#pragma unroll
+      for (int e = 0; e < QE; ++e) sQ[(buf * QB + qa) * KD + qr + e] = rq[e];
+    };
+    vfx_d4 acc2[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) acc2[r] = vfx_d4{0, 0, 0, 0};
+    const int nqb = R / QB;
+    gload2(0);
+    __syncthreads();  // phase-1 reads of sbuf done; sZ complete
+    lstore2(0);
+    __syncthreads();
+    for (int qb = 0; qb < nqb; ++qb) {
+      const int buf = qb & 1;
+      if (qb + 1 < nqb) gload2(qb + 1);
+#pragma unroll
+      for (int ks = 0; ks < QB / 4; ++ks) {
+        const int kk = 4 * ks + lk;
+        const double a = sZ[(16 * w + li) * kLrLDZ + qb * QB + kk];
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+          acc2[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sQ[(buf * QB + kk) * KD + 16 * r + li], acc2[r], 0, 0, 0);
+      }
+      if (qb + 1 < nqb) lstore2(buf ^ 1);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+      const int row = 16 * r + li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ent = 16 * w + lk + 4 * e;
+        if (ent < np) Y[(size_t)(p0 + ent) * KD + row] = acc2[r][e];
+      }
+    }
+  }  // work items
+}
+
+// -------------------------------------------------------------------------
+// Upward pass without the level-by-level chain.  The multipole of a non-leaf
+// box B (level >= 2) about its own centre is the sum, over the leaves L below
+// it, of the leaf multipoles shifted to B.  The shifted coefficients b_l
+// depend only on a_k with k <= l, so they are exact (up to rounding) for any
+// number of levels between L and B.  Scaled form (a_k h_L^-k, b_l h_B^-l):
+//   b_0 = a_0,  b_l = w^l [ sum_{1<=k<=l} C(l-1,k-1) (r/w)^k a_k - a_0/l ],
+// w = (c_L - c_B)/h_B, r = h_L/h_B.  One lane per (box, leaf) pair; a group
+// of <= 8 boxes and <= 64 pairs per wave; per-box sums in pair order through
+// LDS (deterministic).  Slices of a box with more than 64 pairs write
+// partial sums, added in slice order by k_up_sum.
+template <int PM, bool EXACT>
+__global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int* __restrict__ grp, const int* __restrict__ up_box,
+                                           const int* __restrict__ up_ptr, const int* __restrict__ up_src,
+                                           const int* __restrict__ up_pos, const int* __restrict__ box_level,
+                                           const double* __restrict__ box_cx, const double* __restrict__ box_cy,
+                                           const double* __restrict__ pasT, double2* __restrict__ mpole,
+                                           double2* __restrict__ part) {
+  const int P = EXACT ? PM : Prt;
+  __shared__ double2 s_o[8 * 64];
+  const int* gg = grp + 5 * blockIdx.x;
+  const int u0 = gg[0], u1 = gg[1], e0 = gg[2], e1 = gg[3], slot = gg[4];
+  const int lane = threadIdx.x;
+  const int e = e0 + lane;
+  const bool act = e < e1;
+  const int src = act ? up_src[e] : up_box[u0];
+  const int tgt = up_box[act ? up_pos[e] : u0];
+  const int ls = box_level[src], lt = box_level[tgt];
+  const double hb = box_side(root_size, lt);
+  const double2 w = act ? make_double2((box_cx[src] - box_cx[tgt]) / hb, (box_cy[src] - box_cy[tgt]) / hb)
+                        : make_double2(0.5, 0.5);
+  const double r = act ? ldexp(1.0, lt - ls) : 1.0;
+  const double ww = w.x * w.x + w.y * w.y;
+  const double2 q = make_double2(r * w.x / ww, -r * w.y / ww);  // r / w
+  double2 s[PM];
+  {
+    double2 pw = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < PM; ++k) {
+      const double2 a = (act && k < P) ? mpole[(size_t)src * P + k] : make_double2(0.0, 0.0);
+      s[k] = cmul(pw, a);
+      pw = cmul(pw, q);
+    }
+  }
+  const double2 a0 = s[0];
+  double2 wl = make_double2(1.0, 0.0);
+  const int NC = (P + 7) / 8;
+#pragma unroll
+  for (int c = 0; c < (PM + 7) / 8; ++c) {
+    if (c >= NC) break;
+    __syncthreads();
+    // the eight outputs of the chunk accumulate side by side (k outer)
+    double ur[8], ui[8];
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) {
+      const int l = 8 * c + lc;
+      const double il = l > 0 ? 1.0 / (double)l : 0.0;  // compile-time constant
+      ur[lc] = -a0.x * il;
+      ui[lc] = -a0.y * il;
+    }
+#pragma unroll
+    for (int k = 1; k < PM; ++k) {
+#pragma unroll
+      for (int lc = 0; lc < 8; ++lc) {
+        const int l = 8 * c + lc;
+        if (k <= l && l < P) {
+          const double cf = pasT[l * P + k];
+          ur[lc] += cf * s[k].x;
+          ui[lc] += cf * s[k].y;
+        }
+      }
+    }
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) {
+      const int l = 8 * c + lc;
+      double2 out = make_double2(0.0, 0.0);
+      if (l == 0) {
+        out = a0;
+      } else if (l < P) {
+        wl = cmul(wl, w);
+        out = cmul(wl, make_double2(ur[lc], ui[lc]));
+      }
+      s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int lc = lane & 7, seg = lane >> 3;
+    const int uu = u0 + seg, l = 8 * c + lc;
+    if (uu < u1 && l < P) {
+      const int q0 = max(up_ptr[uu], e0), q1 = min(up_ptr[uu + 1], e1);
+      const double2 sv = seg_sum(s_o + lc * 64, q0 - e0, q1 - e0);
+      const double re = sv.x, im = sv.y;
+      if (slot < 0)
+        mpole[(size_t)up_box[uu] * P + l] = make_double2(re, im);
+      else
+        part[(size_t)slot * P + l] = make_double2(re, im);
+    }
+  }
+}
+
+// Multipoles of the split boxes: slices added in slice order.
+__global__ void __launch_bounds__(64) k_up_sum(int P, const int* __restrict__ split, const double2* __restrict__ part,
+                                               double2* __restrict__ mpole) {
+  const int* sp = split + 3 * blockIdx.x;
+  const int l = threadIdx.x;
+  if (l >= P) return;
+  double re = 0.0, im = 0.0;
+  for (int j = 0; j < sp[2]; ++j) {
+    const double2 v = part[(size_t)(sp[1] + j) * P + l];
+    re += v.x;
+    im += v.y;
+  }
+  mpole[(size_t)sp[0] * P + l] = make_double2(re, im);
+}
+
+__device__ __forceinline__ double2 cpow(double2 z, int k) {
+  double2 r = make_double2(1.0, 0.0);
+  while (k) {
+    if (k & 1) r = cmul(r, z);
+    z = cmul(z, z);
+    k >>= 1;
+  }
+  return r;
+}
+
+// -------------------------------------------------------------------------
+// Far field and the near-field reduction, one work-group per leaf, thread i =
+// node i.  The leaf's local expansion is its own (M2L + P2L) part plus the
+// own parts of its ancestors at levels >= 2 shifted directly to the leaf
+// (scaled form, w = (c_b - c_A)/h_A, r = h_b/h_A):
+//   c_l += (r/w)^l sum_{k>=l} C(k,l) w^k b_k(A)
+// (an exact polynomial shift, so equal up to rounding to the level-by-level
+// downward pass).  Then L2P by Horner in the scaled node position, M2P for
+// list 3 by Horner in h_w/z, the list-1 sums of the near-field GEMM (in
+// list order, deterministic) and the log(h) a_0 terms of the near field.
+// The per-leaf lists are staged through LDS in two rounds of independent
+// loads (indices, then the data they point to) so their latencies overlap.
+constexpr int kFarCap = 8;  // ancestors / list-3 entries per staging round
+
 __global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, const int* __restrict__ leaf_box,
-                                             const int* __restrict__ box_level, const double* __restrict__ box_cx,
+                                             const int* __restrict__ box_level, const int* __restrict__ anc_ptr,
+                                             const int* __restrict__ anc, const double* __restrict__ box_cx,
                                              const double* __restrict__ box_cy, const double* __restrict__ t,
                                              const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
-                                             const double2* __restrict__ l2p, const double2* __restrict__ local,
+                                             const double* __restrict__ pasL, const double2* __restrict__ local,
                                              const double2* __restrict__ mpole, const int* __restrict__ l1_ptr,
-                                             const int* __restrict__ l1_src, const int* __restrict__ l1_slot,
+                                             const int* __restrict__ l1_srcbox, const int* __restrict__ l1_slot,
                                              const double* __restrict__ Y, double* __restrict__ V) {
-  __shared__ double2 s_a[64];
+  __shared__ double2 s_loc[64];
+  __shared__ double2 s_w[kFarCap * 64];
+  __shared__ double2 s_part[kFarCap * 64];
+  __shared__ double2 s_m3[kFarCap * 64];
+  __shared__ double s_c3[3 * kFarCap];
+  __shared__ int s_slot[64], s_sbox[64], s_anc[kFarCap], s_l3[kFarCap];
+  __shared__ double s_a0[64];
   const int n = K * K;
+  const int nt = blockDim.x;
   const int leaf = blockIdx.x;
   const int i = threadIdx.x;
   const int b = leaf_box[leaf];
   const int lev = box_level[b];
   const double h = box_side(root_size, lev);
-  double acc = 0.0;
-  if (Y != nullptr && i < n) {
-    double yn = 0.0, lg = 0.0;
-    for (int e = l1_ptr[leaf]; e < l1_ptr[leaf + 1]; ++e) {
-      yn += Y[(size_t)l1_slot[e] * n + i];
-      lg += mpole[(size_t)leaf_box[l1_src[e]] * P].x;
+  const int e0 = l1_ptr[leaf], n1 = l1_ptr[leaf + 1] - e0;
+  const int a0 = anc_ptr[leaf], m = lev >= 2 ? anc_ptr[leaf + 1] - a0 : 0;
+  const int f0 = l3_ptr[leaf], n3 = l3_ptr[leaf + 1] - f0;
+  const int cap = min(kFarCap, nt / P);
+  const int ii = i < n ? i : 0;
+  const double tx = 0.5 * t[ii / K], ty = 0.5 * t[ii % K];
+  const double bcx = box_cx[b], bcy = box_cy[b];
+  const int A = i / P, k = i - A * P;  // (ancestor or list-3 entry, coefficient) of this thread
+  // round 1: list indices
+  if (i < n1) {
+    s_slot[i] = l1_slot[e0 + i];
+    s_sbox[i] = l1_srcbox[e0 + i];
+  }
+  if (i < kFarCap && i < m) s_anc[i] = anc[a0 + i];
+  if (i < kFarCap && i < n3) s_l3[i] = l3_src[f0 + i];
+  __syncthreads();
+  // round 2: the data (first chunk of each list)
+  double2 q = make_double2(0.0, 0.0);  // r/w of this thread's ancestor
+  auto stage_anc = [&](int c0) {
+    if (A < min(cap, m - c0)) {
+      const int id = s_anc[A];
+      const int la = box_level[id];
+      const double hA = box_side(root_size, la);
+      const double2 wA = make_double2((bcx - box_cx[id]) / hA, (bcy - box_cy[id]) / hA);
+      const double rA = ldexp(1.0, la - lev);
+      const double ww = wA.x * wA.x + wA.y * wA.y;
+      q = make_double2(rA * wA.x / ww, -rA * wA.y / ww);
+      s_w[A * 64 + k] = cmul(cpow(wA, k), local[(size_t)id * P + k]);
     }
-    acc = h * h * yn + log(h) * lg;
-  }
-  if (lev >= 2) {
-    if (i < P) s_a[i] = local[(size_t)b * P + i];
-    __syncthreads();
-    if (i < n)
-      for (int l = 0; l < P; ++l) {
-        const double2 z = l2p[(size_t)l * n + i];
-        acc += z.x * s_a[l].x - z.y * s_a[l].y;
+  };
+  auto stage_l3 = [&](int c0) {
+    if (A < min(cap, n3 - c0)) {
+      const int w = s_l3[A];
+      s_m3[A * 64 + k] = mpole[(size_t)w * P + k];
+      if (k == 0) {
+        s_c3[3 * A] = box_side(root_size, box_level[w]);
+        s_c3[3 * A + 1] = box_cx[w];
+        s_c3[3 * A + 2] = box_cy[w];
       }
+    }
+  };
+  if (lev >= 2 && i < P) s_loc[i] = local[(size_t)b * P + i];
+  stage_anc(0);
+  stage_l3(0);
+  double acc = 0.0;
+  {
+    // (a leaf has at most one list-1 entry per configuration: n1 <= 33)
+    double yn = 0.0;
+    if (i < n1) s_a0[i] = mpole[(size_t)s_sbox[i] * P].x;
+    if (i < n) {
+#pragma unroll 4
+      for (int e = 0; e < n1; ++e) yn += Y[(size_t)s_slot[e] * n + i];
+    }
+    acc = h * h * yn;
   }
-  const double xi = box_cx[b] + 0.5 * h * t[(i < n ? i : 0) / K];
-  const double yi = box_cy[b] + 0.5 * h * t[(i < n ? i : 0) % K];
-  for (int e = l3_ptr[leaf]; e < l3_ptr[leaf + 1]; ++e) {
-    const int w = l3_src[e];
-    __syncthreads();
-    if (i < P) s_a[i] = mpole[(size_t)w * P + i];
+  __syncthreads();
+  {
+    double lg = 0.0;
+    for (int e = 0; e < n1; ++e) lg += s_a0[e];
+    acc += log(h) * lg;
+  }
+  // local expansion of the leaf: own part plus the shifted ancestor parts
+  if (lev >= 2) {
+    for (int c0 = 0; c0 < m; c0 += cap) {
+      const int cm = min(cap, m - c0);
+      if (c0 > 0) {
+        __syncthreads();
+        if (i < cm) s_anc[i] = anc[a0 + c0 + i];
+        __syncthreads();
+        stage_anc(c0);
+        __syncthreads();
+      }
+      if (A < cm) {
+        double ur = 0.0, ui = 0.0, ur2 = 0.0, ui2 = 0.0;
+        int kk = k;
+        for (; kk + 1 < P; kk += 2) {
+          const double cf = pasL[k * P + kk], cf2 = pasL[k * P + kk + 1];
+          ur += cf * s_w[A * 64 + kk].x;
+          ui += cf * s_w[A * 64 + kk].y;
+          ur2 += cf2 * s_w[A * 64 + kk + 1].x;
+          ui2 += cf2 * s_w[A * 64 + kk + 1].y;
+        }
+        if (kk < P) {
+          const double cf = pasL[k * P + kk];
+          ur += cf * s_w[A * 64 + kk].x;
+          ui += cf * s_w[A * 64 + kk].y;
+        }
+        s_part[A * 64 + k] = cmul(cpow(q, k), make_double2(ur + ur2, ui + ui2));
+      }
+      __syncthreads();
+      if (i < P) {
+        double2 c = s_loc[i];
+        for (int j = 0; j < cm; ++j) {
+          c.x += s_part[j * 64 + i].x;
+          c.y += s_part[j * 64 + i].y;
+        }
+        s_loc[i] = c;
+      }
+    }
     __syncthreads();
     if (i < n) {
-      const double hw = box_side(root_size, box_level[w]);
-      const double zx = xi - box_cx[w], zy = yi - box_cy[w];
-      const double r2 = zx * zx + zy * zy;
-      // zeta = hw / z
-      const double zr = hw * zx / r2, zi = -hw * zy / r2;
-      double sr = 0.0, si = 0.0;  // Horner: sum_{k>=1} a_k zeta^k
-      for (int k = P - 1; k >= 1; --k) {
-        const double ar = sr + s_a[k].x, ai = si + s_a[k].y;
-        sr = ar * zr - ai * zi;
-        si = ar * zi + ai * zr;
+      double2 u = s_loc[P - 1];
+      for (int l = P - 2; l >= 0; --l) {
+        const double ur = u.x * tx - u.y * ty, ui = u.x * ty + u.y * tx;
+        u = make_double2(ur + s_loc[l].x, ui + s_loc[l].y);
       }
-      acc += s_a[0].x * 0.5 * log(r2) + sr;
+      acc += u.x;
     }
   }
-  if (i < n) {
-    if (Y != nullptr)
-      V[(size_t)leaf * n + i] = kInv2Pi * acc;
-    else
-      V[(size_t)leaf * n + i] += kInv2Pi * acc;
+  // M2P for list 3
+  const double xi = bcx + h * tx;
+  const double yi = bcy + h * ty;
+  for (int c0 = 0; c0 < n3; c0 += cap) {
+    const int cm = min(cap, n3 - c0);
+    if (c0 > 0) {
+      __syncthreads();
+      if (i < cm) s_l3[i] = l3_src[f0 + c0 + i];
+      __syncthreads();
+      stage_l3(c0);
+      __syncthreads();
+    }
+    if (i < n)
+      for (int j = 0; j < cm; j += 2) {
+        // two entries at a time (the second a zero expansion at distance 1
+        // when cm is odd), their Horner chains interleaved
+        const bool two = j + 1 < cm;
+        const int j2 = two ? j + 1 : j;
+        const double hw = s_c3[3 * j], hw2 = s_c3[3 * j2];
+        const double zx = xi - s_c3[3 * j + 1], zy = yi - s_c3[3 * j + 2];
+        const double zx2 = xi - s_c3[3 * j2 + 1], zy2 = yi - s_c3[3 * j2 + 2];
+        const double r2 = zx * zx + zy * zy, r22 = zx2 * zx2 + zy2 * zy2;
+        // zeta = hw / z
+        const double iv = hw / r2, iv2 = hw2 / r22;
+        const double zr = zx * iv, zi = -zy * iv, zr2 = zx2 * iv2, zi2 = -zy2 * iv2;
+        const double2* a = s_m3 + j * 64;
+        const double2* a2 = s_m3 + j2 * 64;
+        const double m2 = two ? 1.0 : 0.0;
+        double sr = 0.0, si = 0.0, sr2 = 0.0, si2 = 0.0;  // Horner: sum_{k>=1} a_k zeta^k
+        for (int kk = P - 1; kk >= 1; --kk) {
+          const double ar = sr + a[kk].x, ai = si + a[kk].y;
+          const double ar2 = sr2 + m2 * a2[kk].x, ai2 = si2 + m2 * a2[kk].y;
+          sr = ar * zr - ai * zi;
+          si = ar * zi + ai * zr;
+          sr2 = ar2 * zr2 - ai2 * zi2;
+          si2 = ar2 * zi2 + ai2 * zr2;
+        }
+        acc += a[0].x * 0.5 * log(r2) + sr;
+        if (two) acc += a2[0].x * 0.5 * log(r22) + sr2;
+      }
   }
+  if (i < n) V[(size_t)leaf * n + i] = kInv2Pi * acc;
 }
 
 // -------------------------------------------------------------------------
@@ -669,6 +1017,9 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.AbarT, T.AbarT);
   UP(D.cbar, T.cbar);
   UP(D.near, T.near);
+  UP(D.lr_R, T.lr_R);
+  UP(D.lr_W, T.lr_W);
+  UP(D.lr_Q, T.lr_Q);
   UP(D.p2l_gemm, T.p2l_gemm);
   UP(D.p2m_gemm, T.p2m_gemm);
   UP(D.pas_m2l, T.pas_m2l);
@@ -713,7 +1064,8 @@ void free_tables_device(Context* c) {
   void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
-                  D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t};
+                  D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
+                  D.lr_R,     D.lr_W,     D.lr_Q};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   D = DeviceTables();
@@ -735,6 +1087,7 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.l1_ptr, H.l1_ptr);
   UP(D.l1_src, H.l1_src);
   UP(D.l1_cfg, H.l1_cfg);
+  UP(D.l1_srcbox, H.l1_srcbox);
   UP(D.l2_ptr, H.l2_ptr);
   UP(D.l2_src, H.l2_src);
   UP(D.l2_off, H.l2_off);
@@ -742,6 +1095,15 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.m2l_grp, H.m2l_grp);
   UP(D.l3_ptr, H.l3_ptr);
   UP(D.l3_src, H.l3_src);
+  UP(D.anc_ptr, H.anc_ptr);
+  UP(D.anc, H.anc);
+  UP(D.up_box, H.up_box);
+  UP(D.up_ptr, H.up_ptr);
+  UP(D.up_src, H.up_src);
+  UP(D.up_pos, H.up_pos);
+  UP(D.up_grp, H.up_grp);
+  UP(D.up_split, H.up_split);
+  if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P));
   UP(D.l4_ptr, H.l4_ptr);
   UP(D.l4_src, H.l4_src);
   UP(D.l4_cfg, H.l4_cfg);
@@ -750,6 +1112,9 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.nt_cfg, H.nt_cfg);
   UP(D.nt_first, H.nt_first);
   UP(D.nt_count, H.nt_count);
+  UP(D.nl_cfg, H.nl_cfg);
+  UP(D.nl_first, H.nl_first);
+  UP(D.nl_count, H.nl_count);
   UP(D.p4_src, H.p4_src);
   UP(D.l4_slot, H.l4_slot);
   UP(D.t4_cfg, H.t4_cfg);
@@ -786,7 +1151,9 @@ void free_plan_device(Plan* p) {
                   D.nt_cfg,    D.nt_first,   D.nt_count, D.near_y,     D.p4_src,   D.l4_slot,  D.t4_cfg,
                   D.t4_first,  D.t4_count,   D.p2l_y,    D.cut_leaf,   D.ext_ptr,  D.ext_tgt,  D.pinv_ptr,
                   D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local,    D.t0_cfg,   D.t0_first,
-                  D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp};
+                  D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp,  D.up_box,   D.up_ptr,   D.up_src,
+                  D.up_pos,    D.up_split,   D.up_grp,   D.up_part,  D.anc_ptr,  D.anc,
+                  D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -802,33 +1169,51 @@ void free_plan_device(Plan* p) {
   p->side = nullptr;
 }
 
-template <int KD, int EPI, int TE>
-static void launch_gemm(int items, int MT, const int* cfg, const int* first, const int* count, const int* src,
+template <int KD, int EPI, int TE, int MTB>
+static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
                         const double* A, const double* X, double* Y, int P2, double root, const int* leaf_box,
                         const int* box_level, hipStream_t s, int max_wgs) {
+  const int items = ntiles * (MT / MTB);
   const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
-  hipLaunchKernelGGL((k_gemm<KD, EPI, TE>), dim3(grid), dim3(256), 0, s, items, MT, cfg, first, count, src, A, X, Y,
-                     P2, root, leaf_box, box_level);
+  hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid), dim3(256), 0, s, items, MT, cfg, first, count, src, A,
+                     X, Y, P2, root, leaf_box, box_level);
 }
 
-// ntiles tiles of <= TE entries; each is split into ceil(MT/8) row blocks;
-// max_wgs > 0 bounds the grid (the work-groups then loop over the items)
-template <int EPI, int TE>
-static void gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
-                 const double* A, const double* X, double* Y, hipStream_t s, int max_wgs = 0, int P2 = 0,
-                 double root = 0, const int* leaf_box = nullptr, const int* box_level = nullptr) {
+// Dense near-field tables: MT = n/16 row tiles (1, 4, 9 or 16 for K = 4, 8,
+// 12, 16), in blocks of MTB = 1, 4, 9, 8.
+static void near_gemm(int n, int ntiles, const int* cfg, const int* first, const int* count, const int* src,
+                      const double* A, const double* X, double* Y, hipStream_t s, int max_wgs) {
   if (ntiles <= 0) return;
-  const int items = ntiles * ((MT + 7) / 8);
-#define VFX_GEMM_CASE(KDV)                                                                                   \
-  launch_gemm<KDV, EPI, TE>(items, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, \
-                            max_wgs)
+  const int MT = n / 16;
   switch (n) {
-    case 16: VFX_GEMM_CASE(16); break;
-    case 64: VFX_GEMM_CASE(64); break;
-    case 144: VFX_GEMM_CASE(144); break;
-    default: VFX_GEMM_CASE(256); break;
+    case 16: launch_gemm<16, 0, 64, 1>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
+    case 64: launch_gemm<64, 0, 64, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
+    case 144: launch_gemm<144, 0, 64, 9>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
+    default: launch_gemm<256, 0, 64, 8>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
   }
-#undef VFX_GEMM_CASE
+}
+
+// P2L (EPI 0, TE 64) and P2M (EPI 1, TE 16) tables: rows padded to a
+// multiple of 64, so MT is 4 or 8 and one row block covers it.
+template <int EPI, int TE>
+static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count,
+                           const int* src, const double* A, const double* X, double* Y, hipStream_t s, int P2 = 0,
+                           double root = 0, const int* leaf_box = nullptr, const int* box_level = nullptr) {
+  if (ntiles <= 0) return;
+#define VFX_EXP_CASE(KDV)                                                                                       \
+  do {                                                                                                          \
+    if (MT == 4)                                                                                                \
+      launch_gemm<KDV, EPI, TE, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0); \
+    else                                                                                                        \
+      launch_gemm<KDV, EPI, TE, 8>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0); \
+  } while (0)
+  switch (n) {
+    case 16: VFX_EXP_CASE(16); break;
+    case 64: VFX_EXP_CASE(64); break;
+    case 144: VFX_EXP_CASE(144); break;
+    default: VFX_EXP_CASE(256); break;
+  }
+#undef VFX_EXP_CASE
 }
 
 constexpr int kNearWgs = 512;
@@ -849,8 +1234,7 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   const DeviceTables& DT = c->D;
   const DevicePlan& D = p->D;
   const int n = T.n, P = T.p + 1, L = H.L;
-  const bool big = P > 32;
-  constexpr int kMaxTimed = 4096;
+    constexpr int kMaxTimed = 4096;
   constexpr int NE = Plan::kEvents;
   const bool timed = p->timing && p->n_timed < kMaxTimed;
   const size_t ev0 = (size_t)p->n_timed * NE;
@@ -891,36 +1275,53 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
                        DT.t, DT.AbarT, DT.cbar, D.leaf_box, D.box_cx, D.box_cy, D.box_level, f_cut, fe);
   VFX_HIP(hipGetLastError());
   MARK(1, s);
-  // multipoles of the leaves (start of the critical chain)
-  gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids, DT.p2m_gemm,
-              fe, (double*)D.mpole, s, 0, 2 * P, T.root_size, D.leaf_box, D.box_level);
-  // fork: near field on the side stream, concurrent with the upward pass,
-  // M2L/P2L and the downward pass on the caller's stream.  Its grid is
+  // fork: near field on the side stream, concurrent with P2M, the upward
+  // pass and M2L/P2L on the caller's stream.  Its grid is
   // bounded (about two work-groups per CU, looping over the tiles) so the
   // latency-bound tree kernels keep CU slots.
   VFX_HIP(hipEventRecord(p->fork_ev, s));
   VFX_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
   MARK(5, p->side);
-  gemm<0, 64>(n, (int)H.nt_cfg.size(), n / 16, D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y,
-              p->side, kNearWgs);
+  if (!H.nl_cfg.empty()) {
+    const int items = (int)H.nl_cfg.size();
+    hipLaunchKernelGGL(k_near_lr<256>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, D.nl_cfg,
+                       D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y);
+  }
+  near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
+            kNearWgs);
   VFX_HIP(hipGetLastError());
   MARK(6, p->side);
   VFX_HIP(hipEventRecord(p->join_ev, p->side));
-  for (int l = H.nlev - 2; l >= 2; --l) {
-    const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
-    if (cnt <= 0) continue;
-    if (big)
-      hipLaunchKernelGGL(k_m2m<64>, dim3(cnt), dim3(64), 0, s, P, first, D.box_child0, DT.pas_m2m, DT.m2m_in,
-                         DT.m2m_out, D.mpole);
+  // multipoles of the leaves
+  expansion_gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
+                        DT.p2m_gemm, fe, (double*)D.mpole, s, 2 * P, T.root_size, D.leaf_box, D.box_level);
+  if (!H.up_grp.empty()) {
+    const int ng = (int)H.up_grp.size() / 5;
+#define VFX_UP(PMV, EX)                                                                                            \
+  hipLaunchKernelGGL((k_up<PMV, EX>), dim3(ng), dim3(64), 0, s, P, T.root_size, D.up_grp, D.up_box, D.up_ptr,     \
+                     D.up_src, D.up_pos, D.box_level, D.box_cx, D.box_cy, DT.pas_m2m_t, D.mpole, D.up_part)
+    if (P == 21)
+      VFX_UP(21, true);
+    else if (P == 25)
+      VFX_UP(25, true);
+    else if (P == 31)
+      VFX_UP(31, true);
+    else if (P == 41)
+      VFX_UP(41, true);
+    else if (P <= 32)
+      VFX_UP(32, false);
     else
-      hipLaunchKernelGGL(k_m2m<32>, dim3(cnt), dim3(64), 0, s, P, first, D.box_child0, DT.pas_m2m, DT.m2m_in,
-                         DT.m2m_out, D.mpole);
+      VFX_UP(64, false);
+#undef VFX_UP
+    if (!H.up_split.empty())
+      hipLaunchKernelGGL(k_up_sum, dim3((int)H.up_split.size() / 3), dim3(64), 0, s, P, D.up_split, D.up_part,
+                         D.mpole);
   }
   VFX_HIP(hipGetLastError());
   MARK(2, s);
   if (H.nlev > 2) {
-    gemm<0, 64>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src, DT.p2l_gemm,
-            fe, D.p2l_y, s);
+    expansion_gemm<0, 64>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src,
+                          DT.p2l_gemm, fe, D.p2l_y, s);
     const int ng = (int)H.m2l_grp.size() - 1;
     if (ng > 0) {
 #define VFX_M2L(PMV)                                                                                             \
@@ -949,23 +1350,14 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   }
   VFX_HIP(hipGetLastError());
   MARK(3, s);
-  for (int l = 3; l < H.nlev; ++l) {
-    const int first = H.level_start[l], cnt = H.level_start[l + 1] - first;
-    if (cnt <= 0) continue;
-    if (big)
-      hipLaunchKernelGGL(k_l2l<64>, dim3(cnt), dim3(64), 0, s, P, first, D.box_parent, D.box_child0, DT.pas_l2l,
-                         DT.l2l_in, DT.l2l_out, D.local);
-    else
-      hipLaunchKernelGGL(k_l2l<32>, dim3(cnt), dim3(64), 0, s, P, first, D.box_parent, D.box_child0, DT.pas_l2l,
-                         DT.l2l_in, DT.l2l_out, D.local);
-  }
+  // (the downward shifts are applied per leaf in the far-field kernel)
   VFX_HIP(hipGetLastError());
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(7, s);
   hipLaunchKernelGGL(k_far, dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box, D.box_level,
-                     D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.l2p, D.local, D.mpole, D.l1_ptr, D.l1_src,
-                     D.l1_slot, D.near_y, V);
+                     D.anc_ptr, D.anc, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.pas_l2l_t, D.local,
+                     D.mpole, D.l1_ptr, D.l1_srcbox, D.l1_slot, D.near_y, V);
   VFX_HIP(hipGetLastError());
   MARK(8, s);
   if (timed) p->n_timed++;

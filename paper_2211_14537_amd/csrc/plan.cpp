@@ -235,6 +235,13 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     for (int s : l3[leaf]) H.l3_src.push_back(s);
   }
   // ---- list-1 pairs grouped by configuration -----------------------------
+  for (int leaf = 0; leaf < L; ++leaf)
+    if (H.l1_ptr[leaf + 1] - H.l1_ptr[leaf] > kNearConfigs) {
+      err = "internal: list 1 of a leaf longer than the number of near configurations";
+      return VFX_EINVAL;
+    }
+  H.l1_srcbox.resize(H.l1_src.size());
+  for (size_t e = 0; e < H.l1_src.size(); ++e) H.l1_srcbox[e] = H.leaf_box[H.l1_src[e]];
   {
     const int N1 = H.l1_ptr[L];
     std::vector<int> cnt(kNearConfigs + 1, 0);
@@ -251,13 +258,23 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         H.np_tgt[s] = leaf;
         H.l1_slot[e] = s;
       }
+    // tiles of <= 64 pairs; configurations with a low-rank form (K = 16)
+    // go to the low-rank kernel, the others to the dense table GEMM
     constexpr int kTile = 64;
-    for (int c = 0; c < kNearConfigs; ++c)
+    for (int c = 0; c < kNearConfigs; ++c) {
+      const bool lr = T.n == 256 && !T.lr_R.empty() && T.lr_R[c] > 0;
       for (int f = cnt[c]; f < cnt[c + 1]; f += kTile) {
+        if (lr) {
+          H.nl_cfg.push_back(c);
+          H.nl_first.push_back(f);
+          H.nl_count.push_back(std::min(kTile, cnt[c + 1] - f));
+          continue;
+        }
         H.nt_cfg.push_back(c);
         H.nt_first.push_back(f);
         H.nt_count.push_back(std::min(kTile, cnt[c + 1] - f));
       }
+    }
   }
   // ---- lists 2 and 4 (per box, level >= 2) ------------------------------
   H.l2_ptr.assign(B + 1, 0);
@@ -312,6 +329,63 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         return VFX_EINVAL;
       }
       H.m2l_grp.push_back(b);
+    }
+  }
+  // ---- upward pass: every non-leaf box at level >= 2 gathers the
+  // multipoles of its leaf descendants directly (one translation per
+  // (ancestor, leaf) pair, no level-by-level chain).  Pairs are ordered by
+  // box, then by leaf box; groups of <= 8 boxes and <= 64 pairs go to one
+  // wave, a box with more pairs is split into slices whose partial sums are
+  // added in slice order by a second kernel.
+  {
+    std::vector<int> pos(B, -1);
+    for (int b = H.level_start[std::min(2, H.nlev)]; b < B; ++b)
+      if (H.box_leaf[b] < 0) {
+        pos[b] = (int)H.up_box.size();
+        H.up_box.push_back(b);
+      }
+    const int nU = (int)H.up_box.size();
+    std::vector<std::vector<int>> lst(nU);
+    for (int b = 0; b < B; ++b) {
+      if (H.box_leaf[b] < 0) continue;
+      for (int a = H.box_parent[b]; a >= 0 && H.box_level[a] >= 2; a = H.box_parent[a]) lst[pos[a]].push_back(b);
+    }
+    H.up_ptr.assign(nU + 1, 0);
+    for (int u = 0; u < nU; ++u) {
+      std::sort(lst[u].begin(), lst[u].end());
+      H.up_ptr[u + 1] = H.up_ptr[u] + (int)lst[u].size();
+      for (int b : lst[u]) {
+        H.up_src.push_back(b);
+        H.up_pos.push_back(u);
+      }
+    }
+    int u = 0, slots = 0;
+    while (u < nU) {
+      const int cnt = H.up_ptr[u + 1] - H.up_ptr[u];
+      if (cnt > 64) {
+        const int ns = (cnt + 63) / 64;
+        H.up_split.insert(H.up_split.end(), {H.up_box[u], slots, ns});
+        for (int j = 0; j < ns; ++j) {
+          const int e0 = H.up_ptr[u] + 64 * j;
+          H.up_grp.insert(H.up_grp.end(), {u, u + 1, e0, std::min(e0 + 64, H.up_ptr[u + 1]), slots++});
+        }
+        ++u;
+        continue;
+      }
+      int v = u, ne = 0;
+      while (v < nU && v - u < 8 && ne + (H.up_ptr[v + 1] - H.up_ptr[v]) <= 64) {
+        ne += H.up_ptr[v + 1] - H.up_ptr[v];
+        ++v;
+      }
+      H.up_grp.insert(H.up_grp.end(), {u, v, H.up_ptr[u], H.up_ptr[v], -1});
+      u = v;
+    }
+    H.up_slots = slots;
+    H.anc_ptr.assign(L + 1, 0);
+    for (int leaf = 0; leaf < L; ++leaf) {
+      for (int a = H.box_parent[H.leaf_box[leaf]]; a >= 0 && H.box_level[a] >= 2; a = H.box_parent[a])
+        H.anc.push_back(a);
+      H.anc_ptr[leaf + 1] = (int)H.anc.size();
     }
   }
   // ---- list-4 entries grouped by P2L slot --------------------------------

@@ -382,6 +382,105 @@ static void build_near(Tables& T) {
   }
 }
 
+// Truncated rank-revealing factorisation of the n x n near-field operator
+// A (A[i][j] = near[c][j][i]): Householder QR with column pivoting, stopped
+// when the largest remaining column norm falls below tol times the first
+// one, so ||A - Q W||_F <= sqrt(n - r) tol ||A e_piv0||.  Q: n x r with
+// orthonormal columns, W = R_r Pi^T: r x n.  Returns r, or -1 when the rank
+// exceeds rmax.
+static int near_rrqr(const double* near_c, int n, double tol, int rmax, std::vector<double>& Q,
+                     std::vector<double>& W) {
+  std::vector<double> M((size_t)n * n);  // M[i][j] = A[i][j]
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) M[(size_t)i * n + j] = near_c[(size_t)j * n + i];
+  std::vector<int> perm(n);
+  for (int j = 0; j < n; ++j) perm[j] = j;
+  std::vector<std::vector<double>> V;
+  std::vector<double> tau;
+  double r00 = 0.0;
+  int r = 0;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    double best = -1.0;
+    for (int j = k; j < n; ++j) {
+      double s2 = 0.0;
+      for (int i = k; i < n; ++i) s2 += M[(size_t)i * n + j] * M[(size_t)i * n + j];
+      if (s2 > best) {
+        best = s2;
+        piv = j;
+      }
+    }
+    const double cn = std::sqrt(best);
+    if (k == 0) r00 = cn;
+    if (cn <= tol * r00 || cn == 0.0) break;
+    if (k >= rmax) return -1;
+    if (piv != k) {
+      for (int i = 0; i < n; ++i) std::swap(M[(size_t)i * n + k], M[(size_t)i * n + piv]);
+      std::swap(perm[k], perm[piv]);
+    }
+    std::vector<double> v(n - k);
+    for (int i = k; i < n; ++i) v[i - k] = M[(size_t)i * n + k];
+    const double alpha = v[0] >= 0 ? -cn : cn;
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (double x : v) vn2 += x * x;
+    const double tk = vn2 > 0 ? 2.0 / vn2 : 0.0;
+    for (int j = k; j < n; ++j) {
+      double d = 0.0;
+      for (int i = k; i < n; ++i) d += v[i - k] * M[(size_t)i * n + j];
+      d *= tk;
+      for (int i = k; i < n; ++i) M[(size_t)i * n + j] -= d * v[i - k];
+    }
+    V.push_back(std::move(v));
+    tau.push_back(tk);
+    r = k + 1;
+  }
+  W.assign((size_t)r * n, 0.0);
+  for (int a = 0; a < r; ++a)
+    for (int j = a; j < n; ++j) W[(size_t)a * n + perm[j]] = M[(size_t)a * n + j];
+  // Q = H_0 ... H_{r-1} [I_r; 0]
+  Q.assign((size_t)n * r, 0.0);
+  for (int a = 0; a < r; ++a) Q[(size_t)a * r + a] = 1.0;
+  for (int k = r - 1; k >= 0; --k) {
+    const std::vector<double>& v = V[k];
+    for (int a = 0; a < r; ++a) {
+      double d = 0.0;
+      for (int i = k; i < n; ++i) d += v[i - k] * Q[(size_t)i * r + a];
+      d *= tau[k];
+      for (int i = k; i < n; ++i) Q[(size_t)i * r + a] -= d * v[i - k];
+    }
+  }
+  return r;
+}
+
+// Low-rank forms of the near-field configurations whose factorisation at
+// relative tolerance kNearLrTol saves work: rank rounded up to R (a
+// multiple of 16, at most 64) with 2 R <= 0.6 n.  Stored as GEMM operands:
+// lr_W[c][j][a] = W[a][j] (n x 64), lr_Q[c][a][i] = Q[i][a] (64 x n), zero
+// padded; lr_R[c] = R, or 0 for configurations applied densely.
+static void build_near_lowrank(Tables& T) {
+  const int n = T.n;
+  T.lr_R.assign(kNearConfigs, 0);
+  T.lr_rank.assign(kNearConfigs, 0);
+  T.lr_W.assign((size_t)kNearConfigs * n * kNearLrMax, 0.0);
+  T.lr_Q.assign((size_t)kNearConfigs * kNearLrMax * n, 0.0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int c = 0; c < kNearConfigs; ++c) {
+    std::vector<double> Q, W;
+    const int r = near_rrqr(T.near.data() + (size_t)c * n * n, n, kNearLrTol, kNearLrMax, Q, W);
+    if (r <= 0) continue;
+    const int R = 16 * ((r + 15) / 16);
+    if (R > kNearLrMax || 10 * 2 * R > 6 * n) continue;
+    T.lr_R[c] = R;
+    T.lr_rank[c] = r;
+    for (int a = 0; a < r; ++a)
+      for (int j = 0; j < n; ++j) {
+        T.lr_W[((size_t)c * n + j) * kNearLrMax + a] = W[(size_t)a * n + j];
+        T.lr_Q[((size_t)c * kNearLrMax + a) * n + j] = Q[(size_t)j * r + a];
+      }
+  }
+}
+
 // Chebyshev moments of a smooth kernel over a square by tensor Gauss-Legendre
 // on npan x npan panels, for several kernel values at once.
 static void build_p2l(Tables& T) {
@@ -610,7 +709,7 @@ static void build_pascal(Tables& T) {
     }
   }
   // P2L as a real GEMM operand
-  T.p2l_rows = 16 * ((2 * P + 15) / 16);
+  T.p2l_rows = 64 * ((2 * P + 63) / 64);
   const int R = T.p2l_rows;
   T.p2l_gemm.assign((size_t)kP2LSlots * n * R, 0.0);
   for (int s = 0; s < kP2LSlots; ++s)
@@ -654,6 +753,7 @@ void build_tables(Tables& T) {
   build_stencil(T);
   build_expansions(T);
   build_near(T);
+  build_near_lowrank(T);
   build_p2l(T);
   build_pascal(T);
 }

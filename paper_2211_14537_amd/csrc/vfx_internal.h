@@ -19,6 +19,11 @@ namespace vfx {
 //           values in {-3,-1,1,3} with max(|ox|,|oy|) = 3
 //   21..32  one level finer, centre offset in units h/4, same value set
 constexpr int kNearConfigs = 33;
+// Near-field operators are applied in low-rank form Q W when the truncated
+// pivoted QR at this relative tolerance has rank <= kNearLrMax and saves at
+// least 40% of the dense work.
+constexpr double kNearLrTol = 1e-14;
+constexpr int kNearLrMax = 64;
 // M2L (list 2): centre offset (dx, dy) in units h, |dx|,|dy| <= 3, index
 // (dx+3)*7 + (dy+3); only max(|dx|,|dy|) >= 2 occurs.
 constexpr int kM2LSlots = 49;
@@ -42,6 +47,10 @@ struct Tables {
   std::vector<double> cbar;            // Kbar x Kbar values -> coefficients
   std::vector<double> near;            // 33 x n x n, [c][j][i]
   std::vector<double> near_s2;         // 33: (source side / target side)^2
+  // low-rank near-field operators (near ~ Q W), see build_near_lowrank
+  std::vector<int> lr_R, lr_rank;      // 33: padded rank (0 = dense), rank
+  std::vector<double> lr_W;            // 33 x n x kNearLrMax, [c][j][a]
+  std::vector<double> lr_Q;            // 33 x kNearLrMax x n, [c][a][i]
   std::vector<double> p2m;             // (p+1) x n complex, [k][j] (re,im)
   std::vector<double> l2p;             // n x (p+1) complex, [i][l]
   std::vector<double> m2m;             // 4 x (p+1) x (p+1) complex, [q][k][l]
@@ -63,7 +72,7 @@ struct Tables {
   std::vector<double> m2m_in, m2m_out;            // 4 x P complex: (2w)^-k, w^l
   std::vector<double> l2l_in, l2l_out;            // 4 x P complex: w^k, (2w)^-l
   // P2L tables as real GEMM operands: [slot][j][row], row = 2l (re) or
-  // 2l+1 (im), rows padded to p2l_rows (a multiple of 16)
+  // 2l+1 (im), rows padded to p2l_rows (a multiple of 64)
   int p2l_rows = 0;
   std::vector<double> p2l_gemm;
   // P2M as a real GEMM operand: [j][row], rows as for P2L
@@ -86,6 +95,8 @@ struct DeviceTables {
   int device = -1;
   double *t = nullptr, *tbar = nullptr, *w2 = nullptr, *AbarT = nullptr, *cbar = nullptr;
   double *near = nullptr, *near_s2 = nullptr;
+  int* lr_R = nullptr;
+  double *lr_W = nullptr, *lr_Q = nullptr;
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
@@ -109,17 +120,25 @@ struct HostPlan {
   std::vector<int> leaf_box;                 // L
   std::vector<int8_t> kind;                  // L
   std::vector<int> l1_ptr, l1_src, l1_cfg;   // per leaf
+  std::vector<int> l1_srcbox;                // box of each list-1 source leaf
   std::vector<int> l2_ptr, l2_src, l2_off;   // per box
   std::vector<int> l2_tgt;                   // target box of each list-2 entry
   std::vector<int> m2l_grp;                  // groups of consecutive boxes (level >= 2):
                                              // <= 64 list-2 entries, <= 8 boxes
   std::vector<int> l3_ptr, l3_src;           // per leaf (source boxes)
+  // direct upward pass: non-leaf boxes at level >= 2, their leaf-descendant
+  // pairs, wave groups {pos0, pos1, e0, e1, slot} and split boxes
+  // {box, slot0, nslots}
+  std::vector<int> up_box, up_ptr, up_src, up_pos, up_grp, up_split;
+  std::vector<int> anc_ptr, anc;             // per leaf: ancestors at level >= 2, nearest first
+  int up_slots = 0;
   std::vector<int> l4_ptr, l4_src, l4_cfg;   // per box (source leaves)
   // list-1 pairs regrouped by table configuration (config-major, targets
   // ascending inside a configuration) for the batched near-field GEMM;
   // l1_slot maps each per-target list-1 entry to its pair index
   std::vector<int> np_src, np_tgt, l1_slot;
-  std::vector<int> nt_cfg, nt_first, nt_count;  // GEMM tiles of <= 64 pairs
+  std::vector<int> nt_cfg, nt_first, nt_count;  // dense GEMM tiles of <= 64 pairs
+  std::vector<int> nl_cfg, nl_first, nl_count;  // low-rank tiles of <= 64 pairs
   // list-4 entries regrouped by P2L slot, the same way
   std::vector<int> p4_src, l4_slot, t4_cfg, t4_first, t4_count;
   // P2M over all leaves as one GEMM configuration
@@ -140,11 +159,16 @@ struct DevicePlan {
   double *box_cx = nullptr, *box_cy = nullptr;
   int* leaf_box = nullptr;
   int8_t* kind = nullptr;
-  int *l1_ptr = nullptr, *l1_src = nullptr, *l1_cfg = nullptr;
+  int *l1_ptr = nullptr, *l1_src = nullptr, *l1_cfg = nullptr, *l1_srcbox = nullptr;
   int *l2_ptr = nullptr, *l2_src = nullptr, *l2_off = nullptr, *l2_tgt = nullptr, *m2l_grp = nullptr;
   int *l3_ptr = nullptr, *l3_src = nullptr;
+  int *up_box = nullptr, *up_ptr = nullptr, *up_src = nullptr, *up_pos = nullptr, *up_grp = nullptr,
+      *up_split = nullptr;
+  double2* up_part = nullptr;
+  int *anc_ptr = nullptr, *anc = nullptr;  // partial multipoles of split boxes, up_slots x (p+1)
   int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
   int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;
+  int *nl_cfg = nullptr, *nl_first = nullptr, *nl_count = nullptr;
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;

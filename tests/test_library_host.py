@@ -192,3 +192,31 @@ def test_rejects_invalid_input():
     with pytest.raises(vfx.VfxError) as e:
         vfx.Plan(ctx, [0], [0], [0], [5])
     assert e.value.code == vfx.VFX_EINVAL
+
+
+def test_near_lowrank_factors_match_oracle_quadrature():
+    """K = 16 near-field operators in truncated low-rank form: the factors
+    reproduce the dense table to the truncation tolerance and, applied to
+    random leaf data, the oracle's direct quadrature of the near potential."""
+    K, n = 16, 256
+    ctx = vfx.Context(K, 24)
+    rk = ctx.debug_table(22, 0, 66)
+    R, rank = rk[:33].astype(int), rk[33:].astype(int)
+    assert R[4] == 0  # the self interaction is full rank and stays dense
+    assert (R[np.arange(33) != 4] > 0).all()
+    assert ((R % 16) == 0).all() and (R <= 64).all() and (rank <= R).all()
+    t = cheb.nodes(K)
+    tx = (0.5 * t[:, None] + 0 * t[None, :]).ravel()
+    ty = (0 * t[:, None] + 0.5 * t[None, :]).ravel()
+    rng = np.random.default_rng(1)
+    for c in (0, 1, 9, 10, 21, 22):
+        A = ctx.debug_table(0, c, n * n).reshape(n, n)
+        W = ctx.debug_table(20, c, n * 64).reshape(n, 64)
+        Q = ctx.debug_table(21, c, n * 64).reshape(64, n)
+        assert np.abs(W[:, rank[c]:]).max() == 0 and np.abs(Q[rank[c]:]).max() == 0
+        assert np.abs(W @ Q - A).max() <= 1e-13 * np.abs(A).max(), c
+        ox, oy, s = _near_geometry(c)
+        f = rng.standard_normal(n)
+        vo = volume.potential_boxes(tx, ty, [ox], [oy], [s], volume.leaf_coefficients(f[None], K), K)
+        err = np.abs((f @ W) @ Q - 2 * np.pi * vo).max()
+        assert err < 1e-13 * max(1.0, np.abs(2 * np.pi * vo).max()), (c, err)
