@@ -55,54 +55,136 @@ __global__ void k_fe_init(int n, int L, const int8_t* __restrict__ kind, const d
 }
 
 // -------------------------------------------------------------------------
+// Extension of one cut leaf per work-group (256 threads): f_G = P_i f_I
+// (A1), values on the Kbar x Kbar grid of Sbar (given data at interior
+// nodes, A_{Xbar,G} f_G elsewhere; A2), the total-order Chebyshev
+// coefficients (A3) and their values on the K x K nodes of every target
+// leaf.  Every global load whose address is known early is issued at the
+// start (two rounds: indices/geometry, then the data they point to), so the
+// work-group's critical path holds few memory round trips.
+constexpr int kExtTgtMax = 16;  // targets whose geometry is staged in LDS
+
 __global__ void __launch_bounds__(256) k_extension(
-    int K, int Kb, int nX, int nG, double root_size, const int* __restrict__ cut_leaf,
-    const int* __restrict__ pinv_ptr, const uint16_t* __restrict__ pinv_idx, const double* __restrict__ pinv_val,
-    const uint8_t* __restrict__ sbar_given, const int* __restrict__ ext_ptr, const int* __restrict__ ext_tgt,
-    const double* __restrict__ t, const double* __restrict__ AbarT, const double* __restrict__ cbar,
-    const int* __restrict__ leaf_box, const double* __restrict__ box_cx, const double* __restrict__ box_cy,
-    const int* __restrict__ box_level, const double* __restrict__ f_cut, double* __restrict__ fe) {
+    int K, int Kb, int nX, int nG, const int* __restrict__ pinv_ptr, const uint16_t* __restrict__ pinv_idx,
+    const double* __restrict__ pinv_val, const uint8_t* __restrict__ sbar_given, const int* __restrict__ ext_ptr,
+    const int* __restrict__ ext_tgt, const double* __restrict__ ext_geo, const double* __restrict__ t,
+    const double* __restrict__ AbarT, const double* __restrict__ cbar, const double* __restrict__ f_cut,
+    double* __restrict__ fe) {
   __shared__ double s_fI[kMaxX];
   __shared__ double s_fG[kMaxG];
+  __shared__ double s_cb[kMaxKb * kMaxKb];
   __shared__ double s_g[kMaxKb * kMaxKb];
   __shared__ double s_tmp[kMaxKb * kMaxKb];
   __shared__ double s_coef[kMaxKb * kMaxKb];
   __shared__ double s_Ex[kMaxK * kMaxKb];
   __shared__ double s_Ey[kMaxK * kMaxKb];
+  __shared__ double s_t[kMaxK];
+  __shared__ double s_geo[3 * kExtTgtMax];
+  __shared__ int s_tg[kExtTgtMax];
+  __shared__ uint8_t s_given[kMaxKb * kMaxKb];
   const int c = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = K * K, Kb2 = Kb * Kb;
   const int off = pinv_ptr[c], ni = pinv_ptr[c + 1] - off;
+  const int e0 = ext_ptr[c], ne = ext_ptr[c + 1] - e0;
   const double* fc = f_cut + (size_t)c * nX;
-  for (int q = tid; q < ni; q += blockDim.x) s_fI[q] = fc[pinv_idx[off + q]];
+  // round 1: indices, flags, small tables, target geometry
+  int idx0 = tid < ni ? pinv_idx[off + tid] : 0;
+  int idx1 = tid + 256 < ni ? pinv_idx[off + tid + 256] : 0;
+  const bool given = tid < Kb2 && sbar_given[(size_t)c * Kb2 + tid];
+  if (tid < Kb2) s_cb[tid] = cbar[tid];
+  if (tid < K) s_t[tid] = t[tid];
+  if (tid < ne && tid < kExtTgtMax) {
+    s_tg[tid] = ext_tgt[e0 + tid];
+    s_geo[3 * tid] = ext_geo[3 * (e0 + tid)];
+    s_geo[3 * tid + 1] = ext_geo[3 * (e0 + tid) + 1];
+    s_geo[3 * tid + 2] = ext_geo[3 * (e0 + tid) + 2];
+  }
+  // round 2: interior samples and the given Sbar-grid values
+  if (tid < ni) s_fI[tid] = fc[idx0];
+  if (tid + 256 < ni) s_fI[tid + 256] = fc[idx1];
+  for (int q = tid + 512; q < ni; q += blockDim.x) s_fI[q] = fc[pinv_idx[off + q]];
+  if (tid < Kb2) {
+    s_given[tid] = given;
+    if (given) s_g[tid] = fc[n + tid];
+  }
   __syncthreads();
-  // f_G = P_i f_I  (P_i: nG x ni row-major)
+  // A1: f_G = P_i f_I  (P_i: nG x ni row-major).  Wave w takes rows
+  // 16w..16w+15, lane l the columns l, l+64, ...; every load of a wave is
+  // 512 contiguous bytes of one row, and two column steps (32 loads) are in
+  // flight at once.  The 16 row partials are combined across the lanes by a
+  // recursive-halving reduce-scatter over lane bits 3..0 (lane l ends with
+  // row l & 15) and two plain butterfly steps over bits 4 and 5.  Rows >= 64
+  // (a stencil degree above 10) use wave sums.
   const double* P = pinv_val + (size_t)off * nG;
-  for (int r = wave; r < nG; r += blockDim.x / 64) {
-    double acc = 0.0;
-    const double* pr = P + (size_t)r * ni;
-    for (int q = lane; q < ni; q += 64) acc += pr[q] * s_fI[q];
-    acc = wave_sum(acc);
-    if (lane == 0) s_fG[r] = acc;
-  }
-  __syncthreads();
-  // values on the Kbar x Kbar grid of Sbar
-  for (int a = tid; a < Kb2; a += blockDim.x) {
-    double v;
-    if (sbar_given[(size_t)c * Kb2 + a]) {
-      v = fc[n + a];
-    } else {
-      v = 0.0;
-      for (int r = 0; r < nG; ++r) v += AbarT[(size_t)r * Kb2 + a] * s_fG[r];
+  {
+    double acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
+    const int r0 = 16 * wave;
+    for (int q = lane; q < ni; q += 128) {
+      const bool q2 = q + 64 < ni;
+      const double f0 = s_fI[q], f1 = q2 ? s_fI[q + 64] : 0.0;
+      double pa[16], pb[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = min(r0 + r, nG - 1);
+        pa[r] = P[row * ni + q];
+        pb[r] = q2 ? P[row * ni + q + 64] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const double m = (r0 + r < nG) ? 1.0 : 0.0;
+        acc[r] += m * (pa[r] * f0 + pb[r] * f1);
+      }
     }
-    s_g[a] = v;
+#pragma unroll
+    for (int s = 8; s >= 1; s >>= 1) {
+      const bool up = (lane & s) != 0;
+#pragma unroll
+      for (int j = 0; j < s; ++j) {
+        const double send = up ? acc[j] : acc[j + s];
+        const double keep = up ? acc[j + s] : acc[j];
+        acc[j] = keep + __shfl_xor(send, s, 64);
+      }
+    }
+    acc[0] += __shfl_xor(acc[0], 16, 64);
+    acc[0] += __shfl_xor(acc[0], 32, 64);
+    if (lane < 16 && r0 + lane < nG) s_fG[r0 + lane] = acc[0];
+  }
+  for (int r = 64 + wave; r < nG; r += blockDim.x / 64) {
+    double a = 0.0;
+    const double* pr = P + (size_t)r * ni;
+    for (int q = lane; q < ni; q += 64) a += pr[q] * s_fI[q];
+    a = wave_sum(a);
+    if (lane == 0) s_fG[r] = a;
   }
   __syncthreads();
-  // coefficients c = C g C^T, truncated to total order < Kbar
+  // A2: the Sbar grid values not given as data, A_{Xbar,G} f_G (universal
+  // operator rows in batches of 16 independent loads)
+  for (int a = tid; a < Kb2; a += blockDim.x) {
+    if (s_given[a]) continue;
+    double v0 = 0.0, v1 = 0.0;
+    int r = 0;
+    for (; r + 16 <= nG; r += 16) {
+      double w[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) w[u] = AbarT[(size_t)(r + u) * Kb2 + a];
+#pragma unroll
+      for (int u = 0; u < 16; u += 2) {
+        v0 += w[u] * s_fG[r + u];
+        v1 += w[u + 1] * s_fG[r + u + 1];
+      }
+    }
+    for (; r < nG; ++r) v0 += AbarT[(size_t)r * Kb2 + a] * s_fG[r];
+    s_g[a] = v0 + v1;
+  }
+  __syncthreads();
+  // A3: coefficients c = C g C^T, truncated to total order < Kbar
   for (int e = tid; e < Kb2; e += blockDim.x) {
     const int m = e / Kb, j = e % Kb;
     double acc = 0.0;
-    for (int i = 0; i < Kb; ++i) acc += cbar[m * Kb + i] * s_g[i * Kb + j];
+    for (int i = 0; i < Kb; ++i) acc += s_cb[m * Kb + i] * s_g[i * Kb + j];
     s_tmp[e] = acc;
   }
   __syncthreads();
@@ -110,23 +192,29 @@ __global__ void __launch_bounds__(256) k_extension(
     const int m = e / Kb, nn = e % Kb;
     double acc = 0.0;
     if (m + nn < Kb)
-      for (int j = 0; j < Kb; ++j) acc += s_tmp[m * Kb + j] * cbar[nn * Kb + j];
+      for (int j = 0; j < Kb; ++j) acc += s_tmp[m * Kb + j] * s_cb[nn * Kb + j];
     s_coef[e] = acc;
   }
   __syncthreads();
-  const int bS = leaf_box[cut_leaf[c]];
-  const double cxS = box_cx[bS], cyS = box_cy[bS];
-  const double hS = box_side(root_size, box_level[bS]);
-  for (int e = ext_ptr[c]; e < ext_ptr[c + 1]; ++e) {
-    const int j = ext_tgt[e];
-    const int bj = leaf_box[j];
-    const double cxj = box_cx[bj], cyj = box_cy[bj];
-    const double hj = box_side(root_size, box_level[bj]);
+  // values at the K x K nodes of every target leaf (the cut leaf first)
+  for (int q = 0; q < ne; ++q) {
+    int j;
+    double ox, oy, sc;
+    if (q < kExtTgtMax) {
+      j = s_tg[q];
+      ox = s_geo[3 * q];
+      oy = s_geo[3 * q + 1];
+      sc = s_geo[3 * q + 2];
+    } else {
+      j = ext_tgt[e0 + q];
+      ox = ext_geo[3 * (e0 + q)];
+      oy = ext_geo[3 * (e0 + q) + 1];
+      sc = ext_geo[3 * (e0 + q) + 2];
+    }
     if (tid < 2 * K) {
       const int a = tid % K;
       const bool isy = tid >= K;
-      const double X = (isy ? cyj : cxj) + 0.5 * hj * t[a];
-      const double xi = (X - (isy ? cyS : cxS)) / (1.5 * hS);
+      const double xi = (isy ? oy : ox) + sc * s_t[a];
       double* dst = (isy ? s_Ey : s_Ex) + a * Kb;
       double t0 = 1.0, t1 = xi;
       dst[0] = 1.0;
@@ -1129,6 +1217,7 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.cut_leaf, H.cut_leaf);
   UP(D.ext_ptr, H.ext_ptr);
   UP(D.ext_tgt, H.ext_tgt);
+  UP(D.ext_geo, H.ext_geo);
   UP(D.pinv_ptr, H.pinv_ptr);
   UP(D.pinv_idx, H.pinv_idx);
   UP(D.pinv_val, H.pinv_val);
@@ -1153,7 +1242,7 @@ void free_plan_device(Plan* p) {
                   D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local,    D.t0_cfg,   D.t0_first,
                   D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp,  D.up_box,   D.up_ptr,   D.up_src,
                   D.up_pos,    D.up_split,   D.up_grp,   D.up_part,  D.anc_ptr,  D.anc,
-                  D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox};
+                  D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -1270,9 +1359,8 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
     hipLaunchKernelGGL(k_fe_init, dim3(blocks), dim3(256), 0, s, n, L, D.kind, f_leaf, fe);
   }
   if (H.ncut > 0)
-    hipLaunchKernelGGL(k_extension, dim3(H.ncut), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, T.root_size,
-                       D.cut_leaf, D.pinv_ptr, D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt,
-                       DT.t, DT.AbarT, DT.cbar, D.leaf_box, D.box_cx, D.box_cy, D.box_level, f_cut, fe);
+    hipLaunchKernelGGL(k_extension, dim3(H.ncut), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, D.pinv_ptr, D.pinv_idx,
+                       D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t, DT.AbarT, DT.cbar, f_cut, fe);
   VFX_HIP(hipGetLastError());
   MARK(1, s);
   // fork: near field on the side stream, concurrent with P2M, the upward

@@ -490,6 +490,17 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
   for (int c = 0; c < H.ncut; ++c) {
     H.ext_ptr[c + 1] = H.ext_ptr[c] + (int)tg[c].size();
     H.ext_tgt.insert(H.ext_tgt.end(), tg[c].begin(), tg[c].end());
+    // target grid in the cut leaf's Sbar frame (Sbar = 3x the cut leaf,
+    // same centre): node a of target j sits at o + s t_a per axis
+    const int bS = H.leaf_box[H.cut_leaf[c]];
+    const double hS = std::ldexp(T.root_size, -H.box_level[bS]);
+    for (int j : tg[c]) {
+      const int bj = H.leaf_box[j];
+      const double hj = std::ldexp(T.root_size, -H.box_level[bj]);
+      H.ext_geo.push_back((H.box_cx[bj] - H.box_cx[bS]) / (1.5 * hS));
+      H.ext_geo.push_back((H.box_cy[bj] - H.box_cy[bS]) / (1.5 * hS));
+      H.ext_geo.push_back(hj / (3.0 * hS));
+    }
   }
 
   // ---- per-cut-leaf pseudo-inverses --------------------------------------

@@ -146,6 +146,7 @@ struct HostPlan {
   std::vector<int> cut_leaf;                 // ncut
   std::vector<int> owner;                    // L
   std::vector<int> ext_ptr, ext_tgt;         // per cut leaf (targets, itself first)
+  std::vector<double> ext_geo;               // per target: x0, y0, scale in the Sbar frame
   std::vector<int> pinv_ptr;                 // ncut + 1 (in interior points)
   std::vector<uint16_t> pinv_idx;            // interior stencil indices
   std::vector<double> pinv_val;              // per cut: nG x N_I row-major
@@ -174,6 +175,7 @@ struct DevicePlan {
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
   double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
   int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
+  double* ext_geo = nullptr;
   uint16_t* pinv_idx = nullptr;
   double* pinv_val = nullptr;
   uint8_t* sbar_given = nullptr;
