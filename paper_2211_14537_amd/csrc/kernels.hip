@@ -538,7 +538,8 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
   // global -> register staging of one K block
   constexpr int AE = TE * KB / 256;                  // entry values per thread (4 or 1)
   const int aj = tid % TE, ak = (tid / TE) * AE;     // entry aj, k = ak..ak+AE-1
-  const int bk = tid >> 4, br = (tid & 15) * BE;     // table: k = bk, rows br..br+BE-1
+  // table block KB x LDB: thread tid stages the values tid, tid + 256, ...
+  // (v = k * LDB + row), so consecutive lanes touch consecutive rows
   const bool a_ok = aj < np;
   const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
   double ra[AE], rbv[BE];
@@ -546,15 +547,17 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
     const int k0 = kb * KB;
 #pragma unroll
     for (int e = 0; e < AE; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
-    const double* ar = Ac + (size_t)(k0 + bk) * R + row0 + br;
 #pragma unroll
-    for (int e = 0; e < BE; ++e) rbv[e] = ar[e];
+    for (int e = 0; e < BE; ++e) {
+      const int v = tid + 256 * e, bk = v / LDB, br = v - bk * LDB;
+      rbv[e] = Ac[(size_t)(k0 + bk) * R + row0 + br];
+    }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < AE; ++e) sA[buf][(ak + e) * LDA + aj] = ra[e];
 #pragma unroll
-    for (int e = 0; e < BE; ++e) sB[buf][bk * LDB + br + e] = rbv[e];
+    for (int e = 0; e < BE; ++e) sB[buf][tid + 256 * e] = rbv[e];
   };
   // wave w: TE = 64 -> entries 16w..16w+15, every row tile;
   //         TE = 16 -> entries 0..15, row tiles w, w+4
@@ -626,22 +629,21 @@ __device__ __forceinline__ void near_lr_phase1(const double* __restrict__ xsrc, 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int aj = tid & 63, ak = (tid >> 6) * 4;  // entry aj, k = ak..ak+3
-  const int bk = tid >> 4, ba = (tid & 15) * 4;  // factor: k = bk, ranks ba..ba+3
+  const int ba = tid & 63, bk = tid >> 6;        // factor: rank ba, k = bk + 4e
   const bool b_ok = ba < 16 * MT1;
   double ra[4], rw[4];
   auto gload = [&](int kb) {
     const int k0 = kb * KB;
 #pragma unroll
     for (int e = 0; e < 4; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
-    const double* wr = Wc + (size_t)(k0 + bk) * LM + ba;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) rw[e] = b_ok ? wr[e] : 0.0;
+    for (int e = 0; e < 4; ++e) rw[e] = b_ok ? Wc[(k0 + bk + 4 * e) * LM + ba] : 0.0;
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) sX[(buf * KB + ak + e) * kLrLDX + aj] = ra[e];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sW[(buf * KB + bk) * kLrLDW + ba + e] = rw[e];
+    for (int e = 0; e < 4; ++e) sW[(buf * KB + bk + 4 * e) * kLrLDW + ba] = rw[e];
   };
   vfx_d4 acc[MT1];
 #pragma unroll
@@ -713,17 +715,20 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
       default: near_lr_phase1<KD, 4>(xsrc, a_ok, Wc, sX, sW, sZ); break;
     }
     // ---- phase 2: Y = Z Q^T
-    constexpr int QE = KD / 32;
-    const int qa = tid >> 5, qr = (tid & 31) * QE;  // rank qa, rows qr..qr+QE-1
+    // Q block: QB ranks x KD rows; thread tid stages rows tid, tid + 256, ...
+    // of every rank (consecutive lanes, consecutive addresses)
+    constexpr int QE = QB * KD / 256;
     double rq[QE];
     auto gload2 = [&](int qb) {
-      const double* qrow = Qc + (size_t)(qb * QB + qa) * KD + qr;
 #pragma unroll
-      for (int e = 0; e < QE; ++e) rq[e] = qrow[e];
+      for (int e = 0; e < QE; ++e) {
+        const int v = tid + 256 * e;  // v = rank * KD + row within the block
+        rq[e] = Qc[(size_t)qb * QB * KD + v];
+      }
     };
     auto lstore2 = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < QE; ++e) sQ[(buf * QB + qa) * KD + qr + e] = rq[e];
+      for (int e = 0; e < QE; ++e) sQ[buf * QB * KD + tid + 256 * e] = rq[e];
     };
     vfx_d4 acc2[NRT];
 #pragma unroll
@@ -884,191 +889,162 @@ __device__ __forceinline__ double2 cpow(double2 z, int k) {
 }
 
 // -------------------------------------------------------------------------
-// Far field and the near-field reduction, one work-group per leaf, thread i =
-// node i.  The leaf's local expansion is its own (M2L + P2L) part plus the
-// own parts of its ancestors at levels >= 2 shifted directly to the leaf
-// (scaled form, w = (c_b - c_A)/h_A, r = h_b/h_A):
-//   c_l += (r/w)^l sum_{k>=l} C(k,l) w^k b_k(A)
-// (an exact polynomial shift, so equal up to rounding to the level-by-level
-// downward pass).  Then L2P by Horner in the scaled node position, M2P for
-// list 3 by Horner in h_w/z, the list-1 sums of the near-field GEMM (in
-// list order, deterministic) and the log(h) a_0 terms of the near field.
-// The per-leaf lists are staged through LDS in two rounds of independent
-// loads (indices, then the data they point to) so their latencies overlap.
-constexpr int kFarCap = 8;  // ancestors / list-3 entries per staging round
+// Downward pass without the level-by-level chain: the local expansion of a
+// leaf b is its own (M2L + P2L) part plus the own parts of its ancestors A
+// at levels >= 2 shifted directly to its centre (an exact polynomial shift,
+// so equal up to rounding to the level-by-level pass).  Scaled form,
+// w = (c_b - c_A)/h_A, r = h_b/h_A:
+//   c_l += (r/w)^l sum_{k>=l} C(k,l) w^k b_k(A).
+// One lane per (leaf, ancestor) pair; a group of <= 8 leaves and <= 64
+// pairs per wave; per-leaf sums in pair order through LDS (deterministic).
+template <int PM, bool EXACT>
+__global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const int* __restrict__ grp,
+                                             const int* __restrict__ anc_ptr, const int* __restrict__ anc,
+                                             const int* __restrict__ anc_leaf, const int* __restrict__ leaf_box,
+                                             const int* __restrict__ box_level, const double* __restrict__ box_cx,
+                                             const double* __restrict__ box_cy, const double* __restrict__ pasT,
+                                             const double2* __restrict__ local, double2* __restrict__ locf) {
+  const int P = EXACT ? PM : Prt;
+  __shared__ double2 s_o[8 * 64];
+  const int f0 = grp[blockIdx.x], f1 = grp[blockIdx.x + 1];
+  const int e0 = anc_ptr[f0], e1 = anc_ptr[f1];
+  const int lane = threadIdx.x;
+  const int e = e0 + lane;
+  const bool act = e < e1;
+  const int A = act ? anc[e] : 0;
+  const int b = leaf_box[act ? anc_leaf[e] : f0];
+  const int la = box_level[A], lb = box_level[b];
+  const double hA = box_side(root_size, la);
+  const double2 w = act ? make_double2((box_cx[b] - box_cx[A]) / hA, (box_cy[b] - box_cy[A]) / hA)
+                        : make_double2(0.5, 0.5);
+  const double r = act ? ldexp(1.0, la - lb) : 1.0;
+  const double ww = w.x * w.x + w.y * w.y;
+  const double2 q = make_double2(r * w.x / ww, -r * w.y / ww);  // r / w
+  double2 s[PM];
+  {
+    double2 pw = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < PM; ++k) {
+      const double2 a = (act && k < P) ? local[(size_t)A * P + k] : make_double2(0.0, 0.0);
+      s[k] = cmul(pw, a);
+      pw = cmul(pw, w);
+    }
+  }
+  double2 ql = make_double2(1.0, 0.0);
+  const int NC = (P + 7) / 8;
+#pragma unroll
+  for (int c = 0; c < (PM + 7) / 8; ++c) {
+    if (c >= NC) break;
+    __syncthreads();
+    // the eight outputs of the chunk accumulate side by side (k outer)
+    double ur[8], ui[8];
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) ur[lc] = ui[lc] = 0.0;
+#pragma unroll
+    for (int k = 0; k < PM; ++k) {
+#pragma unroll
+      for (int lc = 0; lc < 8; ++lc) {
+        const int l = 8 * c + lc;
+        if (k >= l && k < P) {
+          const double cf = pasT[l * P + k];
+          ur[lc] += cf * s[k].x;
+          ui[lc] += cf * s[k].y;
+        }
+      }
+    }
+#pragma unroll
+    for (int lc = 0; lc < 8; ++lc) {
+      const int l = 8 * c + lc;
+      double2 out = make_double2(0.0, 0.0);
+      if (l < P) {
+        out = cmul(ql, make_double2(ur[lc], ui[lc]));
+        ql = cmul(ql, q);
+      }
+      s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int lc = lane & 7, seg = lane >> 3;
+    const int f = f0 + seg, l = 8 * c + lc;
+    if (f < f1 && l < P) {
+      const int bf = leaf_box[f];
+      double2 v = make_double2(0.0, 0.0);
+      if (box_level[bf] >= 2) {
+        const double2 sv = seg_sum(s_o + lc * 64, anc_ptr[f] - e0, anc_ptr[f + 1] - e0);
+        const double2 own = local[(size_t)bf * P + l];
+        v = make_double2(own.x + sv.x, own.y + sv.y);
+      }
+      locf[(size_t)f * P + l] = v;
+    }
+  }
+}
 
-__global__ void __launch_bounds__(256) k_far(int K, int P, double root_size, const int* __restrict__ leaf_box,
-                                             const int* __restrict__ box_level, const int* __restrict__ anc_ptr,
-                                             const int* __restrict__ anc, const double* __restrict__ box_cx,
+// -------------------------------------------------------------------------
+// Far field and the near-field reduction, one work-group per leaf, thread i =
+// node i: L2P of the leaf's full local expansion by Horner in the scaled node
+// position, M2P for list 3 by Horner in h_w/z, the list-1 sums of the
+// near-field GEMM (in list order, deterministic) and the log(h) a_0 terms
+// of the near field.  The expansions used are the same for the whole
+// work-group (uniform addresses: scalar loads and SGPR operands).
+template <int PM, bool EXACT>
+__global__ void __launch_bounds__(256) k_far(int K, int Prt, double root_size, const int* __restrict__ leaf_box,
+                                             const int* __restrict__ box_level, const double* __restrict__ box_cx,
                                              const double* __restrict__ box_cy, const double* __restrict__ t,
                                              const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
-                                             const double* __restrict__ pasL, const double2* __restrict__ local,
-                                             const double2* __restrict__ mpole, const int* __restrict__ l1_ptr,
-                                             const int* __restrict__ l1_srcbox, const int* __restrict__ l1_slot,
-                                             const double* __restrict__ Y, double* __restrict__ V) {
-  __shared__ double2 s_loc[64];
-  __shared__ double2 s_w[kFarCap * 64];
-  __shared__ double2 s_part[kFarCap * 64];
-  __shared__ double2 s_m3[kFarCap * 64];
-  __shared__ double s_c3[3 * kFarCap];
-  __shared__ int s_slot[64], s_sbox[64], s_anc[kFarCap], s_l3[kFarCap];
-  __shared__ double s_a0[64];
+                                             const double2* __restrict__ locf, const double2* __restrict__ mpole,
+                                             const int* __restrict__ l1_ptr, const int* __restrict__ l1_srcbox,
+                                             const int* __restrict__ l1_slot, const double* __restrict__ Y,
+                                             double* __restrict__ V) {
+  const int P = EXACT ? PM : Prt;
   const int n = K * K;
-  const int nt = blockDim.x;
   const int leaf = blockIdx.x;
   const int i = threadIdx.x;
   const int b = leaf_box[leaf];
   const int lev = box_level[b];
   const double h = box_side(root_size, lev);
-  const int e0 = l1_ptr[leaf], n1 = l1_ptr[leaf + 1] - e0;
-  const int a0 = anc_ptr[leaf], m = lev >= 2 ? anc_ptr[leaf + 1] - a0 : 0;
-  const int f0 = l3_ptr[leaf], n3 = l3_ptr[leaf + 1] - f0;
-  const int cap = min(kFarCap, nt / P);
   const int ii = i < n ? i : 0;
   const double tx = 0.5 * t[ii / K], ty = 0.5 * t[ii % K];
-  const double bcx = box_cx[b], bcy = box_cy[b];
-  const int A = i / P, k = i - A * P;  // (ancestor or list-3 entry, coefficient) of this thread
-  // round 1: list indices
-  if (i < n1) {
-    s_slot[i] = l1_slot[e0 + i];
-    s_sbox[i] = l1_srcbox[e0 + i];
-  }
-  if (i < kFarCap && i < m) s_anc[i] = anc[a0 + i];
-  if (i < kFarCap && i < n3) s_l3[i] = l3_src[f0 + i];
-  __syncthreads();
-  // round 2: the data (first chunk of each list)
-  double2 q = make_double2(0.0, 0.0);  // r/w of this thread's ancestor
-  auto stage_anc = [&](int c0) {
-    if (A < min(cap, m - c0)) {
-      const int id = s_anc[A];
-      const int la = box_level[id];
-      const double hA = box_side(root_size, la);
-      const double2 wA = make_double2((bcx - box_cx[id]) / hA, (bcy - box_cy[id]) / hA);
-      const double rA = ldexp(1.0, la - lev);
-      const double ww = wA.x * wA.x + wA.y * wA.y;
-      q = make_double2(rA * wA.x / ww, -rA * wA.y / ww);
-      s_w[A * 64 + k] = cmul(cpow(wA, k), local[(size_t)id * P + k]);
-    }
-  };
-  auto stage_l3 = [&](int c0) {
-    if (A < min(cap, n3 - c0)) {
-      const int w = s_l3[A];
-      s_m3[A * 64 + k] = mpole[(size_t)w * P + k];
-      if (k == 0) {
-        s_c3[3 * A] = box_side(root_size, box_level[w]);
-        s_c3[3 * A + 1] = box_cx[w];
-        s_c3[3 * A + 2] = box_cy[w];
-      }
-    }
-  };
-  if (lev >= 2 && i < P) s_loc[i] = local[(size_t)b * P + i];
-  stage_anc(0);
-  stage_l3(0);
-  double acc = 0.0;
-  {
-    // (a leaf has at most one list-1 entry per configuration: n1 <= 33)
-    double yn = 0.0;
-    if (i < n1) s_a0[i] = mpole[(size_t)s_sbox[i] * P].x;
-    if (i < n) {
+  // near field: list-1 partial sums and the log terms (a leaf has at most
+  // one list-1 entry per configuration)
+  const int e0 = l1_ptr[leaf], n1 = l1_ptr[leaf + 1] - e0;
+  double yn = 0.0, lg = 0.0;
 #pragma unroll 4
-      for (int e = 0; e < n1; ++e) yn += Y[(size_t)s_slot[e] * n + i];
-    }
-    acc = h * h * yn;
+  for (int e = 0; e < n1; ++e) {
+    yn += Y[(size_t)l1_slot[e0 + e] * n + ii];
+    lg += mpole[(size_t)l1_srcbox[e0 + e] * P].x;
   }
-  __syncthreads();
-  {
-    double lg = 0.0;
-    for (int e = 0; e < n1; ++e) lg += s_a0[e];
-    acc += log(h) * lg;
-  }
-  // local expansion of the leaf: own part plus the shifted ancestor parts
+  double acc = h * h * yn + log(h) * lg;
+  // L2P
   if (lev >= 2) {
-    for (int c0 = 0; c0 < m; c0 += cap) {
-      const int cm = min(cap, m - c0);
-      if (c0 > 0) {
-        __syncthreads();
-        if (i < cm) s_anc[i] = anc[a0 + c0 + i];
-        __syncthreads();
-        stage_anc(c0);
-        __syncthreads();
-      }
-      if (A < cm) {
-        double ur = 0.0, ui = 0.0, ur2 = 0.0, ui2 = 0.0;
-        int kk = k;
-        for (; kk + 1 < P; kk += 2) {
-          const double cf = pasL[k * P + kk], cf2 = pasL[k * P + kk + 1];
-          ur += cf * s_w[A * 64 + kk].x;
-          ui += cf * s_w[A * 64 + kk].y;
-          ur2 += cf2 * s_w[A * 64 + kk + 1].x;
-          ui2 += cf2 * s_w[A * 64 + kk + 1].y;
-        }
-        if (kk < P) {
-          const double cf = pasL[k * P + kk];
-          ur += cf * s_w[A * 64 + kk].x;
-          ui += cf * s_w[A * 64 + kk].y;
-        }
-        s_part[A * 64 + k] = cmul(cpow(q, k), make_double2(ur + ur2, ui + ui2));
-      }
-      __syncthreads();
-      if (i < P) {
-        double2 c = s_loc[i];
-        for (int j = 0; j < cm; ++j) {
-          c.x += s_part[j * 64 + i].x;
-          c.y += s_part[j * 64 + i].y;
-        }
-        s_loc[i] = c;
-      }
+    const double2* c = locf + (size_t)leaf * P;
+    double2 u = c[P - 1];
+#pragma unroll
+    for (int l = P - 2; l >= 0; --l) {
+      const double ur = u.x * tx - u.y * ty, ui = u.x * ty + u.y * tx;
+      u = make_double2(ur + c[l].x, ui + c[l].y);
     }
-    __syncthreads();
-    if (i < n) {
-      double2 u = s_loc[P - 1];
-      for (int l = P - 2; l >= 0; --l) {
-        const double ur = u.x * tx - u.y * ty, ui = u.x * ty + u.y * tx;
-        u = make_double2(ur + s_loc[l].x, ui + s_loc[l].y);
-      }
-      acc += u.x;
-    }
+    acc += u.x;
   }
   // M2P for list 3
-  const double xi = bcx + h * tx;
-  const double yi = bcy + h * ty;
-  for (int c0 = 0; c0 < n3; c0 += cap) {
-    const int cm = min(cap, n3 - c0);
-    if (c0 > 0) {
-      __syncthreads();
-      if (i < cm) s_l3[i] = l3_src[f0 + c0 + i];
-      __syncthreads();
-      stage_l3(c0);
-      __syncthreads();
+  const double xi = box_cx[b] + h * tx;
+  const double yi = box_cy[b] + h * ty;
+  const int f0 = l3_ptr[leaf], n3 = l3_ptr[leaf + 1] - f0;
+  for (int j = 0; j < n3; ++j) {
+    const int w = l3_src[f0 + j];
+    const double hw = box_side(root_size, box_level[w]);
+    const double2* a = mpole + (size_t)w * P;
+    const double zx = xi - box_cx[w], zy = yi - box_cy[w];
+    const double r2 = zx * zx + zy * zy;
+    // zeta = hw / z
+    const double iv = hw / r2;
+    const double zr = zx * iv, zi = -zy * iv;
+    double sr = 0.0, si = 0.0;  // Horner: sum_{k>=1} a_k zeta^k
+#pragma unroll
+    for (int kk = P - 1; kk >= 1; --kk) {
+      const double ar = sr + a[kk].x, ai = si + a[kk].y;
+      sr = ar * zr - ai * zi;
+      si = ar * zi + ai * zr;
     }
-    if (i < n)
-      for (int j = 0; j < cm; j += 2) {
-        // two entries at a time (the second a zero expansion at distance 1
-        // when cm is odd), their Horner chains interleaved
-        const bool two = j + 1 < cm;
-        const int j2 = two ? j + 1 : j;
-        const double hw = s_c3[3 * j], hw2 = s_c3[3 * j2];
-        const double zx = xi - s_c3[3 * j + 1], zy = yi - s_c3[3 * j + 2];
-        const double zx2 = xi - s_c3[3 * j2 + 1], zy2 = yi - s_c3[3 * j2 + 2];
-        const double r2 = zx * zx + zy * zy, r22 = zx2 * zx2 + zy2 * zy2;
-        // zeta = hw / z
-        const double iv = hw / r2, iv2 = hw2 / r22;
-        const double zr = zx * iv, zi = -zy * iv, zr2 = zx2 * iv2, zi2 = -zy2 * iv2;
-        const double2* a = s_m3 + j * 64;
-        const double2* a2 = s_m3 + j2 * 64;
-        const double m2 = two ? 1.0 : 0.0;
-        double sr = 0.0, si = 0.0, sr2 = 0.0, si2 = 0.0;  // Horner: sum_{k>=1} a_k zeta^k
-        for (int kk = P - 1; kk >= 1; --kk) {
-          const double ar = sr + a[kk].x, ai = si + a[kk].y;
-          const double ar2 = sr2 + m2 * a2[kk].x, ai2 = si2 + m2 * a2[kk].y;
-          sr = ar * zr - ai * zi;
-          si = ar * zi + ai * zr;
-          sr2 = ar2 * zr2 - ai2 * zi2;
-          si2 = ar2 * zi2 + ai2 * zr2;
-        }
-        acc += a[0].x * 0.5 * log(r2) + sr;
-        if (two) acc += a2[0].x * 0.5 * log(r22) + sr2;
-      }
+    acc += a[0].x * 0.5 * log(r2) + sr;
   }
   if (i < n) V[(size_t)leaf * n + i] = kInv2Pi * acc;
 }
@@ -1185,6 +1161,9 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.l3_src, H.l3_src);
   UP(D.anc_ptr, H.anc_ptr);
   UP(D.anc, H.anc);
+  UP(D.anc_leaf, H.anc_leaf);
+  UP(D.dn_grp, H.dn_grp);
+  VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P));
   UP(D.up_box, H.up_box);
   UP(D.up_ptr, H.up_ptr);
   UP(D.up_src, H.up_src);
@@ -1242,7 +1221,8 @@ void free_plan_device(Plan* p) {
                   D.pinv_idx,  D.pinv_val,   D.sbar_given, D.mpole,    D.local,    D.t0_cfg,   D.t0_first,
                   D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp,  D.up_box,   D.up_ptr,   D.up_src,
                   D.up_pos,    D.up_split,   D.up_grp,   D.up_part,  D.anc_ptr,  D.anc,
-                  D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo};
+                  D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
+                  D.anc_leaf,  D.dn_grp,     D.locf};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -1269,7 +1249,7 @@ static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, co
 }
 
 // Dense near-field tables: MT = n/16 row tiles (1, 4, 9 or 16 for K = 4, 8,
-// 12, 16), in blocks of MTB = 1, 4, 9, 8.
+// 12, 16), in blocks of MTB = 1, 4, 9, 4.
 static void near_gemm(int n, int ntiles, const int* cfg, const int* first, const int* count, const int* src,
                       const double* A, const double* X, double* Y, hipStream_t s, int max_wgs) {
   if (ntiles <= 0) return;
@@ -1278,7 +1258,7 @@ static void near_gemm(int n, int ntiles, const int* cfg, const int* first, const
     case 16: launch_gemm<16, 0, 64, 1>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
     case 64: launch_gemm<64, 0, 64, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
     case 144: launch_gemm<144, 0, 64, 9>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
-    default: launch_gemm<256, 0, 64, 8>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
+    default: launch_gemm<256, 0, 64, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
   }
 }
 
@@ -1438,14 +1418,45 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   }
   VFX_HIP(hipGetLastError());
   MARK(3, s);
-  // (the downward shifts are applied per leaf in the far-field kernel)
+  // full local expansions of the leaves (downward pass)
+  {
+    const int ng = (int)H.dn_grp.size() - 1;
+#define VFX_DOWN(PMV, EX)                                                                                          \
+  hipLaunchKernelGGL((k_down<PMV, EX>), dim3(ng), dim3(64), 0, s, P, T.root_size, D.dn_grp, D.anc_ptr, D.anc,      \
+                     D.anc_leaf, D.leaf_box, D.box_level, D.box_cx, D.box_cy, DT.pas_l2l_t, D.local, D.locf)
+    if (P == 21)
+      VFX_DOWN(21, true);
+    else if (P == 25)
+      VFX_DOWN(25, true);
+    else if (P == 31)
+      VFX_DOWN(31, true);
+    else if (P == 41)
+      VFX_DOWN(41, true);
+    else if (P <= 32)
+      VFX_DOWN(32, false);
+    else
+      VFX_DOWN(64, false);
+#undef VFX_DOWN
+  }
   VFX_HIP(hipGetLastError());
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(7, s);
-  hipLaunchKernelGGL(k_far, dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box, D.box_level,
-                     D.anc_ptr, D.anc, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, DT.pas_l2l_t, D.local,
-                     D.mpole, D.l1_ptr, D.l1_srcbox, D.l1_slot, D.near_y, V);
+#define VFX_FAR(PMV, EX)                                                                                       \
+  hipLaunchKernelGGL((k_far<PMV, EX>), dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box,  \
+                     D.box_level, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, D.locf, D.mpole, D.l1_ptr,     \
+                     D.l1_srcbox, D.l1_slot, D.near_y, V)
+  if (P == 21)
+    VFX_FAR(21, true);
+  else if (P == 25)
+    VFX_FAR(25, true);
+  else if (P == 31)
+    VFX_FAR(31, true);
+  else if (P == 41)
+    VFX_FAR(41, true);
+  else
+    VFX_FAR(64, false);
+#undef VFX_FAR
   VFX_HIP(hipGetLastError());
   MARK(8, s);
   if (timed) p->n_timed++;

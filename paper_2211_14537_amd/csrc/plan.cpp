@@ -381,11 +381,27 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
       u = v;
     }
     H.up_slots = slots;
+    // downward pass: (leaf, ancestor at level >= 2) pairs, nearest ancestor
+    // first, and wave groups of <= 8 leaves with <= 64 pairs
     H.anc_ptr.assign(L + 1, 0);
     for (int leaf = 0; leaf < L; ++leaf) {
-      for (int a = H.box_parent[H.leaf_box[leaf]]; a >= 0 && H.box_level[a] >= 2; a = H.box_parent[a])
+      for (int a = H.box_parent[H.leaf_box[leaf]]; a >= 0 && H.box_level[a] >= 2; a = H.box_parent[a]) {
         H.anc.push_back(a);
+        H.anc_leaf.push_back(leaf);
+      }
       H.anc_ptr[leaf + 1] = (int)H.anc.size();
+    }
+    int f = 0;
+    H.dn_grp.push_back(0);
+    while (f < L) {
+      int g = f;
+      while (g < L && g - f < 8 && H.anc_ptr[g + 1] - H.anc_ptr[f] <= 64) ++g;
+      if (g == f) {
+        err = "internal: more than 64 ancestors";
+        return VFX_EINVAL;
+      }
+      H.dn_grp.push_back(g);
+      f = g;
     }
   }
   // ---- list-4 entries grouped by P2L slot --------------------------------

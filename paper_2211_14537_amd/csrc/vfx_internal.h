@@ -130,7 +130,8 @@ struct HostPlan {
   // pairs, wave groups {pos0, pos1, e0, e1, slot} and split boxes
   // {box, slot0, nslots}
   std::vector<int> up_box, up_ptr, up_src, up_pos, up_grp, up_split;
-  std::vector<int> anc_ptr, anc;             // per leaf: ancestors at level >= 2, nearest first
+  std::vector<int> anc_ptr, anc, anc_leaf;   // per leaf: ancestors at level >= 2, nearest first
+  std::vector<int> dn_grp;                   // leaf groups of the downward kernel
   int up_slots = 0;
   std::vector<int> l4_ptr, l4_src, l4_cfg;   // per box (source leaves)
   // list-1 pairs regrouped by table configuration (config-major, targets
@@ -166,7 +167,8 @@ struct DevicePlan {
   int *up_box = nullptr, *up_ptr = nullptr, *up_src = nullptr, *up_pos = nullptr, *up_grp = nullptr,
       *up_split = nullptr;
   double2* up_part = nullptr;
-  int *anc_ptr = nullptr, *anc = nullptr;  // partial multipoles of split boxes, up_slots x (p+1)
+  int *anc_ptr = nullptr, *anc = nullptr, *anc_leaf = nullptr, *dn_grp = nullptr;
+  double2* locf = nullptr;  // full local expansion of every leaf, L x (p+1)  // partial multipoles of split boxes, up_slots x (p+1)
   int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
   int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;
   int *nl_cfg = nullptr, *nl_first = nullptr, *nl_count = nullptr;
