@@ -28,31 +28,94 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_work(stats, K, p, nX_total_interior):
-    """Algorithmic flops and HBM bytes per launch of each phase (FP64)."""
+# phase -> (kernel name as in a kernel trace, marker comment that opens its
+# source block in kernels.hip); a phase of several kernels names the one
+# that dominates it.  The roofline object describes the slowest phase that
+# is a single kernel launch (the others hold several launches, and their
+# event-timed spans include waits for the other stream).
+SINGLE_KERNEL_PHASES = ("extension", "down", "near_lowrank", "near_dense", "far")
+PHASE_KERNEL = {
+    "extension": ("k_extension", "// Extension of one cut leaf per work-group"),
+    "p2m_up": ("k_up", "// Upward pass without the level-by-level chain."),
+    "m2l_p2l": ("k_m2l_lanes", "// M2L: one lane per list-2 entry"),
+    "down": ("k_down", "// Downward pass without the level-by-level chain"),
+    "near_lowrank": ("k_near_lr", "// Near field in low-rank form"),
+    "near_dense": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
+    "far": ("k_far", "// Far field and the near-field reduction"),
+}
+
+
+def algorithmic_work(case):
+    """Algorithmic FP64 flops and HBM bytes of one execute, per phase.
+
+    Flops count the arithmetic the method needs (a complex multiply-add is 8
+    flops), bytes the compulsory HBM traffic (every operand read once, every
+    result written once)."""
+    import numpy as np
+    plan, ctx = case["plan"], case["ctx"]
+    st = plan.stats()
+    K = case["K"]
     n = K * K
-    P = p + 1
-    L = stats["n_leaves"]
-    B = stats["n_boxes"]
-    N1, N2, N3, N4 = stats["n_list1"], stats["n_list2"], stats["n_list3"], stats["n_list4"]
+    P = case["p"] + 1
+    L, B = st["n_leaves"], st["n_boxes"]
+    N2, N3, N4 = st["n_list2"], st["n_list3"], st["n_list4"]
     nG = 66
-    ext_targets = stats["n_ext_targets"]
-    ncut = stats["n_cut"]
+    ext_targets, ncut = st["n_ext_targets"], st["n_cut"]
+    ptr, src, cfg = plan.lists(1)
+    counts = np.bincount(cfg, minlength=33)
+    rk = ctx.debug_table(22, 0, 66)
+    lrR, rank = rk[:33].astype(int), rk[33:].astype(int)
+    lr = lrR > 0
+    n_lr, n_dense = int(counts[lr].sum()), int(counts[~lr].sum())
+    # pairs (box, leaf below it) of the direct upward/downward passes
+    lev = np.asarray(case["tree"]["level"])
+    n_pairs_ud = int(np.maximum(lev - 2, 0).sum())
+    nI = case["interior"]
     work = {
-        # per pair: n x n table times n values (2 n^2 flops); the leaf data is
-        # read once and V written once; the 33 tables are read once
-        "near": (2.0 * n * n * N1, 8.0 * (2 * L * n + 33 * n * n)),
-        # P_i (nG x N_I) streamed once, plus the gathered interior samples,
-        # f_leaf read / f^e written for every leaf, and the list targets
-        "extension": (2.0 * nG * nX_total_interior + ncut * (2 * nG * 144 + 4 * 144 * 12)
-                      + ext_targets * (2 * 12 * 12 * K + 2 * 12 * n),
-                      8.0 * (nG * nX_total_interior + nX_total_interior + 2 * L * n + ext_targets * n)),
-        "p2m_m2m": (8.0 * P * n * L + 8.0 * P * P * 4 * (B - L) / 2, 8.0 * (L * n + 2 * B * P)),
-        "m2l_p2l": (8.0 * P * P * N2 + 8.0 * P * n * N4, 16.0 * 2 * B * P),
-        "l2l": (4.0 * P * P * B, 16.0 * 2 * B * P),
-        "far": (8.0 * P * n * L + 8.0 * P * n * N3, 8.0 * 2 * L * n + 16.0 * B * P),
+        "extension": (2.0 * nG * nI + ncut * (2 * nG * 144 + 4 * 144 * 12) + ext_targets * (2 * 12 * 12 * K + 2 * 12 * n),
+                      8.0 * (nG * nI + nI + ncut * 144 + (L + ext_targets) * n)),
+        "p2m_up": (8.0 * P * n * L / 2 + 8.0 * P * P / 2 * n_pairs_ud, 8.0 * L * n + 16.0 * B * P),
+        "m2l_p2l": (8.0 * P * P * N2 + 4.0 * P * n * N4, 16.0 * 2 * B * P + 8.0 * N4 * n),
+        "down": (8.0 * P * P / 2 * n_pairs_ud, 16.0 * (B + L) * P),
+        # low-rank near field: W (r x n) then Q (n x r) per pair, true ranks;
+        # bytes: every leaf's samples once, one n-vector written per pair,
+        # the factors once
+        "near_lowrank": (float((counts * 4.0 * n * rank)[lr].sum()),
+                         8.0 * (L * n + n * n_lr) + 8.0 * 2 * n * 64 * int(lr.sum())),
+        "near_dense": (2.0 * n * n * n_dense, 8.0 * (L * n + n * n_dense) + 8.0 * n * n * int((~lr).sum())),
+        "far": (8.0 * P * n * L + (8.0 * P + 40) * n * N3, 8.0 * n * st["n_list1"] + 8.0 * L * n + 16.0 * (L + N3) * P),
     }
     return work
+
+
+def kernel_digest(marker):
+    """Digest of the source block of a kernel in kernels.hip (from its
+    opening comment to the next separator line)."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2211_14537_amd", "csrc", "kernels.hip")).read()
+    i = src.find(marker)
+    if i < 0:
+        return None
+    j = src.find("// ------", i + len(marker))
+    return hashlib.sha256(src[i:j if j > 0 else len(src)].encode()).hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, digest):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel factor), or
+    None if there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("traffic:"):
+            for kv in line[len("traffic:"):].split():
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("digest") != digest:
+        return None
+    return float(vals["bytes_per_launch"])
 
 
 def cpu_baseline(case, target_seconds=15.0):
@@ -86,7 +149,43 @@ def cpu_baseline(case, target_seconds=15.0):
         "sample": f"float64 extension of all {len(info)} cut leaves ({t_ext:.2f} s) + direct quadrature "
                   f"of V at {ns} seeded nodes ({t_v * ns:.2f} s), scaled to {N} nodes "
                   f"(estimated full oracle time {full:.0f} s)",
-    }, (sel2, v, fe)
+    }, (sel2, v, fe, info)
+
+
+def accuracy_check(case, plan, fe_gpu, sel, v_o, fe_o, info, dev):
+    """Accuracy of the measured configuration against the oracle.
+
+    volume: the library's V of the oracle's extended data (an all-regular
+    plan of the same tree) against the oracle's direct quadrature of it, at
+    the sampled nodes; extension: the library's extended values against the
+    oracle's float64 extension, as the worst ratio to the least-squares
+    forward-error bound (<= 1 passes)."""
+    import numpy as np
+    import torch
+    from oracle import extension
+    from paper_2211_14537_amd import vfx
+    tr = case["tree"]
+    plan_v = vfx.Plan(case["ctx"], tr["level"], tr["ix"], tr["iy"], np.ones_like(tr["kind"]))
+    fo = torch.tensor(fe_o, dtype=torch.float64, device=dev)
+    Vv = torch.empty_like(fo)
+    fe2 = torch.empty_like(fo)
+    plan_v.execute(fo, fo, fe2, Vv)
+    torch.cuda.synchronize()
+    Vg = Vv.cpu().numpy().ravel()[sel]
+    feg = fe_gpu.cpu().numpy()
+    worst = 0.0
+    cut_ids = list(tr["cut_ids"])
+    for i, rec in info.items():
+        tg = rec["targets"]
+        r = cut_ids.index(i)
+        f_int = case["f_cut"][r][tr["mask"][r] != 0]
+        tol = extension.extension_tolerance(rec, fe_o[tg], f_int)
+        worst = max(worst, float(np.abs(feg[tg] - fe_o[tg]).max()) / tol)
+    return {"volume_nodes": int(sel.size),
+            "volume_rel_linf_vs_oracle": float(np.abs(Vg - v_o).max() / np.abs(v_o).max()),
+            "extension_worst_error_over_bound": worst,
+            "note": "V of the oracle's float64 extension, library vs direct quadrature; extension vs oracle "
+                    "within 16 u cond(A_I) max|f|"}
 
 
 def build_case(name, p):
@@ -120,6 +219,8 @@ def main():
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs the path on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -149,27 +250,34 @@ def main():
     t1 = time.perf_counter()
     phases = plan.timings()
     plan.set_timing(False)
+    if args.copy_calibration:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        bcopy = torch.empty_like(a)
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        del a, bcopy
     elapsed = t1 - t0
     N = st["n_leaves"] * case["K"] ** 2
     value = N * args.steps / elapsed
 
-    work = algorithmic_work(st, case["K"], case["p"], case["interior"])
-    dom = max((k for k in work), key=lambda k: phases[k])
+    work = algorithmic_work(case)
+    dom = max(SINGLE_KERNEL_PHASES, key=lambda k: phases[k])
     flops, nbytes = work[dom]
     sec = phases[dom] * 1e-3
-    intensity = flops / nbytes
-    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if intensity >= ridge:
+    t_mfma = flops / (FP64_PEAK_TFLOPS * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    if t_mfma >= t_hbm:
         roof = {"bound": "mfma", "achieved": flops / sec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = {"near": "k_near", "extension": "k_fe_init+k_extension", "p2m_m2m": "k_p2m+k_m2m",
-                      "m2l_p2l": "k_m2l", "l2l": "k_l2l", "far": "k_far"}[dom]
-    roof["phase_ms"] = phases[dom]
+    kname, marker = PHASE_KERNEL[dom]
+    roof["traffic"] = load_traffic(kname, case["cfg"]["name"], kernel_digest(marker))
+    roof["kernel"] = kname
+    roof["kernel_ms"] = phases[dom]
     roof["algorithmic_flops"] = flops
     roof["algorithmic_bytes"] = nbytes
+    roof["roofline_ms"] = 1e3 * max(t_mfma, t_hbm)
 
     out = {
         "metric": METRIC, "value": value, "unit": "leaf points/s", "n_gpus": 1, "steps": args.steps,
@@ -183,12 +291,9 @@ def main():
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        base, (sel, v_o, fe_o) = cpu_baseline(case, args.baseline_seconds)
+        base, (sel, v_o, fe_o, info) = cpu_baseline(case, args.baseline_seconds)
         out["cpu_baseline"] = base
-        Vg = V.cpu().numpy().ravel()[sel]
-        out["check"] = {"nodes": int(sel.size),
-                        "rel_linf_vs_oracle": float(np.abs(Vg - v_o).max() / np.abs(v_o).max()),
-                        "note": "GPU V against the oracle's V of the oracle's float64 extension"}
+        out["check"] = accuracy_check(case, plan, fe, sel, v_o, fe_o, info, dev)
     print(json.dumps(out), flush=True)
 
 

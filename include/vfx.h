@@ -130,18 +130,23 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
 int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
                 double* V_out, void* stream);
 
-/* Per-phase timing with HIP events.  The near-field GEMM runs on a side
+/* Per-phase timing with HIP events.  The near-field kernels run on a side
  * stream of the plan (default priority), forked from `stream` after the
- * extension and joined before the far-field kernel; its phase is timed with
- * events on that side stream, the others on `stream`.  While enabled, every
- * vfx_execute records its events (at most 4096 executes are recorded;
+ * extension and joined before the far-field kernel; their phases are timed
+ * with events on that side stream, the others on `stream`.  While enabled,
+ * every vfx_execute records its events (at most 4096 executes are recorded;
  * enabling again restarts the count).  The query synchronises on the last
  * recorded event and returns, averaged over the recorded executes, the
- * milliseconds of: extension (f^e assembly and the cut-leaf kernel),
- * P2M+M2M, M2L+P2L, L2L, near field, far field (near-field reduction,
- * L2P, M2P), total; ms[7] (if n_out >= 8) receives the number of executes
- * averaged.  Phases on the two streams overlap, so they do not add up to the
- * total.  n_out must be >= 7. */
+ * milliseconds of eight phases:
+ *   ms[0] extension (f^e assembly and the cut-leaf kernel)
+ *   ms[1] P2M and the upward pass        ms[2] P2L and M2L
+ *   ms[3] downward pass (leaf local expansions)
+ *   ms[4] near field, low-rank operators (side stream)
+ *   ms[5] near field, dense operators (side stream)
+ *   ms[6] far field (near-field reduction, L2P, M2P)   ms[7] total
+ * and ms[8] (if n_out >= 9) the number of executes averaged.  Phases on the
+ * two streams overlap, so they do not add up to the total.  n_out must be
+ * >= 8. */
 int vfx_plan_set_timing(vfx_plan* plan, int enable);
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
 

@@ -172,27 +172,28 @@ int vfx_plan_set_timing(vfx_plan* plan, int enable) {
 }
 
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
-  if (!plan || !ms || n_out < 7) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
+  constexpr int NP = 8;  // phases
+  if (!plan || !ms || n_out < NP) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
   vfx::Plan& p = plan->p;
   constexpr int NE = vfx::Plan::kEvents;
   if (p.n_timed == 0) return fail(VFX_EINVAL, "vfx_plan_timings: no timed execute recorded");
-  hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * NE + 8]);
+  hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * NE + 9]);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
   // phase k runs from event a[k] to event b[k]
-  static const int a_[7] = {0, 1, 2, 3, 5, 7, 0};
-  static const int b_[7] = {1, 2, 3, 4, 6, 8, 8};
-  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  static const int a_[NP] = {0, 1, 2, 3, 5, 6, 8, 0};
+  static const int b_[NP] = {1, 2, 3, 4, 6, 7, 9, 9};
+  double acc[NP] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < p.n_timed; ++r) {
     const hipEvent_t* ev = &p.ev[(size_t)r * NE];
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < NP; ++k) {
       float t = 0;
       e = hipEventElapsedTime(&t, ev[a_[k]], ev[b_[k]]);
       if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
       acc[k] += t;
     }
   }
-  for (int k = 0; k < 7; ++k) ms[k] = acc[k] / p.n_timed;
-  if (n_out >= 8) ms[7] = p.n_timed;
+  for (int k = 0; k < NP; ++k) ms[k] = acc[k] / p.n_timed;
+  if (n_out > NP) ms[NP] = p.n_timed;
   return VFX_OK;
 }
 

@@ -1315,8 +1315,9 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
     }
   }
   // events on the caller's stream: 0 start, 1 after the extension, 2 after
-  // P2M+M2M, 3 after M2L+P2L, 4 after L2L, 7 after the join, 8 end; on the
-  // side stream: 5 and 6 around the near-field GEMM
+  // P2M and the upward pass, 3 after P2L+M2L, 4 after the downward pass, 8
+  // after the join, 9 end; on the side stream: 5 start, 6 after the low-rank
+  // near-field kernel, 7 after the dense one
   auto mark = [&](int k, hipStream_t st) -> int {
     if (timed) {
       hipError_t e = hipEventRecord(p->ev[ev0 + k], st);
@@ -1344,9 +1345,8 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipGetLastError());
   MARK(1, s);
   // fork: near field on the side stream, concurrent with P2M, the upward
-  // pass and M2L/P2L on the caller's stream.  Its grid is
-  // bounded (about two work-groups per CU, looping over the tiles) so the
-  // latency-bound tree kernels keep CU slots.
+  // pass, P2L/M2L and the downward pass on the caller's stream.  Its grids
+  // are bounded (about two work-groups per CU, looping over the tiles).
   VFX_HIP(hipEventRecord(p->fork_ev, s));
   VFX_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
   MARK(5, p->side);
@@ -1355,10 +1355,11 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
     hipLaunchKernelGGL(k_near_lr<256>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, D.nl_cfg,
                        D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y);
   }
+  MARK(6, p->side);
   near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
             kNearWgs);
   VFX_HIP(hipGetLastError());
-  MARK(6, p->side);
+  MARK(7, p->side);
   VFX_HIP(hipEventRecord(p->join_ev, p->side));
   // multipoles of the leaves
   expansion_gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
@@ -1441,7 +1442,7 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipGetLastError());
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
-  MARK(7, s);
+  MARK(8, s);
 #define VFX_FAR(PMV, EX)                                                                                       \
   hipLaunchKernelGGL((k_far<PMV, EX>), dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box,  \
                      D.box_level, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, D.locf, D.mpole, D.l1_ptr,     \
@@ -1458,7 +1459,7 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
     VFX_FAR(64, false);
 #undef VFX_FAR
   VFX_HIP(hipGetLastError());
-  MARK(8, s);
+  MARK(9, s);
   if (timed) p->n_timed++;
   return VFX_OK;
 }

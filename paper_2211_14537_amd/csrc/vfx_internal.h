@@ -193,7 +193,7 @@ struct Plan {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // per-phase timing: one set of kEvents events per timed execute
-  static constexpr int kEvents = 9;
+  static constexpr int kEvents = 10;
   bool timing = false;
   std::vector<hipEvent_t> ev;   // kEvents * capacity
   int n_timed = 0;

@@ -215,15 +215,15 @@ class Plan:
     def set_timing(self, on=True):
         _check(lib().vfx_plan_set_timing(self._h, 1 if on else 0))
 
-    PHASES = ("extension", "p2m_m2m", "m2l_p2l", "l2l", "near", "far", "total")
+    PHASES = ("extension", "p2m_up", "m2l_p2l", "down", "near_lowrank", "near_dense", "far", "total")
 
     def timings(self):
         """Per-phase milliseconds averaged over the executes recorded since
         set_timing(True), plus their count."""
-        ms = np.zeros(8)
-        _check(lib().vfx_plan_timings(self._h, _ptr(ms, ctypes.c_double), 8))
-        out = dict(zip(self.PHASES, ms[:7].tolist()))
-        out["count"] = int(ms[7])
+        ms = np.zeros(len(self.PHASES) + 1)
+        _check(lib().vfx_plan_timings(self._h, _ptr(ms, ctypes.c_double), ms.size))
+        out = dict(zip(self.PHASES, ms[:-1].tolist()))
+        out["count"] = int(ms[-1])
         return out
 
     def close(self):
