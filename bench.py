@@ -118,8 +118,11 @@ def load_traffic(kernel, workload, digest):
     return float(vals["bytes_per_launch"])
 
 
-def cpu_baseline(case, target_seconds=15.0):
-    """Oracle timed on a bounded sample of the workload, scaled to it."""
+def oracle_sample(case, ns, seed, calibrate_seconds=None):
+    """The oracle's float64 extension of every cut leaf and its direct
+    quadrature of V at ns seeded leaf nodes (or, with calibrate_seconds, at
+    as many as fit that time budget).  Returns the nodes, the values, the
+    extended data and per-leaf records, and the two times."""
     import numpy as np
     from oracle import extension, geometry, volume
 
@@ -130,29 +133,36 @@ def cpu_baseline(case, target_seconds=15.0):
     fe, info = extension.extend(ot, tr["kind"], f_leaf, f_cut, tr["mask"].astype(bool), K, precision="fp64")
     t_ext = time.perf_counter() - t0
     X, Y = ot.leaf_nodes(K)
-    rng = np.random.default_rng(12345)
-    # calibrate, then size the sample to the time budget
-    sel = rng.choice(X.size, 16, replace=False)
-    t0 = time.perf_counter()
-    v16 = volume.potential(ot, fe, K, X.ravel()[sel], Y.ravel()[sel])
-    per = (time.perf_counter() - t0) / 16
-    ns = int(max(16, min(4096, (target_seconds - t_ext) / max(per, 1e-6))))
+    rng = np.random.default_rng(seed)
+    if calibrate_seconds is not None:
+        sel = rng.choice(X.size, 16, replace=False)
+        t0 = time.perf_counter()
+        volume.potential(ot, fe, K, X.ravel()[sel], Y.ravel()[sel])
+        per = (time.perf_counter() - t0) / 16
+        ns = int(max(16, min(4096, (calibrate_seconds - t_ext) / max(per, 1e-6))))
     sel2 = rng.choice(X.size, ns, replace=False)
     t0 = time.perf_counter()
     v = volume.potential(ot, fe, K, X.ravel()[sel2], Y.ravel()[sel2])
-    t_v = (time.perf_counter() - t0) / ns
-    N = X.size
-    full = t_ext + t_v * N
+    t_v = time.perf_counter() - t0
+    return sel2, v, fe, info, t_ext, t_v
+
+
+def cpu_baseline(case, target_seconds=15.0):
+    """Oracle timed on a bounded sample of the workload, scaled to it."""
+    sel, v, fe, info, t_ext, t_v = oracle_sample(case, 0, 12345, calibrate_seconds=target_seconds)
+    ns = sel.size
+    N = case["tree"]["level"].size * case["K"] ** 2
+    full = t_ext + t_v / ns * N
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {
         "value": N / full, "unit": "leaf points/s", "cores": cores, "kind": "oracle",
         "sample": f"float64 extension of all {len(info)} cut leaves ({t_ext:.2f} s) + direct quadrature "
-                  f"of V at {ns} seeded nodes ({t_v * ns:.2f} s), scaled to {N} nodes "
+                  f"of V at {ns} seeded nodes ({t_v:.2f} s), scaled to {N} nodes "
                   f"(estimated full oracle time {full:.0f} s)",
-    }, (sel2, v, fe, info)
+    }, (sel, v, fe, info)
 
 
-def accuracy_check(case, plan, fe_gpu, sel, v_o, fe_o, info, dev):
+def accuracy_check(case, plan, fe_gpu, sel, v_o, fe_o, info, dev, args):
     """Accuracy of the measured configuration against the oracle.
 
     volume: the library's V of the oracle's extended data (an all-regular
@@ -166,6 +176,8 @@ def accuracy_check(case, plan, fe_gpu, sel, v_o, fe_o, info, dev):
     from paper_2211_14537_amd import vfx
     tr = case["tree"]
     plan_v = vfx.Plan(case["ctx"], tr["level"], tr["ix"], tr["iy"], np.ones_like(tr["kind"]))
+    if args.precision == "mixed":
+        plan_v.set_precision(1, args.min_level)
     fo = torch.tensor(fe_o, dtype=torch.float64, device=dev)
     Vv = torch.empty_like(fo)
     fe2 = torch.empty_like(fo)
@@ -219,6 +231,12 @@ def main():
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--baseline-seconds", type=float, default=15.0)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="near field in FP64 or in bf16 slices with FP32 accumulation")
+    ap.add_argument("--min-level", type=int, default=0,
+                    help="with --precision mixed: sources at this level or finer run mixed")
+    ap.add_argument("--check-nodes", type=int, default=0,
+                    help="without the CPU baseline: oracle accuracy check at this many seeded nodes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -232,6 +250,8 @@ def main():
     dev = torch.device("cuda:0")
     case = build_case(args.config, args.p)
     plan = case["plan"]
+    if args.precision == "mixed":
+        plan.set_precision(1, args.min_level)
     st = plan.stats()
     fl = torch.tensor(case["f_leaf"], dtype=torch.float64, device=dev)
     fc = torch.tensor(case["f_cut"], dtype=torch.float64, device=dev)
@@ -285,7 +305,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": case["cfg"]["name"], "leaves": st["n_leaves"], "nodes": N, "K": case["K"],
                    "p": case["p"], "levels": st["n_levels"], "cut_leaves": st["n_cut"],
-                   "ext_targets": st["n_ext_targets"], "precision": "fp64"},
+                   "ext_targets": st["n_ext_targets"],
+                   "precision": "fp64" if args.precision == "fp64" else
+                   f"mixed: near field of sources at level >= {args.min_level} in bf16 slices, FP32 accumulation"},
         "phases_ms": {k: round(v, 4) for k, v in phases.items() if k != "count"},
         "plan_s": st["plan_seconds"], "tables_s": case["t_ctx"],
         "roofline": roof,
@@ -293,7 +315,10 @@ def main():
     if not args.no_cpu_baseline:
         base, (sel, v_o, fe_o, info) = cpu_baseline(case, args.baseline_seconds)
         out["cpu_baseline"] = base
-        out["check"] = accuracy_check(case, plan, fe, sel, v_o, fe_o, info, dev)
+        out["check"] = accuracy_check(case, plan, fe, sel, v_o, fe_o, info, dev, args)
+    elif args.check_nodes > 0:
+        sel, v_o, fe_o, info, _, _ = oracle_sample(case, args.check_nodes, 12345)
+        out["check"] = accuracy_check(case, plan, fe, sel, v_o, fe_o, info, dev, args)
     print(json.dumps(out), flush=True)
 
 

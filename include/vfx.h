@@ -130,6 +130,61 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
 int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
                 double* V_out, void* stream);
 
+/* ---- refinement classifier (learned refine/keep decision) --------------
+ * A 64-64-64-1 perceptron with exact GELU activations whose input is the
+ * last four rows (16 values each) of a K = 16 leaf's Chebyshev coefficient
+ * array, in the order the host feature code fixes, and whose output logit
+ * means "refine" (the refinement test it learns is the plain coefficient-
+ * tail criterion of the tree; the host keeps that criterion as fallback and
+ * judge).  Parameters: one flat FP32 vector of vfx_mlp_param_count() values,
+ * W1 (64 x 64, [out][in]), b1, W2, b2, w3 (64), b3 (1).  All pointers are
+ * device memory, row-major (x: batch x 64); calls are asynchronous on
+ * `stream`; VFX_EINVAL for null pointers or bad sizes.
+ *   vfx_mlp_forward   FP32 logits
+ *   vfx_mlp_grad      gradient of the mean binary cross-entropy of the
+ *                     logits against labels y (0/1); `work` holds
+ *                     vfx_mlp_grad_work(batch) floats of per-tile partials,
+ *                     summed in tile order (deterministic)
+ *   vfx_mlp_adam      one Adam step (bias-corrected, step >= 1) on theta
+ *                     with moment buffers m, v
+ *   vfx_f32_to_f16    FP16 copy (round to nearest) of n floats
+ *   vfx_mlp_infer_f16 logits from FP16 parameters and FP16 inputs with FP32
+ *                     accumulation */
+int vfx_mlp_param_count(void);
+int64_t vfx_mlp_grad_work(int64_t batch);
+int vfx_mlp_forward(const float* theta, const float* x, int64_t batch, float* logits, void* stream);
+int vfx_mlp_grad(const float* theta, const float* x, const float* y, int64_t batch, float* grad, float* work,
+                 int64_t work_floats, void* stream);
+int vfx_mlp_adam(float* theta, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
+                 float eps, void* stream);
+int vfx_f32_to_f16(const float* a, uint16_t* h, int64_t n, void* stream);
+int vfx_mlp_infer_f16(const uint16_t* theta_h, const uint16_t* x_h, int64_t batch, float* logits, void* stream);
+
+/* Values at arbitrary points of data given on the leaf grids of the plan's
+ * tree (e.g. V_out, at the boundary nodes a boundary-integral solve needs):
+ * the tensor first-kind Chebyshev interpolant of the K x K samples of the
+ * leaf that holds each point (the paper evaluates V off the grid by
+ * interpolating the leaf expansions, \S4).  V: device, n_leaves x K^2 as in
+ * vfx_execute; px, py: device, npts coordinates; out: device, npts values
+ * (NaN for points outside the root box; a point on an edge between leaves
+ * uses the upper/right one).  Asynchronous on `stream`.  VFX_EINVAL for null
+ * pointers or npts < 0. */
+int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, const double* py, double* out,
+               void* stream);
+
+/* Precision of the near field (NEXT: mixed precision).  mode 0: FP64
+ * everywhere (the default).  mode 1: the list-1 interactions whose source
+ * leaf is at level >= min_level are applied with the operands split into
+ * three bf16 slices (about 24 significant bits) on the bf16 matrix cores
+ * with FP32 accumulation; their results, the log(h) terms, every multipole
+ * and local expansion, the M2L log term and the final sums stay FP64.  The
+ * near-field contribution of a source of side h scales like h^2, so a
+ * min_level bounds the error those interactions can add.  Available for
+ * K = 16 only (VFX_EINVAL otherwise, and the plan stays FP64).  The plan's
+ * device data are rebuilt on the next vfx_execute; the call synchronises the
+ * device and must not overlap an execute of the same plan. */
+int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level);
+
 /* Per-phase timing with HIP events.  The near-field kernels run on a side
  * stream of the plan (default priority), forked from `stream` after the
  * extension and joined before the far-field kernel; their phases are timed

@@ -164,6 +164,75 @@ int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, doubl
   }
 }
 
+int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level) {
+  if (!plan || (mode != 0 && mode != 1)) return fail(VFX_EINVAL, "vfx_plan_set_precision: mode must be 0 or 1");
+  vfx::Plan& p = plan->p;
+  try {
+    std::string err;
+    int rc = vfx::build_near_tiles(p.ctx->T, p.H, mode, mode == 1 ? min_level : 0, err);
+    if (rc) {
+      vfx::build_near_tiles(p.ctx->T, p.H, 0, 0, err);
+      return fail(rc, "vfx_plan_set_precision: " + err);
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_plan_set_precision: out of host memory");
+  }
+  vfx::free_plan_device(&p);  // re-uploaded by the next execute
+  return VFX_OK;
+}
+
+int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, const double* py, double* out,
+               void* stream) {
+  if (!plan || npts < 0 || (npts > 0 && (!V || !px || !py || !out)))
+    return fail(VFX_EINVAL, "vfx_interp: null argument or negative count");
+  try {
+    std::string err;
+    int rc = vfx::launch_interp(&plan->p, V, (long)npts, px, py, out, (hipStream_t)stream, err);
+    if (rc) return fail(rc, "vfx_interp: " + err);
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_interp: out of host memory");
+  }
+  return VFX_OK;
+}
+
+int vfx_mlp_param_count(void) { return vfx::mlp_param_count(); }
+
+int64_t vfx_mlp_grad_work(int64_t batch) { return batch > 0 ? (int64_t)vfx::mlp_grad_work((long)batch) : 0; }
+
+int vfx_mlp_forward(const float* theta, const float* x, int64_t batch, float* logits, void* stream) {
+  if (batch < 0 || (batch > 0 && (!theta || !x || !logits))) return fail(VFX_EINVAL, "vfx_mlp_forward: bad argument");
+  int rc = vfx::mlp_forward(theta, x, (long)batch, logits, (hipStream_t)stream);
+  return rc ? fail(rc, "vfx_mlp_forward: launch failed") : VFX_OK;
+}
+
+int vfx_mlp_grad(const float* theta, const float* x, const float* y, int64_t batch, float* grad, float* work,
+                 int64_t work_floats, void* stream) {
+  if (batch <= 0 || !theta || !x || !y || !grad || !work) return fail(VFX_EINVAL, "vfx_mlp_grad: bad argument");
+  if (work_floats < (int64_t)vfx::mlp_grad_work((long)batch)) return fail(VFX_EINVAL, "vfx_mlp_grad: work too small");
+  int rc = vfx::mlp_grad(theta, x, y, (long)batch, grad, work, (hipStream_t)stream);
+  return rc ? fail(rc, "vfx_mlp_grad: launch failed") : VFX_OK;
+}
+
+int vfx_mlp_adam(float* theta, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
+                 float eps, void* stream) {
+  if (!theta || !grad || !m || !v || step < 1) return fail(VFX_EINVAL, "vfx_mlp_adam: bad argument");
+  int rc = vfx::mlp_adam(theta, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream);
+  return rc ? fail(rc, "vfx_mlp_adam: launch failed") : VFX_OK;
+}
+
+int vfx_f32_to_f16(const float* a, uint16_t* h, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!a || !h))) return fail(VFX_EINVAL, "vfx_f32_to_f16: bad argument");
+  int rc = vfx::mlp_to_f16(a, h, (long)n, (hipStream_t)stream);
+  return rc ? fail(rc, "vfx_f32_to_f16: launch failed") : VFX_OK;
+}
+
+int vfx_mlp_infer_f16(const uint16_t* theta_h, const uint16_t* x_h, int64_t batch, float* logits, void* stream) {
+  if (batch < 0 || (batch > 0 && (!theta_h || !x_h || !logits)))
+    return fail(VFX_EINVAL, "vfx_mlp_infer_f16: bad argument");
+  int rc = vfx::mlp_infer_f16(theta_h, x_h, (long)batch, logits, (hipStream_t)stream);
+  return rc ? fail(rc, "vfx_mlp_infer_f16: launch failed") : VFX_OK;
+}
+
 int vfx_plan_set_timing(vfx_plan* plan, int enable) {
   if (!plan) return fail(VFX_EINVAL, "vfx_plan_set_timing: null argument");
   plan->p.timing = enable != 0;

@@ -765,6 +765,174 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
 }
 
 // -------------------------------------------------------------------------
+// Mixed-precision near field (K = 16).  Operands are split into three bf16
+// slices, x ~ x0 + x1 + x2 (about 24 significant bits); a product keeps the
+// six slice pairs down to order 2^-24, x0 y0 + x0 y1 + x1 y0 + x0 y2 +
+// x1 y1 + x2 y0, on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) with
+// FP32 accumulation, and results are written as FP64 (the far-field kernel
+// sums them with the FP64 terms in FP64).  MFMA operands are loaded straight
+// from memory: a lane's eight consecutive contraction values are 16
+// contiguous bytes (tables stored contraction-fastest).
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16]
+// (j = 0..7) and the outputs D[4(l/16)+r][l%16], r = 0..3 (checked on gfx950).
+typedef short vfx_s8 __attribute__((ext_vector_type(8)));
+typedef float vfx_f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// leaf data -> three bf16 slices, xs[s][leaf][node]
+__global__ void k_split3(long total, const double* __restrict__ x, uint16_t* __restrict__ xs) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
+    double r = x[i];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const uint16_t h = bf16_rne((float)r);
+      xs[(size_t)s * total + i] = h;
+      r -= (double)bf16_float(h);
+    }
+  }
+}
+
+__device__ __forceinline__ vfx_f4 mfma_bf16(vfx_s8 a, vfx_s8 b, vfx_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// acc += A B over the six slice pairs
+__device__ __forceinline__ vfx_f4 mfma_x3(const vfx_s8 a[3], const vfx_s8 b[3], vfx_f4 acc) {
+  acc = mfma_bf16(a[2], b[0], acc);
+  acc = mfma_bf16(a[1], b[1], acc);
+  acc = mfma_bf16(a[0], b[2], acc);
+  acc = mfma_bf16(a[1], b[0], acc);
+  acc = mfma_bf16(a[0], b[1], acc);
+  acc = mfma_bf16(a[0], b[0], acc);
+  return acc;
+}
+
+// acc[r] = X-rows (this lane's pair) times B rows 16r.. of wbase, r < MT1
+// (compile-time, so the MFMA sequence has no branches); acc[r >= MT1] = 0
+template <int MT1>
+__device__ __forceinline__ void mx_phase1(const uint16_t* __restrict__ xrow, long xs_slice,
+                                          const uint16_t* __restrict__ wbase, size_t wslice, vfx_f4 acc[4]) {
+  constexpr int n = 256;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = vfx_f4{0, 0, 0, 0};
+  for (int kb = 0; kb < n / 32; ++kb) {
+    vfx_s8 a[3], b[MT1][3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) a[s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice + 32 * kb);
+#pragma unroll
+    for (int r = 0; r < MT1; ++r)
+#pragma unroll
+      for (int s = 0; s < 3; ++s)
+        b[r][s] = *(const vfx_s8*)(wbase + (size_t)s * wslice + (size_t)(16 * r + li) * n + 32 * kb + 8 * lk);
+#pragma unroll
+    for (int r = 0; r < MT1; ++r) acc[r] = mfma_x3(a, b[r], acc[r]);
+  }
+}
+
+// One work item: a tile of <= 64 pairs of one configuration (wave w owns
+// pairs 16w..16w+15).  LR: Z = X W^T (R_c ranks), then Y = Z Q^T with Z
+// re-split into bf16 slices; dense (self operator): Y = X A^T for one block
+// of 64 target rows (four row blocks per tile).  Persistent, XCD-aware item
+// order as in k_gemm.
+template <bool LR>
+__global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int* __restrict__ t_cfg,
+                                                 const int* __restrict__ t_first, const int* __restrict__ t_count,
+                                                 const int* __restrict__ src, const int* __restrict__ lr_R,
+                                                 const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ Qb,
+                                                 const uint16_t* __restrict__ xs, long xs_slice,
+                                                 double* __restrict__ Y) {
+  constexpr int n = 256, LM = kNearLrMax, LDZ = LM + 4;
+  __shared__ float sZ[LR ? 64 * LDZ : 1];
+  const int nb = gridDim.x, bb = blockIdx.x;
+  const int x = bb & 7;
+  const int q = nitems >> 3, rr = nitems & 7;
+  const int xfirst = x * q + min(x, rr), xcount = q + (x < rr ? 1 : 0);
+  const int xwgs = (nb - x + 7) >> 3;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int j = bb >> 3; j < xcount; j += xwgs) {
+    const int item = xfirst + j;
+    const int tile = item / nrb, rb = item - tile * nrb;
+    const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
+    const int ent = 16 * w + li;  // this lane's A-operand pair
+    const int leaf = src[p0 + (ent < np ? ent : 0)];
+    const uint16_t* xrow = xs + (size_t)leaf * n + 8 * lk;
+    // phase 1: B operand rows (ranks, or target rows of the dense block)
+    const int MT1 = LR ? lr_R[c] / 16 : 4;
+    const size_t wslice = LR ? (size_t)LM * n : (size_t)n * n;
+    const uint16_t* wbase = LR ? Wb + (size_t)c * 3 * wslice : Wb + (size_t)64 * rb * n;
+    vfx_f4 acc[4];
+    switch (MT1) {
+      case 1: mx_phase1<1>(xrow, xs_slice, wbase, wslice, acc); break;
+      case 2: mx_phase1<2>(xrow, xs_slice, wbase, wslice, acc); break;
+      case 3: mx_phase1<3>(xrow, xs_slice, wbase, wslice, acc); break;
+      default: mx_phase1<4>(xrow, xs_slice, wbase, wslice, acc); break;
+    }
+    if (!LR) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int pe = 16 * w + 4 * lk + e;
+          if (pe < np) Y[(size_t)(p0 + pe) * n + 64 * rb + 16 * r + li] = (double)acc[r][e];
+        }
+      continue;
+    }
+    // Z (FP32) of this wave's pairs to LDS, ranks >= R zero
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sZ[(16 * w + 4 * lk + e) * LDZ + 16 * r + li] = r < MT1 ? acc[r][e] : 0.0f;
+    __syncthreads();
+    // phase 2: Y = Z Q^T over the ranks in blocks of 32
+    const uint16_t* qbase = Qb + (size_t)c * 3 * LM * n;
+    const int nkb = (16 * MT1 + 31) / 32;
+    vfx_f4 acc2[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc2[r] = vfx_f4{0, 0, 0, 0};
+    for (int kb = 0; kb < nkb; ++kb) {
+      vfx_s8 a[3];
+      {
+        const float* zr = sZ + (16 * w + li) * LDZ + 32 * kb + 8 * lk;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          float v = zr[t];
+#pragma unroll
+          for (int s = 0; s < 3; ++s) {
+            const uint16_t h = bf16_rne(v);
+            a[s][t] = (short)h;
+            v -= bf16_float(h);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        vfx_s8 b[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s)
+          b[s] = *(const vfx_s8*)(qbase + (size_t)s * LM * n + (size_t)(16 * r + li) * LM + 32 * kb + 8 * lk);
+        acc2[r] = mfma_x3(a, b, acc2[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pe = 16 * w + 4 * lk + e;
+        if (pe < np) Y[(size_t)(p0 + pe) * n + 16 * r + li] = (double)acc2[r][e];
+      }
+    __syncthreads();  // sZ is rewritten by the next item
+  }
+}
+
+// -------------------------------------------------------------------------
 // Upward pass without the level-by-level chain.  The multipole of a non-leaf
 // box B (level >= 2) about its own centre is the sum, over the leaves L below
 // it, of the leaf multipoles shifted to B.  The shifted coefficients b_l
@@ -1050,6 +1218,85 @@ __global__ void __launch_bounds__(256) k_far(int K, int Prt, double root_size, c
 }
 
 // -------------------------------------------------------------------------
+// Values of leaf-grid data at arbitrary points (e.g. boundary nodes): the leaf
+// holding a point is found by descending the tree from the root (children in
+// Morton order, a point on a box edge goes to the upper/right child); the value
+// is the tensor interpolant of the leaf's K x K first-kind Chebyshev samples,
+// evaluated by the barycentric formula with weights (-1)^a sin((2a+1)pi/2K).
+// Points outside the root box get NaN.  One thread per point.
+__global__ void k_interp(int K, double root_cx, double root_cy, double root_size, const int* __restrict__ box_child0,
+                         const int* __restrict__ box_leaf, const double* __restrict__ t,
+                         const double* __restrict__ V, long npts, const double* __restrict__ px,
+                         const double* __restrict__ py, double* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npts) return;
+  const double x = px[i], y = py[i];
+  double cx = root_cx, cy = root_cy, h = root_size;
+  if (!(fabs(x - cx) <= 0.5 * h && fabs(y - cy) <= 0.5 * h)) {
+    out[i] = __builtin_nan("");
+    return;
+  }
+  int b = 0;
+  while (box_leaf[b] < 0) {
+    const int dx = x >= cx, dy = y >= cy;
+    h *= 0.5;
+    cx += (dx ? 0.5 : -0.5) * h;
+    cy += (dy ? 0.5 : -0.5) * h;
+    b = box_child0[b] + dx + 2 * dy;
+  }
+  const int leaf = box_leaf[b];
+  const double xi = 2.0 * (x - cx) / h, eta = 2.0 * (y - cy) / h;
+  double lx[kMaxK], ly[kMaxK];
+  auto weights = [&](double s, double* l) {
+    int hit = -1;
+    double sum = 0.0;
+    for (int a = 0; a < K; ++a) {
+      const double d = s - t[a];
+      if (d == 0.0) hit = a;
+      const double wa = ((a & 1) ? -1.0 : 1.0) * sin((2 * a + 1) * M_PI / (2 * K));
+      l[a] = wa / (d == 0.0 ? 1.0 : d);
+      sum += l[a];
+    }
+    if (hit >= 0) {
+      for (int a = 0; a < K; ++a) l[a] = (a == hit) ? 1.0 : 0.0;
+    } else {
+      const double inv = 1.0 / sum;
+      for (int a = 0; a < K; ++a) l[a] *= inv;
+    }
+  };
+  weights(xi, lx);
+  weights(eta, ly);
+  const double* v = V + (size_t)leaf * K * K;
+  double acc = 0.0;
+  for (int a = 0; a < K; ++a) {
+    double g = 0.0;
+    for (int c = 0; c < K; ++c) g += ly[c] * v[a * K + c];
+    acc += lx[a] * g;
+  }
+  out[i] = acc;
+}
+
+int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
+                  hipStream_t s, std::string& err) {
+  Context* c = p->ctx;
+  const Tables& T = c->T;
+  if (!c->D.ready) {
+    int rc = upload_tables(c, err);
+    if (rc) return rc;
+  }
+  if (!p->D.ready) {
+    int rc = upload_plan(p, err);
+    if (rc) return rc;
+  }
+  if (npts <= 0) return VFX_OK;
+  const long blocks = (npts + 255) / 256;
+  hipLaunchKernelGGL(k_interp, dim3((unsigned)blocks), dim3(256), 0, s, T.K, T.root_cx, T.root_cy, T.root_size,
+                     p->D.box_child0, p->D.box_leaf, c->D.t, V, npts, px, py, out);
+  VFX_HIP(hipGetLastError());
+  return VFX_OK;
+}
+
+// -------------------------------------------------------------------------
 template <typename T>
 static int upload(T** dst, const T* src, size_t count, std::string& err) {
   *dst = nullptr;
@@ -1084,6 +1331,9 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.lr_R, T.lr_R);
   UP(D.lr_W, T.lr_W);
   UP(D.lr_Q, T.lr_Q);
+  UP(D.lr_Wb, T.lr_Wb);
+  UP(D.lr_Qb, T.lr_Qb);
+  UP(D.self_Ab, T.self_Ab);
   UP(D.p2l_gemm, T.p2l_gemm);
   UP(D.p2m_gemm, T.p2m_gemm);
   UP(D.pas_m2l, T.pas_m2l);
@@ -1129,7 +1379,7 @@ void free_tables_device(Context* c) {
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
-                  D.lr_R,     D.lr_W,     D.lr_Q};
+                  D.lr_R,     D.lr_W,     D.lr_Q,     D.lr_Wb,    D.lr_Qb,    D.self_Ab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   D = DeviceTables();
@@ -1182,6 +1432,13 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.nl_cfg, H.nl_cfg);
   UP(D.nl_first, H.nl_first);
   UP(D.nl_count, H.nl_count);
+  UP(D.mt_cfg, H.mt_cfg);
+  UP(D.mt_first, H.mt_first);
+  UP(D.mt_count, H.mt_count);
+  UP(D.ml_cfg, H.ml_cfg);
+  UP(D.ml_first, H.ml_first);
+  UP(D.ml_count, H.ml_count);
+  if (H.precision == 1) VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 3 * (size_t)H.L * T.n));
   UP(D.p4_src, H.p4_src);
   UP(D.l4_slot, H.l4_slot);
   UP(D.t4_cfg, H.t4_cfg);
@@ -1213,6 +1470,7 @@ int upload_plan(Plan* p, std::string& err) {
 
 void free_plan_device(Plan* p) {
   DevicePlan& D = p->D;
+  if (D.ready) (void)hipDeviceSynchronize();  // no execute of this plan in flight
   void* ptrs[] = {D.box_level, D.box_child0, D.box_leaf, D.box_parent, D.box_cx,   D.box_cy,   D.leaf_box,
                   D.kind,      D.l1_ptr,     D.l1_src,   D.l1_cfg,     D.l2_ptr,   D.l2_src,   D.l2_off,
                   D.l3_ptr,    D.l3_src,     D.l4_ptr,   D.l4_src,     D.l4_cfg,   D.np_src,   D.l1_slot,
@@ -1222,7 +1480,8 @@ void free_plan_device(Plan* p) {
                   D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp,  D.up_box,   D.up_ptr,   D.up_src,
                   D.up_pos,    D.up_split,   D.up_grp,   D.up_part,  D.anc_ptr,  D.anc,
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
-                  D.anc_leaf,  D.dn_grp,     D.locf};
+                  D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg,
+                  D.ml_first,  D.ml_count,   D.xs};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -1358,6 +1617,25 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   MARK(6, p->side);
   near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
             kNearWgs);
+  if (H.precision == 1) {
+    // pairs in mixed precision: bf16 slices of the leaf data, then the
+    // low-rank and the dense (self) kernels
+    const long total = (long)L * n;
+    hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192)), dim3(256), 0, p->side, total,
+                       fe, D.xs);
+    if (!H.ml_cfg.empty()) {
+      const int items = (int)H.ml_cfg.size();
+      hipLaunchKernelGGL(k_near_mx<true>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, 1,
+                         D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs, total,
+                         D.near_y);
+    }
+    if (!H.mt_cfg.empty()) {
+      const int items = 4 * (int)H.mt_cfg.size();
+      hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, 4,
+                         D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
+                         D.near_y);
+    }
+  }
   VFX_HIP(hipGetLastError());
   MARK(7, p->side);
   VFX_HIP(hipEventRecord(p->join_ev, p->side));

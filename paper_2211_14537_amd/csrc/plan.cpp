@@ -50,6 +50,67 @@ inline bool touch(int la, int ax, int ay, int lb, int bx, int by) {
 
 }  // namespace
 
+// List-1 pairs grouped for the near-field kernels: configuration-major, and
+// inside a configuration by precision class (mode 1: sources at level >=
+// min_level are applied in mixed precision), then by target.  Tiles of <= 64
+// pairs go to the low-rank or the dense kernel of their class.  l1_slot maps
+// every per-target list-1 entry to its pair.
+int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std::string& err) {
+  const int L = H.L;
+  const int N1 = H.l1_ptr[L];
+  const bool k16 = T.n == 256 && !T.lr_R.empty();
+  if (mode == 1 && !k16) {
+    err = "mixed precision is available for K = 16 only";
+    return VFX_EINVAL;
+  }
+  auto mixed = [&](int src_leaf) {
+    return mode == 1 && H.box_level[H.leaf_box[src_leaf]] >= min_level;
+  };
+  // counting sort on (configuration, class)
+  std::vector<int> cnt(2 * kNearConfigs + 1, 0);
+  for (int e = 0; e < N1; ++e) cnt[2 * H.l1_cfg[e] + (mixed(H.l1_src[e]) ? 1 : 0) + 1]++;
+  for (int g = 0; g < 2 * kNearConfigs; ++g) cnt[g + 1] += cnt[g];
+  H.np_src.assign(N1, 0);
+  H.np_tgt.assign(N1, 0);
+  H.l1_slot.assign(N1, 0);
+  std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+  for (int leaf = 0; leaf < L; ++leaf)  // targets ascending inside each group
+    for (int e = H.l1_ptr[leaf]; e < H.l1_ptr[leaf + 1]; ++e) {
+      const int s = pos[2 * H.l1_cfg[e] + (mixed(H.l1_src[e]) ? 1 : 0)]++;
+      H.np_src[s] = H.l1_src[e];
+      H.np_tgt[s] = leaf;
+      H.l1_slot[e] = s;
+    }
+  for (auto* v : {&H.nt_cfg, &H.nt_first, &H.nt_count, &H.nl_cfg, &H.nl_first, &H.nl_count, &H.mt_cfg,
+                  &H.mt_first, &H.mt_count, &H.ml_cfg, &H.ml_first, &H.ml_count})
+    v->clear();
+  constexpr int kTile = 64;
+  for (int c = 0; c < kNearConfigs; ++c) {
+    const bool lr = k16 && T.lr_R[c] > 0;
+    for (int cls = 0; cls < 2; ++cls) {
+      const int g = 2 * c + cls;
+      std::vector<int>*cf, *fi, *co;
+      if (cls == 0) {
+        cf = lr ? &H.nl_cfg : &H.nt_cfg;
+        fi = lr ? &H.nl_first : &H.nt_first;
+        co = lr ? &H.nl_count : &H.nt_count;
+      } else {
+        cf = lr ? &H.ml_cfg : &H.mt_cfg;
+        fi = lr ? &H.ml_first : &H.mt_first;
+        co = lr ? &H.ml_count : &H.mt_count;
+      }
+      for (int f = cnt[g]; f < cnt[g + 1]; f += kTile) {
+        cf->push_back(c);
+        fi->push_back(f);
+        co->push_back(std::min(kTile, cnt[g + 1] - f));
+      }
+    }
+  }
+  H.precision = mode;
+  H.mixed_min_level = min_level;
+  return VFX_OK;
+}
+
 int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err) {
   auto t0 = std::chrono::steady_clock::now();
   const int L = tree->n_leaves;
@@ -243,38 +304,8 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
   H.l1_srcbox.resize(H.l1_src.size());
   for (size_t e = 0; e < H.l1_src.size(); ++e) H.l1_srcbox[e] = H.leaf_box[H.l1_src[e]];
   {
-    const int N1 = H.l1_ptr[L];
-    std::vector<int> cnt(kNearConfigs + 1, 0);
-    for (int e = 0; e < N1; ++e) cnt[H.l1_cfg[e] + 1]++;
-    for (int c = 0; c < kNearConfigs; ++c) cnt[c + 1] += cnt[c];
-    H.np_src.assign(N1, 0);
-    H.np_tgt.assign(N1, 0);
-    H.l1_slot.assign(N1, 0);
-    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (int leaf = 0; leaf < L; ++leaf)  // targets ascending inside each configuration
-      for (int e = H.l1_ptr[leaf]; e < H.l1_ptr[leaf + 1]; ++e) {
-        const int s = pos[H.l1_cfg[e]]++;
-        H.np_src[s] = H.l1_src[e];
-        H.np_tgt[s] = leaf;
-        H.l1_slot[e] = s;
-      }
-    // tiles of <= 64 pairs; configurations with a low-rank form (K = 16)
-    // go to the low-rank kernel, the others to the dense table GEMM
-    constexpr int kTile = 64;
-    for (int c = 0; c < kNearConfigs; ++c) {
-      const bool lr = T.n == 256 && !T.lr_R.empty() && T.lr_R[c] > 0;
-      for (int f = cnt[c]; f < cnt[c + 1]; f += kTile) {
-        if (lr) {
-          H.nl_cfg.push_back(c);
-          H.nl_first.push_back(f);
-          H.nl_count.push_back(std::min(kTile, cnt[c + 1] - f));
-          continue;
-        }
-        H.nt_cfg.push_back(c);
-        H.nt_first.push_back(f);
-        H.nt_count.push_back(std::min(kTile, cnt[c + 1] - f));
-      }
-    }
+    int rc = build_near_tiles(T, H, 0, 0, err);
+    if (rc) return rc;
   }
   // ---- lists 2 and 4 (per box, level >= 2) ------------------------------
   H.l2_ptr.assign(B + 1, 0);

@@ -382,6 +382,29 @@ static void build_near(Tables& T) {
   }
 }
 
+// bf16 with round-to-nearest-even of a float (finite inputs)
+static uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static double bf16_value(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+// x ~ s0 + s1 + s2 (each bf16; the residual after three slices is about
+// 2^-24 |x|)
+static void bf16_split3(double x, uint16_t s[3]) {
+  double r = x;
+  for (int k = 0; k < 3; ++k) {
+    s[k] = bf16_rne((float)r);
+    r -= bf16_value(s[k]);
+  }
+}
+
 // Truncated rank-revealing factorisation of the n x n near-field operator
 // A (A[i][j] = near[c][j][i]): Householder QR with column pivoting, stopped
 // when the largest remaining column norm falls below tol times the first
@@ -479,6 +502,30 @@ static void build_near_lowrank(Tables& T) {
         T.lr_Q[((size_t)c * kNearLrMax + a) * n + j] = Q[(size_t)j * r + a];
       }
   }
+  // bf16 slices for the mixed-precision kernels (K = 16)
+  if (n != 256) return;
+  const size_t SW = (size_t)kNearLrMax * n;  // one slice of one configuration
+  T.lr_Wb.assign((size_t)kNearConfigs * 3 * SW, 0);
+  T.lr_Qb.assign((size_t)kNearConfigs * 3 * SW, 0);
+  T.self_Ab.assign((size_t)3 * n * n, 0);
+  for (int c = 0; c < kNearConfigs; ++c)
+    for (int a = 0; a < kNearLrMax; ++a)
+      for (int j = 0; j < n; ++j) {
+        uint16_t w3[3], q3[3];
+        bf16_split3(T.lr_W[((size_t)c * n + j) * kNearLrMax + a], w3);
+        bf16_split3(T.lr_Q[((size_t)c * kNearLrMax + a) * n + j], q3);
+        for (int s = 0; s < 3; ++s) {
+          T.lr_Wb[((size_t)c * 3 + s) * SW + (size_t)a * n + j] = w3[s];
+          T.lr_Qb[((size_t)c * 3 + s) * SW + (size_t)j * kNearLrMax + a] = q3[s];
+        }
+      }
+  const int cs = kNearSelf;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      uint16_t a3[3];
+      bf16_split3(T.near[((size_t)cs * n + j) * n + i], a3);
+      for (int s = 0; s < 3; ++s) T.self_Ab[((size_t)s * n + i) * n + j] = a3[s];
+    }
 }
 
 // Chebyshev moments of a smooth kernel over a square by tensor Gauss-Legendre

@@ -19,6 +19,7 @@ namespace vfx {
 //           values in {-3,-1,1,3} with max(|ox|,|oy|) = 3
 //   21..32  one level finer, centre offset in units h/4, same value set
 constexpr int kNearConfigs = 33;
+constexpr int kNearSelf = 4;  // the self interaction (colleague offset 0, 0)
 // Near-field operators are applied in low-rank form Q W when the truncated
 // pivoted QR at this relative tolerance has rank <= kNearLrMax and saves at
 // least 40% of the dense work.
@@ -51,6 +52,11 @@ struct Tables {
   std::vector<int> lr_R, lr_rank;      // 33: padded rank (0 = dense), rank
   std::vector<double> lr_W;            // 33 x n x kNearLrMax, [c][j][a]
   std::vector<double> lr_Q;            // 33 x kNearLrMax x n, [c][a][i]
+  // bf16 slices (x ~ s0 + s1 + s2) of the K = 16 near-field operators as
+  // MFMA B operands, contraction index fastest:
+  //   lr_Wb [c][s][a][j] = W[a][j],  lr_Qb [c][s][i][a] = Q[i][a],
+  //   self_Ab [s][i][j] = self table, row i (target node), column j
+  std::vector<uint16_t> lr_Wb, lr_Qb, self_Ab;
   std::vector<double> p2m;             // (p+1) x n complex, [k][j] (re,im)
   std::vector<double> l2p;             // n x (p+1) complex, [i][l]
   std::vector<double> m2m;             // 4 x (p+1) x (p+1) complex, [q][k][l]
@@ -97,6 +103,7 @@ struct DeviceTables {
   double *near = nullptr, *near_s2 = nullptr;
   int* lr_R = nullptr;
   double *lr_W = nullptr, *lr_Q = nullptr;
+  uint16_t *lr_Wb = nullptr, *lr_Qb = nullptr, *self_Ab = nullptr;
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
@@ -140,6 +147,9 @@ struct HostPlan {
   std::vector<int> np_src, np_tgt, l1_slot;
   std::vector<int> nt_cfg, nt_first, nt_count;  // dense GEMM tiles of <= 64 pairs
   std::vector<int> nl_cfg, nl_first, nl_count;  // low-rank tiles of <= 64 pairs
+  // the same for the pairs applied in mixed precision (bf16 slices)
+  std::vector<int> mt_cfg, mt_first, mt_count, ml_cfg, ml_first, ml_count;
+  int precision = 0, mixed_min_level = 0;
   // list-4 entries regrouped by P2L slot, the same way
   std::vector<int> p4_src, l4_slot, t4_cfg, t4_first, t4_count;
   // P2M over all leaves as one GEMM configuration
@@ -172,6 +182,9 @@ struct DevicePlan {
   int *l4_ptr = nullptr, *l4_src = nullptr, *l4_cfg = nullptr;
   int *np_src = nullptr, *l1_slot = nullptr, *nt_cfg = nullptr, *nt_first = nullptr, *nt_count = nullptr;
   int *nl_cfg = nullptr, *nl_first = nullptr, *nl_count = nullptr;
+  int *mt_cfg = nullptr, *mt_first = nullptr, *mt_count = nullptr, *ml_cfg = nullptr, *ml_first = nullptr,
+      *ml_count = nullptr;
+  uint16_t* xs = nullptr;  // bf16 slices of the leaf data, 3 x L x n
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
@@ -201,6 +214,7 @@ struct Plan {
 
 // plan.cpp
 int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err);
+int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std::string& err);
 
 // kernels.hip
 int upload_tables(Context* c, std::string& err);
@@ -209,5 +223,17 @@ void free_plan_device(Plan* p);
 void free_tables_device(Context* c);
 int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V,
                    hipStream_t s, std::string& err);
+int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
+                  hipStream_t s, std::string& err);
+
+// mlp.hip (refinement classifier)
+int mlp_param_count();
+int mlp_forward(const float* th, const float* X, long B, float* logits, hipStream_t s);
+long mlp_grad_work(long B);
+int mlp_grad(const float* th, const float* X, const float* y, long B, float* grad, float* work, hipStream_t s);
+int mlp_adam(float* th, const float* grad, float* m, float* v, int step, float lr, float b1, float b2, float eps,
+             hipStream_t s);
+int mlp_to_f16(const float* a, uint16_t* h, long n, hipStream_t s);
+int mlp_infer_f16(const uint16_t* th, const uint16_t* X, long B, float* logits, hipStream_t s);
 
 }  // namespace vfx

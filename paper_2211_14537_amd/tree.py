@@ -196,6 +196,7 @@ def build_tree(cfg, stencil_points=None, max_rounds=50):
         leaves = {(d, x, y) for x in range(1 << d) for y in range(1 << d)}
     else:
         tol, maxd, mincut = spec["tol"], spec["max_depth"], spec.get("min_cut_level", 0)
+        minlev = spec.get("min_level", 0)
         fs = B.fscale()
         leaves = set()
         front = [(0, 0, 0)]
@@ -209,6 +210,8 @@ def build_tree(cfg, stencil_points=None, max_rounds=50):
                     if tl > tol * fs:
                         split = True
                     if kd == CUT and k[0] < mincut:
+                        split = True
+                    if k[0] < minlev:
                         split = True
                 if split:
                     nxt.extend(_children(k))

@@ -52,7 +52,10 @@ _lib = None
 
 EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points", "vfx_leaf_nodes",
             "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
-            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_last_error",
+            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp",
+            "vfx_mlp_param_count", "vfx_mlp_forward", "vfx_mlp_grad", "vfx_mlp_adam", "vfx_f32_to_f16",
+            "vfx_mlp_infer_f16",
+            "vfx_last_error",
             "vfx_debug_table", "vfx_plan_lists", "vfx_plan_boxes")
 
 
@@ -81,6 +84,16 @@ def lib():
         L.vfx_plan_ext_owner.argtypes = [vp, i32p]
         L.vfx_execute.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vfx_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.vfx_plan_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.vfx_interp.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.vfx_mlp_param_count.argtypes = []
+        L.vfx_mlp_grad_work.argtypes = [ctypes.c_int64]
+        L.vfx_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+        L.vfx_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, ctypes.c_int64, vp]
+        L.vfx_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, vp]
+        L.vfx_f32_to_f16.argtypes = [vp, vp, ctypes.c_int64, vp]
+        L.vfx_mlp_infer_f16.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
         L.vfx_plan_timings.argtypes = [vp, dp, ctypes.c_int]
         L.vfx_last_error.restype = ctypes.c_char_p
         L.vfx_debug_table.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int64]
@@ -89,6 +102,7 @@ def lib():
         for name in EXPORTED:
             if name != "vfx_last_error":
                 getattr(L, name).restype = ctypes.c_int
+        L.vfx_mlp_grad_work.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -212,6 +226,26 @@ class Plan:
         _check(lib().vfx_execute(self._h, f_leaf.data_ptr(), fc, fe_out.data_ptr(), V_out.data_ptr(),
                                  ctypes.c_void_p(stream.cuda_stream)))
 
+    def interp(self, V, px, py, out, stream=None):
+        """Interpolate leaf-grid data V (n_leaves x K^2) to the points
+        (px, py) into out (all float64 CUDA tensors)."""
+        import torch
+        n = self.ctx.K * self.ctx.K
+        if not (V.is_cuda and V.dtype == torch.float64 and V.is_contiguous() and tuple(V.shape) == (self.n_leaves, n)):
+            raise ValueError(f"V: expected contiguous float64 CUDA tensor of shape {(self.n_leaves, n)}")
+        m = px.numel()
+        for name, t in (("px", px), ("py", py), ("out", out)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == m):
+                raise ValueError(f"{name}: expected contiguous float64 CUDA tensor with {m} entries")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().vfx_interp(self._h, V.data_ptr(), m, px.data_ptr(), py.data_ptr(), out.data_ptr(),
+                                ctypes.c_void_p(st.cuda_stream)))
+
+    def set_precision(self, mode, min_level=0):
+        """Near-field precision: 0 = FP64, 1 = bf16 slices with FP32
+        accumulation for sources at level >= min_level (K = 16)."""
+        _check(lib().vfx_plan_set_precision(self._h, int(mode), int(min_level)))
+
     def set_timing(self, on=True):
         _check(lib().vfx_plan_set_timing(self._h, 1 if on else 0))
 
@@ -236,3 +270,62 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---- refinement classifier (device tensors; argument marshalling only) ----
+
+def _dev_f32(t, n=None, name="tensor"):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and (n is None or t.numel() == n)):
+        raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor" + (f" with {n} entries" if n else ""))
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def mlp_param_count():
+    return int(lib().vfx_mlp_param_count())
+
+
+def mlp_forward(theta, x, logits, stream=None):
+    B = x.shape[0]
+    _check(lib().vfx_mlp_forward(_dev_f32(theta, mlp_param_count(), "theta"), _dev_f32(x, B * 64, "x"), B,
+                                 _dev_f32(logits, B, "logits"), _stream(stream)))
+
+
+def mlp_grad_work(batch):
+    return int(lib().vfx_mlp_grad_work(batch))
+
+
+def mlp_grad(theta, x, y, grad, work, stream=None):
+    B = x.shape[0]
+    _check(lib().vfx_mlp_grad(_dev_f32(theta, mlp_param_count(), "theta"), _dev_f32(x, B * 64, "x"),
+                              _dev_f32(y, B, "y"), B, _dev_f32(grad, mlp_param_count(), "grad"),
+                              _dev_f32(work, None, "work"), work.numel(), _stream(stream)))
+
+
+def mlp_adam(theta, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    n = mlp_param_count()
+    _check(lib().vfx_mlp_adam(_dev_f32(theta, n, "theta"), _dev_f32(grad, n, "grad"), _dev_f32(m, n, "m"),
+                              _dev_f32(v, n, "v"), int(step), lr, beta1, beta2, eps, _stream(stream)))
+
+
+def f32_to_f16(a, h, stream=None):
+    import torch
+    if not (h.is_cuda and h.dtype == torch.float16 and h.is_contiguous() and h.numel() == a.numel()):
+        raise ValueError("h: expected a contiguous float16 CUDA tensor of the same size")
+    _check(lib().vfx_f32_to_f16(_dev_f32(a, None, "a"), h.data_ptr(), a.numel(), _stream(stream)))
+
+
+def mlp_infer_f16(theta_h, x_h, logits, stream=None):
+    import torch
+    B = x_h.shape[0]
+    for name, t, n in (("theta_h", theta_h, mlp_param_count()), ("x_h", x_h, B * 64)):
+        if not (t.is_cuda and t.dtype == torch.float16 and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name}: expected a contiguous float16 CUDA tensor with {n} entries")
+    _check(lib().vfx_mlp_infer_f16(theta_h.data_ptr(), x_h.data_ptr(), B, _dev_f32(logits, B, "logits"),
+                                   _stream(stream)))
