@@ -200,6 +200,121 @@ def accuracy_check(case, plan, fe_gpu, sel, v_o, fe_o, info, dev, args):
                     "within 16 u cond(A_I) max|f|"}
 
 
+def bench_batch(args, dev):
+    """Many right-hand sides on one tree, one vfx_execute_batch per step."""
+    import numpy as np
+    import torch
+    from paper_2211_14537_amd import tree as T
+    from paper_2211_14537_amd import vfx
+    from workloads import get_config
+    cfg = get_config("starfish_batch")
+    nrhs = min(args.batch, len(cfg["rhs"]))
+    ctx = vfx.Context(cfg["K"], cfg["p"], root=cfg["root"])
+    P = ctx.stencil_points()
+    tr = T.build_tree(cfg, P)
+    plan = vfx.Plan(ctx, tr["level"], tr["ix"], tr["iy"], tr["kind"], tr["mask"])
+    L, n = len(tr["level"]), cfg["K"] ** 2
+    FL = torch.empty((nrhs, L, n), dtype=torch.float64, device=dev)
+    FC = torch.empty((nrhs, len(tr["cut_ids"]), ctx.n_stencil), dtype=torch.float64, device=dev)
+    for r in range(nrhs):
+        c = dict(cfg)
+        c["fun"] = cfg["rhs"][r]
+        fl, fc = T.sample_inputs(c, tr, P)
+        FL[r].copy_(torch.from_numpy(fl))
+        FC[r].copy_(torch.from_numpy(fc))
+    FE, V = torch.empty_like(FL), torch.empty_like(FL)
+    choice = plan.autotune(nrhs, FL, FC, FE, V, reps=1) if args.autotune else None
+    for _ in range(max(args.warmup, 1)):
+        plan.execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    # the same work one right-hand side at a time (first 8), for reference
+    t0 = time.perf_counter()
+    k1 = min(8, nrhs)
+    for r in range(k1):
+        plan.execute(FL[r], FC[r], FE[r], V[r])
+    torch.cuda.synchronize()
+    el1 = (time.perf_counter() - t0) / k1
+    out = {"metric": "leaf points/s over a batch of right-hand sides (ext + volume FMM), FP64", "unit": "leaf points/s",
+           "value": nrhs * L * n / el, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "starfish_batch", "rhs": nrhs, "leaves": L, "nodes_per_rhs": L * n,
+                      "K": cfg["K"], "p": cfg["p"], "cut_leaves": len(tr["cut_ids"])},
+           "single_rhs_ms": 1e3 * el1, "batch_speedup_per_rhs": el1 * nrhs / el, "autotune": choice}
+    print(json.dumps(out), flush=True)
+
+
+def bench_trees(args, dev):
+    """Many uneven trees (random Gaussian sums on the starfish, depth 3-7,
+    1e3-1e5 nodes), every execute captured in one HIP graph: one launch."""
+    import numpy as np
+    import torch
+    from paper_2211_14537_amd import tree as T
+    from paper_2211_14537_amd import vfx
+    from workloads import get_config
+    from workloads.configs import batch_functions
+    base = get_config("starfish_small")
+    ctx = vfx.Context(16, 24, root=base["root"])
+    P = ctx.stencil_points()
+    rng = np.random.default_rng(21)
+    funs = batch_functions(base["domain"], args.trees, seed=22)
+    plans, bufs, nodes = [], [], 0
+    for i in range(args.trees):
+        c = dict(base)
+        c["fun"] = funs[i]
+        d = int(rng.integers(3, 8))
+        c["tree"] = dict(kind="adaptive", tol=float(10 ** rng.uniform(-10, -6)), max_depth=d,
+                         min_cut_level=int(rng.integers(min(3, d), d + 1)))
+        tr = T.build_tree(c, P)
+        L = len(tr["level"])
+        if L * 256 > 1e5:
+            continue
+        fl, fc = T.sample_inputs(c, tr, P)
+        plan = vfx.Plan(ctx, tr["level"], tr["ix"], tr["iy"], tr["kind"], tr["mask"])
+        FL = torch.tensor(fl, device=dev)
+        FC = torch.tensor(fc if fc.size else np.zeros((0, ctx.n_stencil)), device=dev)
+        FE, V = torch.empty_like(FL), torch.empty_like(FL)
+        plan.execute(FL, FC, FE, V)
+        plans.append(plan)
+        bufs.append((FL, FC, FE, V))
+        nodes += L * 256
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for plan, (FL, FC, FE, V) in zip(plans, bufs):
+                plan.execute(FL, FC, FE, V, stream=s)
+        s.synchronize()
+        el_eager = (time.perf_counter() - t0) / args.steps
+        g = vfx.Graph()
+        g.begin(s)
+        for plan, (FL, FC, FE, V) in zip(plans, bufs):
+            plan.execute(FL, FC, FE, V, stream=s)
+        g.end(s)
+        g.launch(s)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.launch(s)
+        s.synchronize()
+        el_graph = (time.perf_counter() - t0) / args.steps
+        g.close()
+    out = {"metric": "leaf points/s over many trees in one HIP graph launch (ext + volume FMM), FP64",
+           "unit": "leaf points/s", "value": nodes / el_graph, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * el_graph, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "uneven_trees", "trees": len(plans), "nodes": nodes,
+                      "nodes_min": int(min(b[0].numel() for b in bufs)), "nodes_max": int(max(b[0].numel() for b in bufs))},
+           "eager_ms": 1e3 * el_eager, "graph_speedup": el_eager / el_graph}
+    print(json.dumps(out), flush=True)
+
+
 def build_case(name, p):
     import numpy as np
     from paper_2211_14537_amd import tree as T
@@ -237,6 +352,11 @@ def main():
                     help="with --precision mixed: sources at this level or finer run mixed")
     ap.add_argument("--check-nodes", type=int, default=0,
                     help="without the CPU baseline: oracle accuracy check at this many seeded nodes")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="many right-hand sides on one tree (workload starfish_batch): vfx_execute_batch")
+    ap.add_argument("--trees", type=int, default=0,
+                    help="many uneven trees (1e3-1e5 nodes) captured in one HIP graph, against eager launches")
+    ap.add_argument("--autotune", action="store_true", help="autotune the near-field launch parameters first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -248,6 +368,10 @@ def main():
     import torch
 
     dev = torch.device("cuda:0")
+    if args.batch > 0:
+        return bench_batch(args, dev)
+    if args.trees > 0:
+        return bench_trees(args, dev)
     case = build_case(args.config, args.p)
     plan = case["plan"]
     if args.precision == "mixed":

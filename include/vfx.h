@@ -61,6 +61,7 @@ extern "C" {
 
 typedef struct vfx_ctx vfx_ctx;
 typedef struct vfx_plan vfx_plan;
+typedef struct vfx_graph vfx_graph;
 
 typedef struct {
   int32_t K;         /* leaf grid size: 4, 8, 12 or 16 (the paper fixes 8)   */
@@ -184,6 +185,43 @@ int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, 
  * device data are rebuilt on the next vfx_execute; the call synchronises the
  * device and must not overlap an execute of the same plan. */
 int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level);
+
+/* Many right-hand sides on one tree (NEXT: batched execution).  Inputs and
+ * outputs are stacked: f_leaf, fe_out, V_out are nrhs x n_leaves x K^2 and
+ * f_cut is nrhs x n_cut x |X| (device, row-major).  Every kernel of the
+ * path runs once for the whole batch with the right-hand side as a grid
+ * dimension: each cut leaf's operator P_i is read once and applied to all
+ * right-hand sides (the work-groups of one cut leaf are consecutive, so the
+ * reuse happens in L2), the near-field and expansion GEMMs see nrhs times
+ * as many pairs, and the latency-bound tree kernels fill the GPU.  Results
+ * are bitwise those of nrhs separate vfx_execute calls.  The plan grows its
+ * per-right-hand-side buffers on first use (it synchronises the device
+ * then).  Errors as vfx_execute, and VFX_EINVAL for nrhs < 1. */
+int vfx_execute_batch(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
+                      double* V_out, void* stream);
+
+/* Launch-parameter autotuner (NEXT): times `reps` executes of the given batch
+ * for each candidate (work-group cap of the persistent near-field kernels
+ * 256/512/768/1024; row tiles per block of the dense near-field GEMM 4/8 at
+ * K = 16) with HIP events on `stream` and keeps the fastest for later
+ * executes of the plan; choice[0..1] (optional) receive it.  The choices
+ * change only how work is distributed, not the arithmetic: results are
+ * bitwise independent of them.  The buffers are overwritten. */
+int vfx_plan_autotune(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
+                      double* V_out, void* stream, int reps, int32_t* choice);
+
+/* HIP graph capture of a sequence of executes, possibly of many plans
+ * (NEXT: many uneven trees in one launch): vfx_graph_begin starts a capture
+ * on `stream`; vfx_execute / vfx_execute_batch calls on that stream are
+ * recorded (each plan must have executed once before, with at least as many
+ * right-hand sides, and have timing off); vfx_graph_end ends the capture and
+ * instantiates the graph; vfx_graph_launch replays all of it with one launch
+ * on a stream; vfx_graph_destroy frees it.  The graph holds no memset
+ * nodes.  VFX_EHIP if the runtime refuses a step. */
+int vfx_graph_begin(void* stream);
+int vfx_graph_end(void* stream, vfx_graph** out);
+int vfx_graph_launch(vfx_graph* graph, void* stream);
+int vfx_graph_destroy(vfx_graph* graph);
 
 /* Per-phase timing with HIP events.  The near-field kernels run on a side
  * stream of the plan (default priority), forked from `stream` after the

@@ -150,18 +150,122 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner) {
   return VFX_OK;
 }
 
-int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out, double* V_out,
-                void* stream) {
-  if (!plan || !f_leaf || !fe_out || !V_out) return fail(VFX_EINVAL, "vfx_execute: null argument");
-  if (plan->p.H.ncut > 0 && !f_cut) return fail(VFX_EINVAL, "vfx_execute: f_cut is null but the tree has cut leaves");
+static int execute_checked(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
+                           double* V_out, void* stream, const char* who) {
+  if (!plan || !f_leaf || !fe_out || !V_out || nrhs < 1)
+    return fail(VFX_EINVAL, std::string(who) + ": null argument or nrhs < 1");
+  if (plan->p.H.ncut > 0 && !f_cut)
+    return fail(VFX_EINVAL, std::string(who) + ": f_cut is null but the tree has cut leaves");
+  vfx::Plan& p = plan->p;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive) {
+    // no allocation or upload may be captured, and timing events neither
+    if (!p.ctx->D.ready || !p.D.ready || nrhs > p.D.cap)
+      return fail(VFX_EINVAL, std::string(who) + ": under stream capture the plan must already hold device data "
+                                                 "for this many right-hand sides (execute it once before capturing)");
+    if (p.timing) return fail(VFX_EINVAL, std::string(who) + ": timing must be off under stream capture");
+  }
   try {
     std::string err;
-    int rc = vfx::launch_execute(&plan->p, f_leaf, f_cut, fe_out, V_out, (hipStream_t)stream, err);
-    if (rc) return fail(rc, "vfx_execute: " + err);
+    int rc = vfx::launch_execute(&p, nrhs, f_leaf, f_cut, fe_out, V_out, (hipStream_t)stream, err);
+    if (rc) return fail(rc, std::string(who) + ": " + err);
     return VFX_OK;
   } catch (const std::bad_alloc&) {
-    return fail(VFX_ENOMEM, "vfx_execute: out of host memory");
+    return fail(VFX_ENOMEM, std::string(who) + ": out of host memory");
   }
+}
+
+int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out, double* V_out,
+                void* stream) {
+  return execute_checked(plan, 1, f_leaf, f_cut, fe_out, V_out, stream, "vfx_execute");
+}
+
+int vfx_execute_batch(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
+                      double* V_out, void* stream) {
+  return execute_checked(plan, nrhs, f_leaf, f_cut, fe_out, V_out, stream, "vfx_execute_batch");
+}
+
+int vfx_plan_autotune(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
+                      double* V_out, void* stream, int reps, int32_t* choice) {
+  if (!plan || reps < 1) return fail(VFX_EINVAL, "vfx_plan_autotune: bad argument");
+  vfx::Plan& p = plan->p;
+  const bool was_timing = p.timing;
+  p.timing = false;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(VFX_EHIP, "vfx_plan_autotune: hipEventCreate failed");
+  const int wgs[] = {256, 512, 768, 1024};
+  const int mtbs[] = {4, 8};
+  const int n_mtb = p.ctx->T.n == 256 ? 2 : 1;
+  float best = 1e30f;
+  vfx::Plan::Tune bt = p.tune;
+  int rc = VFX_OK;
+  for (int a = 0; a < 4 && rc == VFX_OK; ++a)
+    for (int b = 0; b < n_mtb && rc == VFX_OK; ++b) {
+      p.tune.near_wgs = wgs[a];
+      p.tune.dense_mtb = mtbs[b];
+      rc = execute_checked(plan, nrhs, f_leaf, f_cut, fe_out, V_out, stream, "vfx_plan_autotune");  // warm-up
+      if (rc) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && rc == VFX_OK; ++r)
+        rc = execute_checked(plan, nrhs, f_leaf, f_cut, fe_out, V_out, stream, "vfx_plan_autotune");
+      (void)hipEventRecord(e1, s);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = fail(VFX_EHIP, "vfx_plan_autotune: event wait failed");
+      float ms = 0;
+      if (rc == VFX_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
+        best = ms;
+        bt = p.tune;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p.tune = bt;
+  p.timing = was_timing;
+  if (choice) {
+    choice[0] = bt.near_wgs;
+    choice[1] = bt.dense_mtb;
+  }
+  return rc;
+}
+
+struct vfx_graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t e = nullptr;
+};
+
+int vfx_graph_begin(void* stream) {
+  hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed);
+  return e == hipSuccess ? VFX_OK : fail(VFX_EHIP, std::string("vfx_graph_begin: ") + hipGetErrorString(e));
+}
+
+int vfx_graph_end(void* stream, vfx_graph** out) {
+  if (!out) return fail(VFX_EINVAL, "vfx_graph_end: null argument");
+  *out = nullptr;
+  std::unique_ptr<vfx_graph> g(new vfx_graph);
+  hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g->g);
+  if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_graph_end: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&g->e, g->g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g->g);
+    return fail(VFX_EHIP, std::string("vfx_graph_end: instantiate: ") + hipGetErrorString(e));
+  }
+  *out = g.release();
+  return VFX_OK;
+}
+
+int vfx_graph_launch(vfx_graph* g, void* stream) {
+  if (!g) return fail(VFX_EINVAL, "vfx_graph_launch: null graph");
+  hipError_t e = hipGraphLaunch(g->e, (hipStream_t)stream);
+  return e == hipSuccess ? VFX_OK : fail(VFX_EHIP, std::string("vfx_graph_launch: ") + hipGetErrorString(e));
+}
+
+int vfx_graph_destroy(vfx_graph* g) {
+  if (!g) return VFX_OK;
+  if (g->e) (void)hipGraphExecDestroy(g->e);
+  if (g->g) (void)hipGraphDestroy(g->g);
+  delete g;
+  return VFX_OK;
 }
 
 int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level) {

@@ -48,6 +48,8 @@ __device__ __forceinline__ double box_side(double root, int level) { return ldex
 __global__ void k_fe_init(int n, int L, const int8_t* __restrict__ kind, const double* __restrict__ f_leaf,
                           double* __restrict__ fe) {
   const long total = (long)L * n;
+  f_leaf += blockIdx.y * total;  // right-hand side blockIdx.y
+  fe += blockIdx.y * total;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const int leaf = (int)(e / n);
     fe[e] = (kind[leaf] == 1) ? f_leaf[e] : 0.0;
@@ -69,7 +71,12 @@ __global__ void __launch_bounds__(256) k_extension(
     const double* __restrict__ pinv_val, const uint8_t* __restrict__ sbar_given, const int* __restrict__ ext_ptr,
     const int* __restrict__ ext_tgt, const double* __restrict__ ext_geo, const double* __restrict__ t,
     const double* __restrict__ AbarT, const double* __restrict__ cbar, const double* __restrict__ f_cut,
-    double* __restrict__ fe) {
+    double* __restrict__ fe, int nrhs, long sfc, long sfe) {
+  // consecutive work-groups take the right-hand sides of one cut leaf, so
+  // its operator P_i is read from HBM once and reused from L2
+  const int rhs = blockIdx.x % nrhs;
+  f_cut += rhs * sfc;
+  fe += rhs * sfe;
   __shared__ double s_fI[kMaxX];
   __shared__ double s_fG[kMaxG];
   __shared__ double s_cb[kMaxKb * kMaxKb];
@@ -82,7 +89,7 @@ __global__ void __launch_bounds__(256) k_extension(
   __shared__ double s_geo[3 * kExtTgtMax];
   __shared__ int s_tg[kExtTgtMax];
   __shared__ uint8_t s_given[kMaxKb * kMaxKb];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x / nrhs;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = K * K, Kb2 = Kb * Kb;
   const int off = pinv_ptr[c], ni = pinv_ptr[c + 1] - off;
@@ -294,7 +301,10 @@ __global__ void __launch_bounds__(64) k_m2l_pairs(int P, double root_size, const
                                                   const int* __restrict__ leaf_box, int p2l_rows,
                                                   const double* __restrict__ pasT, const double* __restrict__ logd,
                                                   const double2* __restrict__ mpole, const double* __restrict__ p2l_y,
-                                                  double2* __restrict__ local) {
+                                                  double2* __restrict__ local, long smp, long spl) {
+  mpole += blockIdx.y * smp;  // right-hand side blockIdx.y
+  local += blockIdx.y * smp;
+  p2l_y += blockIdx.y * spl;
   __shared__ double2 s_o[8 * 64];
   const int g = blockIdx.x;
   const int b0 = grp[g], b1 = grp[g + 1];
@@ -394,7 +404,10 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
                                                   const int* __restrict__ leaf_box, int p2l_rows,
                                                   const double* __restrict__ pasT, const double* __restrict__ logd,
                                                   const double2* __restrict__ mpole, const double* __restrict__ p2l_y,
-                                                  double2* __restrict__ local) {
+                                                  double2* __restrict__ local, long smp, long spl) {
+  mpole += blockIdx.y * smp;  // right-hand side blockIdx.y
+  local += blockIdx.y * smp;
+  p2l_y += blockIdx.y * spl;
   __shared__ double2 s_o[8 * 64];
   const int g = blockIdx.x;
   const int b0 = grp[g], b1 = grp[g + 1];
@@ -507,8 +520,11 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
                                               const int* __restrict__ t_count, const int* __restrict__ src,
                                               const double* __restrict__ A, const double* __restrict__ X,
                                               double* __restrict__ Y, int P2, double root_size,
-                                              const int* __restrict__ leaf_box, const int* __restrict__ box_level) {
+                                              const int* __restrict__ leaf_box, const int* __restrict__ box_level,
+                                              long sx, long sy) {
   static_assert(TE == 64 || MTB % 4 == 0, "TE = 16 splits the row tiles over the four waves");
+  X += blockIdx.y * sx;  // right-hand side blockIdx.y
+  Y += blockIdx.y * sy;
   constexpr int KB = 16;
   constexpr int LDA = TE;        // entries per LDS row (tile of TE = 64 or 16 entries)
   constexpr int LDB = 16 * MTB;  // table rows per LDS row
@@ -680,7 +696,10 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
                                                     const int* __restrict__ t_first, const int* __restrict__ t_count,
                                                     const int* __restrict__ src, const int* __restrict__ lr_R,
                                                     const double* __restrict__ W, const double* __restrict__ Q,
-                                                    const double* __restrict__ X, double* __restrict__ Y) {
+                                                    const double* __restrict__ X, double* __restrict__ Y, long sx,
+                                                    long sy) {
+  X += blockIdx.y * sx;  // right-hand side blockIdx.y
+  Y += blockIdx.y * sy;
   constexpr int LM = kNearLrMax;  // 64
   constexpr int KB = 16;          // source nodes per phase-1 block
   constexpr int QB = 8;           // rank indices per phase-2 block
@@ -787,6 +806,8 @@ __device__ __forceinline__ float bf16_float(uint16_t h) { return __uint_as_float
 
 // leaf data -> three bf16 slices, xs[s][leaf][node]
 __global__ void k_split3(long total, const double* __restrict__ x, uint16_t* __restrict__ xs) {
+  x += blockIdx.y * total;  // right-hand side blockIdx.y
+  xs += blockIdx.y * 3 * total;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
     double r = x[i];
 #pragma unroll
@@ -847,7 +868,9 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
                                                  const int* __restrict__ src, const int* __restrict__ lr_R,
                                                  const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ Qb,
                                                  const uint16_t* __restrict__ xs, long xs_slice,
-                                                 double* __restrict__ Y) {
+                                                 double* __restrict__ Y, long sy) {
+  xs += blockIdx.y * 3 * xs_slice;  // right-hand side blockIdx.y
+  Y += blockIdx.y * sy;
   constexpr int n = 256, LM = kNearLrMax, LDZ = LM + 4;
   __shared__ float sZ[LR ? 64 * LDZ : 1];
   const int nb = gridDim.x, bb = blockIdx.x;
@@ -949,8 +972,10 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
                                            const int* __restrict__ up_pos, const int* __restrict__ box_level,
                                            const double* __restrict__ box_cx, const double* __restrict__ box_cy,
                                            const double* __restrict__ pasT, double2* __restrict__ mpole,
-                                           double2* __restrict__ part) {
+                                           double2* __restrict__ part, long smp, long spart) {
   const int P = EXACT ? PM : Prt;
+  mpole += blockIdx.y * smp;  // right-hand side blockIdx.y
+  part += blockIdx.y * spart;
   __shared__ double2 s_o[8 * 64];
   const int* gg = grp + 5 * blockIdx.x;
   const int u0 = gg[0], u1 = gg[1], e0 = gg[2], e1 = gg[3], slot = gg[4];
@@ -1033,7 +1058,9 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
 
 // Multipoles of the split boxes: slices added in slice order.
 __global__ void __launch_bounds__(64) k_up_sum(int P, const int* __restrict__ split, const double2* __restrict__ part,
-                                               double2* __restrict__ mpole) {
+                                               double2* __restrict__ mpole, long spart, long smp) {
+  part += blockIdx.y * spart;  // right-hand side blockIdx.y
+  mpole += blockIdx.y * smp;
   const int* sp = split + 3 * blockIdx.x;
   const int l = threadIdx.x;
   if (l >= P) return;
@@ -1071,8 +1098,11 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
                                              const int* __restrict__ anc_leaf, const int* __restrict__ leaf_box,
                                              const int* __restrict__ box_level, const double* __restrict__ box_cx,
                                              const double* __restrict__ box_cy, const double* __restrict__ pasT,
-                                             const double2* __restrict__ local, double2* __restrict__ locf) {
+                                             const double2* __restrict__ local, double2* __restrict__ locf, long smp,
+                                             long slf) {
   const int P = EXACT ? PM : Prt;
+  local += blockIdx.y * smp;  // right-hand side blockIdx.y
+  locf += blockIdx.y * slf;
   __shared__ double2 s_o[8 * 64];
   const int f0 = grp[blockIdx.x], f1 = grp[blockIdx.x + 1];
   const int e0 = anc_ptr[f0], e1 = anc_ptr[f1];
@@ -1161,8 +1191,12 @@ __global__ void __launch_bounds__(256) k_far(int K, int Prt, double root_size, c
                                              const double2* __restrict__ locf, const double2* __restrict__ mpole,
                                              const int* __restrict__ l1_ptr, const int* __restrict__ l1_srcbox,
                                              const int* __restrict__ l1_slot, const double* __restrict__ Y,
-                                             double* __restrict__ V) {
+                                             double* __restrict__ V, long slf, long smp, long sny, long sv) {
   const int P = EXACT ? PM : Prt;
+  locf += blockIdx.y * slf;  // right-hand side blockIdx.y
+  mpole += blockIdx.y * smp;
+  Y += blockIdx.y * sny;
+  V += blockIdx.y * sv;
   const int n = K * K;
   const int leaf = blockIdx.x;
   const int i = threadIdx.x;
@@ -1385,6 +1419,34 @@ void free_tables_device(Context* c) {
   D = DeviceTables();
 }
 
+// Buffers that hold one copy per right-hand side (expansions, near-field
+// partials, P2L partials, leaf local expansions, bf16 slices): reallocated
+// for `nrhs` copies when a larger batch is requested.
+int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
+  const HostPlan& H = p->H;
+  DevicePlan& D = p->D;
+  const Tables& T = p->ctx->T;
+  const size_t P = T.p + 1, R = (size_t)nrhs;
+  if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
+  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs};
+  for (void* q : old)
+    if (q) (void)hipFree(q);
+  D.mpole = D.local = D.up_part = D.locf = nullptr;
+  D.near_y = D.p2l_y = nullptr;
+  D.xs = nullptr;
+  D.cap = 0;
+  VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P * R));
+  VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P * R));
+  VFX_HIP(hipMemset(D.local, 0, sizeof(double2) * (size_t)H.B * P * R));
+  if (!H.np_src.empty()) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n * R));
+  if (!H.p4_src.empty()) VFX_HIP(hipMalloc((void**)&D.p2l_y, sizeof(double) * H.p4_src.size() * T.p2l_rows * R));
+  if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P * R));
+  VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P * R));
+  if (H.precision == 1) VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 3 * (size_t)H.L * T.n * R));
+  D.cap = nrhs;
+  return VFX_OK;
+}
+
 int upload_plan(Plan* p, std::string& err) {
   const HostPlan& H = p->H;
   DevicePlan& D = p->D;
@@ -1413,14 +1475,13 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.anc, H.anc);
   UP(D.anc_leaf, H.anc_leaf);
   UP(D.dn_grp, H.dn_grp);
-  VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P));
+
   UP(D.up_box, H.up_box);
   UP(D.up_ptr, H.up_ptr);
   UP(D.up_src, H.up_src);
   UP(D.up_pos, H.up_pos);
   UP(D.up_grp, H.up_grp);
   UP(D.up_split, H.up_split);
-  if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P));
   UP(D.l4_ptr, H.l4_ptr);
   UP(D.l4_src, H.l4_src);
   UP(D.l4_cfg, H.l4_cfg);
@@ -1438,7 +1499,7 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.ml_cfg, H.ml_cfg);
   UP(D.ml_first, H.ml_first);
   UP(D.ml_count, H.ml_count);
-  if (H.precision == 1) VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 3 * (size_t)H.L * T.n));
+
   UP(D.p4_src, H.p4_src);
   UP(D.l4_slot, H.l4_slot);
   UP(D.t4_cfg, H.t4_cfg);
@@ -1448,8 +1509,7 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.t0_first, H.t0_first);
   UP(D.t0_count, H.t0_count);
   UP(D.leaf_ids, H.leaf_ids);
-  if (!H.np_src.empty()) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n));
-  if (!H.p4_src.empty()) VFX_HIP(hipMalloc((void**)&D.p2l_y, sizeof(double) * H.p4_src.size() * T.p2l_rows));
+
   UP(D.cut_leaf, H.cut_leaf);
   UP(D.ext_ptr, H.ext_ptr);
   UP(D.ext_tgt, H.ext_tgt);
@@ -1458,9 +1518,11 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.pinv_idx, H.pinv_idx);
   UP(D.pinv_val, H.pinv_val);
   UP(D.sbar_given, H.sbar_given);
-  VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P));
-  VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P));
-  VFX_HIP(hipMemset(D.local, 0, sizeof(double2) * (size_t)H.B * P));
+  D.cap = 0;
+  {
+    int rc = ensure_rhs_capacity(p, 1, err);
+    if (rc) return rc;
+  }
   VFX_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
   VFX_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
   VFX_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
@@ -1500,40 +1562,52 @@ void free_plan_device(Plan* p) {
 template <int KD, int EPI, int TE, int MTB>
 static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
                         const double* A, const double* X, double* Y, int P2, double root, const int* leaf_box,
-                        const int* box_level, hipStream_t s, int max_wgs) {
+                        const int* box_level, hipStream_t s, int max_wgs, unsigned R, long sx, long sy) {
   const int items = ntiles * (MT / MTB);
   const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
-  hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid), dim3(256), 0, s, items, MT, cfg, first, count, src, A,
-                     X, Y, P2, root, leaf_box, box_level);
+  hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src,
+                     A, X, Y, P2, root, leaf_box, box_level, sx, sy);
 }
 
 // Dense near-field tables: MT = n/16 row tiles (1, 4, 9 or 16 for K = 4, 8,
 // 12, 16), in blocks of MTB = 1, 4, 9, 4.
 static void near_gemm(int n, int ntiles, const int* cfg, const int* first, const int* count, const int* src,
-                      const double* A, const double* X, double* Y, hipStream_t s, int max_wgs) {
+                      const double* A, const double* X, double* Y, hipStream_t s, int max_wgs, int mtb, unsigned R,
+                      long sx, long sy) {
   if (ntiles <= 0) return;
   const int MT = n / 16;
+#define VFX_NG(KDV, MTBV) \
+  launch_gemm<KDV, 0, 64, MTBV>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs, R, sx, sy)
   switch (n) {
-    case 16: launch_gemm<16, 0, 64, 1>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
-    case 64: launch_gemm<64, 0, 64, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
-    case 144: launch_gemm<144, 0, 64, 9>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
-    default: launch_gemm<256, 0, 64, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, max_wgs); break;
+    case 16: VFX_NG(16, 1); break;
+    case 64: VFX_NG(64, 4); break;
+    case 144: VFX_NG(144, 9); break;
+    default:
+      if (mtb == 8)
+        VFX_NG(256, 8);
+      else
+        VFX_NG(256, 4);
+      break;
   }
+#undef VFX_NG
 }
 
 // P2L (EPI 0, TE 64) and P2M (EPI 1, TE 16) tables: rows padded to a
 // multiple of 64, so MT is 4 or 8 and one row block covers it.
 template <int EPI, int TE>
 static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count,
-                           const int* src, const double* A, const double* X, double* Y, hipStream_t s, int P2 = 0,
-                           double root = 0, const int* leaf_box = nullptr, const int* box_level = nullptr) {
+                           const int* src, const double* A, const double* X, double* Y, hipStream_t s, unsigned R,
+                           long sx, long sy, int P2 = 0, double root = 0, const int* leaf_box = nullptr,
+                           const int* box_level = nullptr) {
   if (ntiles <= 0) return;
 #define VFX_EXP_CASE(KDV)                                                                                       \
   do {                                                                                                          \
     if (MT == 4)                                                                                                \
-      launch_gemm<KDV, EPI, TE, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0); \
+      launch_gemm<KDV, EPI, TE, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
+                                   R, sx, sy);                                                                  \
     else                                                                                                        \
-      launch_gemm<KDV, EPI, TE, 8>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0); \
+      launch_gemm<KDV, EPI, TE, 8>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
+                                   R, sx, sy);                                                                  \
   } while (0)
   switch (n) {
     case 16: VFX_EXP_CASE(16); break;
@@ -1546,8 +1620,8 @@ static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int*
 
 constexpr int kNearWgs = 512;
 
-int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V, hipStream_t s,
-                   std::string& err) {
+int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut, double* fe, double* V,
+                   hipStream_t s, std::string& err) {
   Context* c = p->ctx;
   const Tables& T = c->T;
   if (!c->D.ready) {
@@ -1558,10 +1632,19 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
     int rc = upload_plan(p, err);
     if (rc) return rc;
   }
+  if (nrhs > p->D.cap) {
+    int rc = ensure_rhs_capacity(p, nrhs, err);
+    if (rc) return rc;
+  }
   const HostPlan& H = p->H;
   const DeviceTables& DT = c->D;
   const DevicePlan& D = p->D;
   const int n = T.n, P = T.p + 1, L = H.L;
+  // per-right-hand-side strides (elements) of the batched buffers
+  const long sFL = (long)L * n, sFC = (long)H.ncut * T.nX, sMP = (long)H.B * P;
+  const long sNY = (long)H.np_src.size() * n, sPL = (long)H.p4_src.size() * T.p2l_rows;
+  const long sUP = (long)H.up_slots * P, sLF = (long)L * P;
+  const unsigned R = (unsigned)nrhs;
     constexpr int kMaxTimed = 4096;
   constexpr int NE = Plan::kEvents;
   const bool timed = p->timing && p->n_timed < kMaxTimed;
@@ -1596,11 +1679,12 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   {
     const long total = (long)L * n;
     int blocks = (int)std::min<long>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_fe_init, dim3(blocks), dim3(256), 0, s, n, L, D.kind, f_leaf, fe);
+    hipLaunchKernelGGL(k_fe_init, dim3(blocks, R), dim3(256), 0, s, n, L, D.kind, f_leaf, fe);
   }
   if (H.ncut > 0)
-    hipLaunchKernelGGL(k_extension, dim3(H.ncut), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, D.pinv_ptr, D.pinv_idx,
-                       D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t, DT.AbarT, DT.cbar, f_cut, fe);
+    hipLaunchKernelGGL(k_extension, dim3(H.ncut * R), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, D.pinv_ptr,
+                       D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t, DT.AbarT, DT.cbar,
+                       f_cut, fe, nrhs, sFC, sFL);
   VFX_HIP(hipGetLastError());
   MARK(1, s);
   // fork: near field on the side stream, concurrent with P2M, the upward
@@ -1611,29 +1695,29 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   MARK(5, p->side);
   if (!H.nl_cfg.empty()) {
     const int items = (int)H.nl_cfg.size();
-    hipLaunchKernelGGL(k_near_lr<256>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, D.nl_cfg,
-                       D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y);
+    hipLaunchKernelGGL(k_near_lr<256>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
+                       D.nl_cfg, D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y, sFL, sNY);
   }
   MARK(6, p->side);
   near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
-            kNearWgs);
+            p->tune.near_wgs, p->tune.dense_mtb, R, sFL, sNY);
   if (H.precision == 1) {
     // pairs in mixed precision: bf16 slices of the leaf data, then the
     // low-rank and the dense (self) kernels
     const long total = (long)L * n;
-    hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192)), dim3(256), 0, p->side, total,
-                       fe, D.xs);
+    hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192), R), dim3(256), 0, p->side,
+                       total, fe, D.xs);
     if (!H.ml_cfg.empty()) {
       const int items = (int)H.ml_cfg.size();
-      hipLaunchKernelGGL(k_near_mx<true>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, 1,
-                         D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs, total,
-                         D.near_y);
+      hipLaunchKernelGGL(k_near_mx<true>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
+                         1, D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs, total,
+                         D.near_y, sNY);
     }
     if (!H.mt_cfg.empty()) {
       const int items = 4 * (int)H.mt_cfg.size();
-      hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, kNearWgs)), dim3(256), 0, p->side, items, 4,
-                         D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
-                         D.near_y);
+      hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
+                         4, D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
+                         D.near_y, sNY);
     }
   }
   VFX_HIP(hipGetLastError());
@@ -1641,12 +1725,14 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipEventRecord(p->join_ev, p->side));
   // multipoles of the leaves
   expansion_gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
-                        DT.p2m_gemm, fe, (double*)D.mpole, s, 2 * P, T.root_size, D.leaf_box, D.box_level);
+                        DT.p2m_gemm, fe, (double*)D.mpole, s, R, sFL, 2 * sMP, 2 * P, T.root_size, D.leaf_box,
+                        D.box_level);
   if (!H.up_grp.empty()) {
     const int ng = (int)H.up_grp.size() / 5;
 #define VFX_UP(PMV, EX)                                                                                            \
-  hipLaunchKernelGGL((k_up<PMV, EX>), dim3(ng), dim3(64), 0, s, P, T.root_size, D.up_grp, D.up_box, D.up_ptr,     \
-                     D.up_src, D.up_pos, D.box_level, D.box_cx, D.box_cy, DT.pas_m2m_t, D.mpole, D.up_part)
+  hipLaunchKernelGGL((k_up<PMV, EX>), dim3(ng, R), dim3(64), 0, s, P, T.root_size, D.up_grp, D.up_box, D.up_ptr,  \
+                     D.up_src, D.up_pos, D.box_level, D.box_cx, D.box_cy, DT.pas_m2m_t, D.mpole, D.up_part, sMP,  \
+                     sUP)
     if (P == 21)
       VFX_UP(21, true);
     else if (P == 25)
@@ -1661,24 +1747,24 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
       VFX_UP(64, false);
 #undef VFX_UP
     if (!H.up_split.empty())
-      hipLaunchKernelGGL(k_up_sum, dim3((int)H.up_split.size() / 3), dim3(64), 0, s, P, D.up_split, D.up_part,
-                         D.mpole);
+      hipLaunchKernelGGL(k_up_sum, dim3((int)H.up_split.size() / 3, R), dim3(64), 0, s, P, D.up_split, D.up_part,
+                         D.mpole, sUP, sMP);
   }
   VFX_HIP(hipGetLastError());
   MARK(2, s);
   if (H.nlev > 2) {
     expansion_gemm<0, 64>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src,
-                          DT.p2l_gemm, fe, D.p2l_y, s);
+                          DT.p2l_gemm, fe, D.p2l_y, s, R, sFL, sPL);
     const int ng = (int)H.m2l_grp.size() - 1;
     if (ng > 0) {
 #define VFX_M2L(PMV)                                                                                             \
-  hipLaunchKernelGGL(k_m2l_pairs<PMV>, dim3(ng), dim3(64), 0, s, P, T.root_size, D.m2l_grp, D.box_level, D.l2_ptr, \
-                     D.l2_src, D.l2_off, D.l2_tgt, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows,         \
-                     DT.pas_m2l_t, DT.m2l_logd, D.mpole, D.p2l_y, D.local)
+  hipLaunchKernelGGL(k_m2l_pairs<PMV>, dim3(ng, R), dim3(64), 0, s, P, T.root_size, D.m2l_grp, D.box_level,      \
+                     D.l2_ptr, D.l2_src, D.l2_off, D.l2_tgt, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows, \
+                     DT.pas_m2l_t, DT.m2l_logd, D.mpole, D.p2l_y, D.local, sMP, sPL)
 #define VFX_M2LL(PV)                                                                                             \
-  hipLaunchKernelGGL(k_m2l_lanes<PV>, dim3(ng), dim3(64), 0, s, T.root_size, D.m2l_grp, D.box_level, D.l2_ptr,     \
-                     D.l2_src, D.l2_off, D.l2_tgt, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows,         \
-                     DT.pas_m2l_t, DT.m2l_logd, D.mpole, D.p2l_y, D.local)
+  hipLaunchKernelGGL(k_m2l_lanes<PV>, dim3(ng, R), dim3(64), 0, s, T.root_size, D.m2l_grp, D.box_level,          \
+                     D.l2_ptr, D.l2_src, D.l2_off, D.l2_tgt, D.l4_ptr, D.l4_src, D.l4_slot, D.leaf_box, T.p2l_rows, \
+                     DT.pas_m2l_t, DT.m2l_logd, D.mpole, D.p2l_y, D.local, sMP, sPL)
       if (P == 21)
         VFX_M2LL(21);
       else if (P == 25)
@@ -1701,8 +1787,9 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   {
     const int ng = (int)H.dn_grp.size() - 1;
 #define VFX_DOWN(PMV, EX)                                                                                          \
-  hipLaunchKernelGGL((k_down<PMV, EX>), dim3(ng), dim3(64), 0, s, P, T.root_size, D.dn_grp, D.anc_ptr, D.anc,      \
-                     D.anc_leaf, D.leaf_box, D.box_level, D.box_cx, D.box_cy, DT.pas_l2l_t, D.local, D.locf)
+  hipLaunchKernelGGL((k_down<PMV, EX>), dim3(ng, R), dim3(64), 0, s, P, T.root_size, D.dn_grp, D.anc_ptr, D.anc,   \
+                     D.anc_leaf, D.leaf_box, D.box_level, D.box_cx, D.box_cy, DT.pas_l2l_t, D.local, D.locf, sMP,  \
+                     sLF)
     if (P == 21)
       VFX_DOWN(21, true);
     else if (P == 25)
@@ -1722,9 +1809,9 @@ int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* f
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(8, s);
 #define VFX_FAR(PMV, EX)                                                                                       \
-  hipLaunchKernelGGL((k_far<PMV, EX>), dim3(L), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size, D.leaf_box,  \
-                     D.box_level, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, D.locf, D.mpole, D.l1_ptr,     \
-                     D.l1_srcbox, D.l1_slot, D.near_y, V)
+  hipLaunchKernelGGL((k_far<PMV, EX>), dim3(L, R), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size,          \
+                     D.leaf_box, D.box_level, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, D.locf, D.mpole,     \
+                     D.l1_ptr, D.l1_srcbox, D.l1_slot, D.near_y, V, sLF, sMP, sNY, sFL)
   if (P == 21)
     VFX_FAR(21, true);
   else if (P == 25)

@@ -185,6 +185,7 @@ struct DevicePlan {
   int *mt_cfg = nullptr, *mt_first = nullptr, *mt_count = nullptr, *ml_cfg = nullptr, *ml_first = nullptr,
       *ml_count = nullptr;
   uint16_t* xs = nullptr;  // bf16 slices of the leaf data, 3 x L x n
+  int cap = 0;             // right-hand sides the per-RHS buffers hold
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
@@ -207,6 +208,11 @@ struct Plan {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   // per-phase timing: one set of kEvents events per timed execute
   static constexpr int kEvents = 10;
+  // launch parameters chosen by vfx_plan_autotune
+  struct Tune {
+    int near_wgs = 512;  // work-group cap of the persistent near-field kernels
+    int dense_mtb = 4;   // row tiles per block of the dense near-field GEMM (K = 16)
+  } tune;
   bool timing = false;
   std::vector<hipEvent_t> ev;   // kEvents * capacity
   int n_timed = 0;
@@ -221,8 +227,9 @@ int upload_tables(Context* c, std::string& err);
 int upload_plan(Plan* p, std::string& err);
 void free_plan_device(Plan* p);
 void free_tables_device(Context* c);
-int launch_execute(Plan* p, const double* f_leaf, const double* f_cut, double* fe, double* V,
+int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut, double* fe, double* V,
                    hipStream_t s, std::string& err);
+int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err);
 int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
                   hipStream_t s, std::string& err);
 

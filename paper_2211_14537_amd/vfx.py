@@ -52,7 +52,8 @@ _lib = None
 
 EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points", "vfx_leaf_nodes",
             "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
-            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp",
+            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_execute_batch",
+            "vfx_plan_autotune", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
             "vfx_mlp_param_count", "vfx_mlp_forward", "vfx_mlp_grad", "vfx_mlp_adam", "vfx_f32_to_f16",
             "vfx_mlp_infer_f16",
             "vfx_last_error",
@@ -86,6 +87,12 @@ def lib():
         L.vfx_plan_set_timing.argtypes = [vp, ctypes.c_int]
         L.vfx_plan_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.vfx_interp.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+        L.vfx_execute_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.vfx_plan_autotune.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, i32p]
+        L.vfx_graph_begin.argtypes = [vp]
+        L.vfx_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
+        L.vfx_graph_launch.argtypes = [vp, vp]
+        L.vfx_graph_destroy.argtypes = [vp]
         L.vfx_mlp_param_count.argtypes = []
         L.vfx_mlp_grad_work.argtypes = [ctypes.c_int64]
         L.vfx_mlp_forward.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
@@ -226,6 +233,38 @@ class Plan:
         _check(lib().vfx_execute(self._h, f_leaf.data_ptr(), fc, fe_out.data_ptr(), V_out.data_ptr(),
                                  ctypes.c_void_p(stream.cuda_stream)))
 
+    def _batch_args(self, nrhs, f_leaf, f_cut, fe_out, V_out):
+        import torch
+        n = self.ctx.K * self.ctx.K
+        for name, t in (("f_leaf", f_leaf), ("fe_out", fe_out), ("V_out", V_out)):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                    and t.numel() == nrhs * self.n_leaves * n):
+                raise ValueError(f"{name}: expected contiguous float64 CUDA tensor of {nrhs} x {self.n_leaves} x {n}")
+        fc = 0
+        if self.n_cut:
+            if not (f_cut.is_cuda and f_cut.dtype == torch.float64 and f_cut.is_contiguous()
+                    and f_cut.numel() == nrhs * self.n_cut * self.ctx.n_stencil):
+                raise ValueError("f_cut: expected contiguous float64 CUDA tensor (nrhs, n_cut, |X|)")
+            fc = f_cut.data_ptr()
+        return f_leaf.data_ptr(), fc, fe_out.data_ptr(), V_out.data_ptr()
+
+    def execute_batch(self, nrhs, f_leaf, f_cut, fe_out, V_out, stream=None):
+        """nrhs right-hand sides at once (stacked tensors)."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        a = self._batch_args(nrhs, f_leaf, f_cut, fe_out, V_out)
+        _check(lib().vfx_execute_batch(self._h, int(nrhs), *a, ctypes.c_void_p(st.cuda_stream)))
+
+    def autotune(self, nrhs, f_leaf, f_cut, fe_out, V_out, reps=3, stream=None):
+        """Pick the near-field launch parameters by timing; returns them."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        a = self._batch_args(nrhs, f_leaf, f_cut, fe_out, V_out)
+        ch = np.zeros(2, dtype=np.int32)
+        _check(lib().vfx_plan_autotune(self._h, int(nrhs), *a, ctypes.c_void_p(st.cuda_stream), int(reps),
+                                       _ptr(ch, ctypes.c_int32)))
+        return {"near_wgs": int(ch[0]), "dense_mtb": int(ch[1])}
+
     def interp(self, V, px, py, out, stream=None):
         """Interpolate leaf-grid data V (n_leaves x K^2) to the points
         (px, py) into out (all float64 CUDA tensors)."""
@@ -329,3 +368,32 @@ def mlp_infer_f16(theta_h, x_h, logits, stream=None):
             raise ValueError(f"{name}: expected a contiguous float16 CUDA tensor with {n} entries")
     _check(lib().vfx_mlp_infer_f16(theta_h.data_ptr(), x_h.data_ptr(), B, _dev_f32(logits, B, "logits"),
                                    _stream(stream)))
+
+
+class Graph:
+    """Executes captured on a stream and replayed with one launch."""
+
+    def __init__(self):
+        self._h = None
+
+    def begin(self, stream):
+        _check(lib().vfx_graph_begin(ctypes.c_void_p(stream.cuda_stream)))
+
+    def end(self, stream):
+        h = ctypes.c_void_p()
+        _check(lib().vfx_graph_end(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream):
+        _check(lib().vfx_graph_launch(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def close(self):
+        if self._h is not None:
+            lib().vfx_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

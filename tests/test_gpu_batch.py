@@ -1,0 +1,110 @@
+"""Batched right-hand sides, HIP graph capture of many plans, autotuner.
+
+A batch of right-hand sides runs every kernel once with the right-hand side
+as a grid dimension; it must reproduce separate executes bitwise.  Executes
+of several plans captured in one graph must reproduce the eager results
+bitwise on every replay (with eager work between replays).  The autotuner's
+choices change only the distribution of work, so results are bitwise
+independent of them."""
+import numpy as np
+import pytest
+
+from gpu_cases import say, setup
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(case, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    fl = np.stack([case["f_leaf"] * rng.uniform(0.5, 2.0) + 0.1 * rng.standard_normal(case["f_leaf"].shape)
+                   for _ in range(nrhs)])
+    fc = np.stack([case["f_cut"] * rng.uniform(0.5, 2.0) + 0.1 * rng.standard_normal(case["f_cut"].shape)
+                   for _ in range(nrhs)]) if case["f_cut"].size else np.zeros((nrhs, 0, case["ctx"].n_stencil))
+    return fl, fc
+
+
+def _dev(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def _single(case, fl, fc):
+    import torch
+    plan = case["plan"]
+    fe = torch.empty_like(fl)
+    V = torch.empty_like(fl)
+    plan.execute(fl, fc, fe, V)
+    torch.cuda.synchronize()
+    return fe.cpu().numpy(), V.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,precision", [("starfish_small", 0), ("starfish_small", 1), ("disk_uniform3", 0)])
+def test_batch_matches_single_executes(gpu_device, name, precision):
+    import torch
+    case = setup(name, p=24 if name == "starfish_small" else 20)
+    if precision:
+        case["plan"].set_precision(1, 0)
+    nrhs = 5
+    fl, fc = _inputs(case, nrhs, 1)
+    singles = [_single(case, _dev(fl[r]), _dev(fc[r])) for r in range(nrhs)]
+    FL, FC = _dev(fl), _dev(fc)
+    FE, V = torch.empty_like(FL), torch.empty_like(FL)
+    case["plan"].execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    FE, V = FE.cpu().numpy(), V.cpu().numpy()
+    for r in range(nrhs):
+        assert np.array_equal(FE[r], singles[r][0])
+        assert np.array_equal(V[r], singles[r][1])
+    say(f"    {name} precision {precision}: batch of {nrhs} bitwise equal to single executes")
+
+
+def test_graph_of_several_plans_replays_bitwise(gpu_device):
+    import torch
+    cases = [setup("starfish_small", p=24), setup("disk_uniform3", p=20), setup("disk_adaptive_small", p=40)]
+    bufs = []
+    for i, c in enumerate(cases):
+        fl, fc = _inputs(c, 2, 10 + i)
+        FL, FC = _dev(fl), _dev(fc)
+        FE, V = torch.empty_like(FL), torch.empty_like(FL)
+        c["plan"].execute_batch(2, FL, FC, FE, V)  # uploads and sizes the plan before capture
+        bufs.append((FL, FC, FE, V))
+    torch.cuda.synchronize()
+    eager = [(b[2].cpu().numpy().copy(), b[3].cpu().numpy().copy()) for b in bufs]
+    from paper_2211_14537_amd import vfx
+    s = torch.cuda.Stream()
+    g = vfx.Graph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        for c, (FL, FC, FE, V) in zip(cases, bufs):
+            c["plan"].execute_batch(2, FL, FC, FE, V, stream=s)
+        g.end(s)
+    for rep in range(3):
+        for (_, _, FE, V) in bufs:
+            FE.fill_(float("nan"))
+            V.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        for (FE0, V0), (_, _, FE, V) in zip(eager, bufs):
+            assert np.array_equal(FE.cpu().numpy(), FE0)
+            assert np.array_equal(V.cpu().numpy(), V0)
+        _ = (torch.ones(1000, device="cuda:0") * rep).sum().item()  # eager work between replays
+    g.close()
+    say("    graph of 3 plans x 2 right-hand sides: 3 replays bitwise equal to eager")
+
+
+def test_autotune_keeps_results(gpu_device):
+    import torch
+    case = setup("starfish_small", p=24)
+    fl, fc = _inputs(case, 2, 3)
+    FL, FC = _dev(fl), _dev(fc)
+    FE, V = torch.empty_like(FL), torch.empty_like(FL)
+    case["plan"].execute_batch(2, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    V0 = V.cpu().numpy().copy()
+    ch = case["plan"].autotune(2, FL, FC, FE, V, reps=2)
+    assert ch["near_wgs"] in (256, 512, 768, 1024) and ch["dense_mtb"] in (4, 8)
+    case["plan"].execute_batch(2, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    assert np.array_equal(V.cpu().numpy(), V0)
+    say(f"    autotune choice {ch}; results unchanged")

@@ -17,6 +17,9 @@ the solver); this module only states the recipe.
   of data (widths from U[0.005, 0.1], seed 3), K = 16, cut leaves at level 9,
   every non-exterior leaf at level >= 7: 14254 leaves, 3.65e6 leaf nodes;
   FMM order 24.
+* ``starfish_batch``: 256 seeded right-hand sides (Gaussian sums of 1-8
+  bumps, widths U[0.01, 0.1], seed 4) on one starfish tree of depth 8 (cut
+  leaves at level 8), refined on the sum of all of them; K = 16, p = 24.
 * small variants used by the tests (``disk_tiny``, ``starfish_small``,
   ``disk_adaptive_small``).
 """
@@ -37,6 +40,34 @@ def _seeded_gaussians(domain, n, wlo, whi, seed, box=0.7):
         if domain.inside(p[0], p[1]):
             centers.append(p)
     return GaussianSum(np.array(centers), widths)
+
+
+def batch_functions(domain, nrhs, seed):
+    """Seeded right-hand sides for the batched workload: Gaussian sums of 1-8
+    bumps each (widths U[0.01, 0.1], centres uniform in the domain)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nrhs):
+        nb = int(rng.integers(1, 9))
+        widths = rng.uniform(0.01, 0.1, nb)
+        centers = []
+        while len(centers) < nb:
+            q = rng.uniform(-0.7, 0.7, 2)
+            if domain.inside(q[0], q[1]):
+                centers.append(q)
+        out.append(GaussianSum(np.array(centers), widths, rng.uniform(0.5, 1.5, nb)))
+    return out
+
+
+class _Union:
+    """The sum of several right-hand sides (the tree of a batch is refined on
+    it, so it resolves every member)."""
+
+    def __init__(self, funs):
+        self.funs = funs
+
+    def f(self, x, y):
+        return sum(g.f(x, y) for g in self.funs)
 
 
 def _cfg(name):
@@ -74,11 +105,16 @@ def _cfg(name):
                     fun=_seeded_gaussians(dom, 4, 0.005, 0.1, seed=3),
                     tree=dict(kind="adaptive", tol=1e-12, max_depth=10, min_cut_level=9, min_level=7),
                     seed=3)
+    if name == "starfish_batch":
+        dom = Starfish(0.5, 0.15, 5)
+        funs = batch_functions(dom, 256, seed=4)
+        return dict(name=name, root=(0.0, 0.0, 2.0), K=16, p=24, domain=dom, fun=_Union(funs), rhs=funs,
+                    tree=dict(kind="adaptive", tol=1e-12, max_depth=8, min_cut_level=8), seed=4)
     raise KeyError(name)
 
 
 CONFIG_NAMES = ("disk_uniform3", "disk_tiny", "disk_adaptive_small", "starfish_small",
-                "starfish_adaptive", "wedge_adaptive")
+                "starfish_adaptive", "wedge_adaptive", "starfish_batch")
 
 
 def get_config(name):
