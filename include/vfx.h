@@ -186,6 +186,21 @@ int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, 
  * device and must not overlap an execute of the same plan. */
 int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level);
 
+/* Plan with the per-cut-leaf least-squares operators computed on the GPU
+ * (NEXT: GPU plan stage).  flags = VFX_PLAN_DEFER_FACTOR: the host builds
+ * only the lists and the interior index sets, and vfx_plan_factor_gpu then
+ * computes every P_i = A_{X^I,G}^+ on the device, one work-group per cut
+ * leaf: Householder QR of the N_I x N_G rows of A (the paper's QR per cut
+ * square, \S7), one-sided Jacobi SVD of R, singular values below
+ * 1e-13 sigma_max dropped (minimum-norm when N_I < N_G), P_i = pinv(R) Q^T,
+ * all in FP64.  It is asynchronous on `stream`; executes on other streams
+ * must be ordered after it by the caller.  vfx_execute on a deferred plan
+ * that was not factored returns VFX_EINVAL.  Supports N_G <= 66 (stencil
+ * degree <= 10; VFX_EINVAL otherwise).  flags = 0 is vfx_plan_create. */
+#define VFX_PLAN_DEFER_FACTOR 1
+int vfx_plan_create_ex(vfx_ctx* ctx, const vfx_tree* tree, int flags, vfx_plan** out);
+int vfx_plan_factor_gpu(vfx_plan* plan, void* stream);
+
 /* Many right-hand sides on one tree (NEXT: batched execution).  Inputs and
  * outputs are stacked: f_leaf, fe_out, V_out are nrhs x n_leaves x K^2 and
  * f_cut is nrhs x n_cut x |X| (device, row-major).  Every kernel of the

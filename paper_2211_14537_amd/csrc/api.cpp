@@ -101,21 +101,44 @@ int vfx_leaf_nodes(const vfx_ctx* ctx, double* t) {
   return VFX_OK;
 }
 
-int vfx_plan_create(vfx_ctx* ctx, const vfx_tree* tree, vfx_plan** out) {
-  if (!ctx || !tree || !out) return fail(VFX_EINVAL, "vfx_plan_create: null argument");
+static int plan_create(vfx_ctx* ctx, const vfx_tree* tree, int flags, vfx_plan** out, const char* who) {
+  if (!ctx || !tree || !out) return fail(VFX_EINVAL, std::string(who) + ": null argument");
+  if (flags & ~VFX_PLAN_DEFER_FACTOR) return fail(VFX_EINVAL, std::string(who) + ": unknown flags");
   *out = nullptr;
   try {
     std::unique_ptr<vfx_plan> p(new vfx_plan);
     p->p.ctx = &ctx->c;
     std::string err;
-    int rc = vfx::build_host_plan(ctx->c.T, tree, p->p.H, err);
-    if (rc) return fail(rc, "vfx_plan_create: " + err);
+    int rc = vfx::build_host_plan(ctx->c.T, tree, p->p.H, err, (flags & VFX_PLAN_DEFER_FACTOR) != 0);
+    if (rc) return fail(rc, std::string(who) + ": " + err);
     *out = p.release();
     return VFX_OK;
   } catch (const std::bad_alloc&) {
-    return fail(VFX_ENOMEM, "vfx_plan_create: out of host memory");
-  } catch (const std::exception& e) {
-    return fail(VFX_EINVAL, std::string("vfx_plan_create: ") + e.what());
+    return fail(VFX_ENOMEM, std::string(who) + ": out of host memory");
+  }
+}
+
+int vfx_plan_create(vfx_ctx* ctx, const vfx_tree* tree, vfx_plan** out) {
+  return plan_create(ctx, tree, 0, out, "vfx_plan_create");
+}
+
+int vfx_plan_create_ex(vfx_ctx* ctx, const vfx_tree* tree, int flags, vfx_plan** out) {
+  return plan_create(ctx, tree, flags, out, "vfx_plan_create_ex");
+}
+
+int vfx_plan_factor_gpu(vfx_plan* plan, void* stream) {
+  if (!plan) return fail(VFX_EINVAL, "vfx_plan_factor_gpu: null argument");
+  vfx::Plan& p = plan->p;
+  try {
+    std::string err;
+    int rc = VFX_OK;
+    if (!p.ctx->D.ready) rc = vfx::upload_tables(p.ctx, err);
+    if (!rc && !p.D.ready) rc = vfx::upload_plan(&p, err);
+    if (!rc) rc = vfx::factor_gpu(&p, (hipStream_t)stream, err);
+    if (rc) return fail(rc, "vfx_plan_factor_gpu: " + err);
+    return VFX_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_plan_factor_gpu: out of host memory");
   }
 }
 

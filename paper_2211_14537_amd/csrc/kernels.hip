@@ -1360,6 +1360,7 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.tbar, T.tbar);
   UP(D.w2, T.w2);
   UP(D.AbarT, T.AbarT);
+  UP(D.A, T.A);
   UP(D.cbar, T.cbar);
   UP(D.near, T.near);
   UP(D.lr_R, T.lr_R);
@@ -1409,7 +1410,7 @@ int upload_tables(Context* c, std::string& err) {
 
 void free_tables_device(Context* c) {
   DeviceTables& D = c->D;
-  void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,
+  void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,   D.A,
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
@@ -1516,7 +1517,12 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.ext_geo, H.ext_geo);
   UP(D.pinv_ptr, H.pinv_ptr);
   UP(D.pinv_idx, H.pinv_idx);
-  UP(D.pinv_val, H.pinv_val);
+  if (H.factored) {
+    UP(D.pinv_val, H.pinv_val);
+  } else if (H.ncut > 0) {
+    VFX_HIP(hipMalloc((void**)&D.pinv_val, sizeof(double) * (size_t)H.pinv_ptr[H.ncut] * T.nG));
+  }
+  D.factored = H.factored;
   UP(D.sbar_given, H.sbar_given);
   D.cap = 0;
   {
@@ -1542,7 +1548,7 @@ void free_plan_device(Plan* p) {
                   D.t0_count,  D.leaf_ids,   D.l2_tgt,   D.m2l_grp,  D.up_box,   D.up_ptr,   D.up_src,
                   D.up_pos,    D.up_split,   D.up_grp,   D.up_part,  D.anc_ptr,  D.anc,
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
-                  D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg,
+                  D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg, D.fac_ws,
                   D.ml_first,  D.ml_count,   D.xs};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -1635,6 +1641,10 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   if (nrhs > p->D.cap) {
     int rc = ensure_rhs_capacity(p, nrhs, err);
     if (rc) return rc;
+  }
+  if (!p->D.factored) {
+    err = "the plan defers its least-squares operators to the GPU: call vfx_plan_factor_gpu first";
+    return VFX_EINVAL;
   }
   const HostPlan& H = p->H;
   const DeviceTables& DT = c->D;

@@ -111,7 +111,7 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
   return VFX_OK;
 }
 
-int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err) {
+int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err, bool defer_factor) {
   auto t0 = std::chrono::steady_clock::now();
   const int L = tree->n_leaves;
   if (L <= 0 || !tree->level || !tree->ix || !tree->iy || !tree->kind) {
@@ -566,7 +566,8 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     for (int a = 0; a < Kb2; ++a) H.sbar_given[(size_t)c * Kb2 + a] = m[T.n + a] ? 1 : 0;
   }
   H.pinv_idx.resize(H.pinv_ptr[H.ncut]);
-  H.pinv_val.assign((size_t)H.pinv_ptr[H.ncut] * nG, 0.0);
+  H.factored = !defer_factor;
+  if (H.factored) H.pinv_val.assign((size_t)H.pinv_ptr[H.ncut] * nG, 0.0);
   for (int c = 0; c < H.ncut; ++c) {
     const uint8_t* m = tree->cut_mask + (size_t)c * nX;
     int q = H.pinv_ptr[c];
@@ -574,7 +575,7 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
       if (m[k]) H.pinv_idx[q++] = (uint16_t)k;
   }
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int c = 0; c < H.ncut; ++c) {
+  for (int c = 0; c < (H.factored ? H.ncut : 0); ++c) {
     const int off = H.pinv_ptr[c], ni = H.pinv_ptr[c + 1] - off;
     if (ni == 0) continue;
     std::vector<double> AI((size_t)ni * nG);

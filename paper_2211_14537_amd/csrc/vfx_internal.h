@@ -99,7 +99,7 @@ int pinv_jacobi(const double* A, int m, int n, double rel_cut, double* P);
 struct DeviceTables {
   bool ready = false;
   int device = -1;
-  double *t = nullptr, *tbar = nullptr, *w2 = nullptr, *AbarT = nullptr, *cbar = nullptr;
+  double *t = nullptr, *tbar = nullptr, *w2 = nullptr, *AbarT = nullptr, *cbar = nullptr, *A = nullptr;
   double *near = nullptr, *near_s2 = nullptr;
   int* lr_R = nullptr;
   double *lr_W = nullptr, *lr_Q = nullptr;
@@ -161,6 +161,7 @@ struct HostPlan {
   std::vector<int> pinv_ptr;                 // ncut + 1 (in interior points)
   std::vector<uint16_t> pinv_idx;            // interior stencil indices
   std::vector<double> pinv_val;              // per cut: nG x N_I row-major
+  bool factored = true;                      // false: P_i are computed on the GPU
   std::vector<uint8_t> sbar_given;           // ncut x Kbar^2
   double plan_seconds = 0;
 };
@@ -186,6 +187,8 @@ struct DevicePlan {
       *ml_count = nullptr;
   uint16_t* xs = nullptr;  // bf16 slices of the leaf data, 3 x L x n
   int cap = 0;             // right-hand sides the per-RHS buffers hold
+  bool factored = false;   // pinv_val holds the P_i
+  double* fac_ws = nullptr;  // scratch of the GPU factorisation
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
@@ -219,7 +222,8 @@ struct Plan {
 };
 
 // plan.cpp
-int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err);
+int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::string& err, bool defer_factor = false);
+int factor_gpu(Plan* p, hipStream_t s, std::string& err);
 int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std::string& err);
 
 // kernels.hip

@@ -52,7 +52,8 @@ _lib = None
 
 EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points", "vfx_leaf_nodes",
             "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
-            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_execute_batch",
+            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_execute_batch", "vfx_plan_create_ex",
+            "vfx_plan_factor_gpu",
             "vfx_plan_autotune", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
             "vfx_mlp_param_count", "vfx_mlp_forward", "vfx_mlp_grad", "vfx_mlp_adam", "vfx_f32_to_f16",
             "vfx_mlp_infer_f16",
@@ -88,6 +89,8 @@ def lib():
         L.vfx_plan_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.vfx_interp.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
         L.vfx_execute_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+        L.vfx_plan_create_ex.argtypes = [vp, ctypes.POINTER(_Tree), ctypes.c_int, ctypes.POINTER(vp)]
+        L.vfx_plan_factor_gpu.argtypes = [vp, vp]
         L.vfx_plan_autotune.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, i32p]
         L.vfx_graph_begin.argtypes = [vp]
         L.vfx_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
@@ -167,7 +170,7 @@ class Context:
 class Plan:
     """A tree prepared for repeated execution (lists, extension operators)."""
 
-    def __init__(self, ctx, level, ix, iy, kind, cut_mask=None):
+    def __init__(self, ctx, level, ix, iy, kind, cut_mask=None, defer_factor=False):
         self.ctx = ctx
         self._level = np.ascontiguousarray(level, dtype=np.int32)
         self._ix = np.ascontiguousarray(ix, dtype=np.int32)
@@ -181,10 +184,17 @@ class Plan:
                    _ptr(self._iy, ctypes.c_int32), _ptr(self._kind, ctypes.c_int8),
                    _ptr(self._mask, ctypes.c_uint8))
         h = ctypes.c_void_p()
-        _check(lib().vfx_plan_create(ctx._h, ctypes.byref(tr), ctypes.byref(h)))
+        _check(lib().vfx_plan_create_ex(ctx._h, ctypes.byref(tr), 1 if defer_factor else 0, ctypes.byref(h)))
         self._h = h
         self.n_leaves = self._level.size
         self.n_cut = ncut
+
+    def factor_gpu(self, stream=None):
+        """Compute the cut leaves' least-squares operators on the GPU (plans
+        created with defer_factor=True)."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().vfx_plan_factor_gpu(self._h, ctypes.c_void_p(st.cuda_stream)))
 
     def stats(self):
         s = _Stats()

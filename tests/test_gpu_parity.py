@@ -153,3 +153,32 @@ def test_single_leaf_and_two_levels(gpu_device):
         torch.cuda.synchronize()
         vo = volume.potential(ot, f, 8, X.ravel(), Y.ravel())
         assert np.abs(V.cpu().numpy().ravel() - vo).max() <= 1e-12 * np.abs(vo).max()
+
+
+@pytest.mark.parametrize("name", ["disk_uniform3", "starfish_small"])
+def test_gpu_factorised_plan(gpu_device, name):
+    """Plan stage on the GPU: the least-squares operators from the device QR +
+    Jacobi SVD give an extension within the same conditioning-aware bound of
+    the oracle's float64 extension as the host-factored plan."""
+    import torch
+    from paper_2211_14537_amd import vfx
+    case = setup(name, p=20 if name == "disk_uniform3" else 24)
+    tr = case["tree"]
+    fe_h, V_h = run_gpu(case)
+    plan_d = vfx.Plan(case["ctx"], tr["level"], tr["ix"], tr["iy"], tr["kind"], tr["mask"], defer_factor=True)
+    fl = torch.tensor(case["f_leaf"], dtype=torch.float64, device="cuda:0")
+    fc = torch.tensor(case["f_cut"], dtype=torch.float64, device="cuda:0")
+    fe, V = torch.empty_like(fl), torch.empty_like(fl)
+    with pytest.raises(vfx.VfxError):
+        plan_d.execute(fl, fc, fe, V)  # not factored yet
+    plan_d.factor_gpu()
+    plan_d.execute(fl, fc, fe, V)
+    torch.cuda.synchronize()
+    fe_d = fe.cpu().numpy()
+    ot = case["otree"]
+    ref, info = extension.extend(ot, tr["kind"], case["f_leaf"], case["f_cut"], tr["mask"].astype(bool),
+                                 case["K"], precision="fp64")
+    w = _check_extension(case, fe_d, ref, info, 2.0)
+    w_h = _check_extension(case, fe_h, ref, info, 2.0)
+    say(f"    {name}: GPU-factored worst error/bound {w:.3f} (host-factored {w_h:.3f})")
+    assert np.array_equal(fe_d[tr["kind"] == 1], case["f_leaf"][tr["kind"] == 1])
