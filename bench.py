@@ -454,7 +454,9 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "leaf points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+bf16x3/f32",
+        "data": "synthetic",
         "config": {"workload": case["cfg"]["name"], "leaves": st["n_leaves"], "nodes": N, "K": case["K"],
                    "p": case["p"], "levels": st["n_levels"], "cut_leaves": st["n_cut"],
                    "ext_targets": st["n_ext_targets"],

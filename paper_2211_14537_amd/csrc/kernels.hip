@@ -834,26 +834,80 @@ __device__ __forceinline__ vfx_f4 mfma_x3(const vfx_s8 a[3], const vfx_s8 b[3], 
   return acc;
 }
 
-// acc[r] = X-rows (this lane's pair) times B rows 16r.. of wbase, r < MT1
-// (compile-time, so the MFMA sequence has no branches); acc[r >= MT1] = 0
-template <int MT1>
-__device__ __forceinline__ void mx_phase1(const uint16_t* __restrict__ xrow, long xs_slice,
-                                          const uint16_t* __restrict__ wbase, size_t wslice, vfx_f4 acc[4]) {
-  constexpr int n = 256;
+// Operand staging for the mixed kernels: a block of 64 B-operand rows x 32
+// contraction values x 3 slices, rows padded to 40 bf16 (80 bytes, so the 16
+// rows a quarter-wave reads start in distinct bank groups).  The 256 threads
+// move it in 768 16-byte pieces; consecutive threads take consecutive pieces
+// of a row.
+constexpr int kMxRS = 40;
+constexpr int kMxBuf = 3 * 64 * kMxRS;  // bf16 per staging buffer
+
+struct MxStage {
+  vfx_s8 v[3];
+};
+
+// load the block (rows row0.. of a [s][row][ld] slice array, columns c0..c0+31)
+__device__ __forceinline__ void mx_gload(MxStage& st, const uint16_t* __restrict__ base, size_t slice, int ld,
+                                         int row0, int c0, int nrows) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int q = t + 256 * j, s = q >> 8, rem = q & 255, row = rem >> 2, part = rem & 3;
+    st.v[j] = row < nrows ? *(const vfx_s8*)(base + (size_t)s * slice + (size_t)(row0 + row) * ld + c0 + 8 * part)
+                          : vfx_s8{0, 0, 0, 0, 0, 0, 0, 0};
+  }
+}
+__device__ __forceinline__ void mx_lstore(const MxStage& st, uint16_t* sb) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int q = t + 256 * j, s = q >> 8, rem = q & 255, row = rem >> 2, part = rem & 3;
+    *(vfx_s8*)(sb + s * 64 * kMxRS + row * kMxRS + 8 * part) = st.v[j];
+  }
+}
+// B fragments of row tile r from a staged block
+__device__ __forceinline__ void mx_bfrag(const uint16_t* sb, int r, vfx_s8 b[3]) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
 #pragma unroll
+  for (int s = 0; s < 3; ++s) b[s] = *(const vfx_s8*)(sb + s * 64 * kMxRS + (16 * r + li) * kMxRS + 8 * lk);
+}
+
+// Phase 1: acc[r] = (this lane's pair row of X) . (B rows 16r..16r+15),
+// r < MT1 (compile-time), over n = 256 contraction values in 8 blocks of 32;
+// B from `wbase` ([s][row][256], slice stride wslice, rows row0..), staged
+// through the double buffer sbuf; the A fragments come straight from the
+// pair's bf16 slices (they are this wave's own rows).
+template <int MT1>
+__device__ __forceinline__ void mx_phase1(const uint16_t* __restrict__ xrow, long xs_slice,
+                                          const uint16_t* __restrict__ wbase, size_t wslice, int row0,
+                                          uint16_t* sbuf, vfx_f4 acc[4]) {
+  constexpr int n = 256, NKB = n / 32;
+#pragma unroll
   for (int r = 0; r < 4; ++r) acc[r] = vfx_f4{0, 0, 0, 0};
-  for (int kb = 0; kb < n / 32; ++kb) {
-    vfx_s8 a[3], b[MT1][3];
+  MxStage st;
+  vfx_s8 a[2][3];
+  mx_gload(st, wbase, wslice, n, row0, 0, 16 * MT1);
 #pragma unroll
-    for (int s = 0; s < 3; ++s) a[s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice + 32 * kb);
+  for (int s = 0; s < 3; ++s) a[0][s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice);
+  __syncthreads();  // the previous user of sbuf is done
+  mx_lstore(st, sbuf);
+  __syncthreads();
+  for (int kb = 0; kb < NKB; ++kb) {
+    const int q = kb & 1;
+    if (kb + 1 < NKB) {
+      mx_gload(st, wbase, wslice, n, row0, 32 * (kb + 1), 16 * MT1);
 #pragma unroll
-    for (int r = 0; r < MT1; ++r)
+      for (int s = 0; s < 3; ++s) a[q ^ 1][s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice + 32 * (kb + 1));
+    }
+    const uint16_t* sb = sbuf + q * kMxBuf;
 #pragma unroll
-      for (int s = 0; s < 3; ++s)
-        b[r][s] = *(const vfx_s8*)(wbase + (size_t)s * wslice + (size_t)(16 * r + li) * n + 32 * kb + 8 * lk);
-#pragma unroll
-    for (int r = 0; r < MT1; ++r) acc[r] = mfma_x3(a, b[r], acc[r]);
+    for (int r = 0; r < MT1; ++r) {
+      vfx_s8 b[3];
+      mx_bfrag(sb, r, b);
+      acc[r] = mfma_x3(a[q], b, acc[r]);
+    }
+    if (kb + 1 < NKB) mx_lstore(st, sbuf + (q ^ 1) * kMxBuf);
+    __syncthreads();
   }
 }
 
@@ -872,6 +926,7 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
   xs += blockIdx.y * 3 * xs_slice;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
   constexpr int n = 256, LM = kNearLrMax, LDZ = LM + 4;
+  __shared__ __attribute__((aligned(16))) uint16_t sbuf[2 * kMxBuf];
   __shared__ float sZ[LR ? 64 * LDZ : 1];
   const int nb = gridDim.x, bb = blockIdx.x;
   const int x = bb & 7;
@@ -887,16 +942,16 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
     const int ent = 16 * w + li;  // this lane's A-operand pair
     const int leaf = src[p0 + (ent < np ? ent : 0)];
     const uint16_t* xrow = xs + (size_t)leaf * n + 8 * lk;
-    // phase 1: B operand rows (ranks, or target rows of the dense block)
     const int MT1 = LR ? lr_R[c] / 16 : 4;
     const size_t wslice = LR ? (size_t)LM * n : (size_t)n * n;
-    const uint16_t* wbase = LR ? Wb + (size_t)c * 3 * wslice : Wb + (size_t)64 * rb * n;
+    const uint16_t* wbase = LR ? Wb + (size_t)c * 3 * wslice : Wb;
+    const int row0 = LR ? 0 : 64 * rb;
     vfx_f4 acc[4];
     switch (MT1) {
-      case 1: mx_phase1<1>(xrow, xs_slice, wbase, wslice, acc); break;
-      case 2: mx_phase1<2>(xrow, xs_slice, wbase, wslice, acc); break;
-      case 3: mx_phase1<3>(xrow, xs_slice, wbase, wslice, acc); break;
-      default: mx_phase1<4>(xrow, xs_slice, wbase, wslice, acc); break;
+      case 1: mx_phase1<1>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
+      case 2: mx_phase1<2>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
+      case 3: mx_phase1<3>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
+      default: mx_phase1<4>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
     }
     if (!LR) {
 #pragma unroll
@@ -913,16 +968,23 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int e = 0; e < 4; ++e) sZ[(16 * w + 4 * lk + e) * LDZ + 16 * r + li] = r < MT1 ? acc[r][e] : 0.0f;
-    __syncthreads();
-    // phase 2: Y = Z Q^T over the ranks in blocks of 32
+    // phase 2: Y = Z Q^T; stages (rank block kb, row chunk ch of 64 rows),
+    // Q blocks staged through sbuf
     const uint16_t* qbase = Qb + (size_t)c * 3 * LM * n;
-    const int nkb = (16 * MT1 + 31) / 32;
+    const int nkb = (16 * MT1 + 31) / 32, nst = 4 * nkb;
     vfx_f4 acc2[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc2[r] = vfx_f4{0, 0, 0, 0};
-    for (int kb = 0; kb < nkb; ++kb) {
-      vfx_s8 a[3];
-      {
+    MxStage st;
+    mx_gload(st, qbase, (size_t)LM * n, LM, 0, 0, 64);
+    __syncthreads();  // phase-1 reads of sbuf and the Z writes are done
+    mx_lstore(st, sbuf);
+    __syncthreads();
+    vfx_s8 a[3];
+    for (int sg = 0; sg < nst; ++sg) {
+      const int kb = sg >> 2, ch = sg & 3, qb = sg & 1;
+      if (sg + 1 < nst) mx_gload(st, qbase, (size_t)LM * n, LM, 64 * ((sg + 1) & 3), 32 * ((sg + 1) >> 2), 64);
+      if (ch == 0) {
         const float* zr = sZ + (16 * w + li) * LDZ + 32 * kb + 8 * lk;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -935,14 +997,20 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
           }
         }
       }
+      const uint16_t* sb = sbuf + qb * kMxBuf;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r4 = 0; r4 < 4; ++r4) {
         vfx_s8 b[3];
-#pragma unroll
-        for (int s = 0; s < 3; ++s)
-          b[s] = *(const vfx_s8*)(qbase + (size_t)s * LM * n + (size_t)(16 * r + li) * LM + 32 * kb + 8 * lk);
-        acc2[r] = mfma_x3(a, b, acc2[r]);
+        mx_bfrag(sb, r4, b);
+        switch (ch) {  // row tile 4 ch + r4 (the accumulators stay in registers)
+          case 0: acc2[r4] = mfma_x3(a, b, acc2[r4]); break;
+          case 1: acc2[4 + r4] = mfma_x3(a, b, acc2[4 + r4]); break;
+          case 2: acc2[8 + r4] = mfma_x3(a, b, acc2[8 + r4]); break;
+          default: acc2[12 + r4] = mfma_x3(a, b, acc2[12 + r4]); break;
+        }
       }
+      if (sg + 1 < nst) mx_lstore(st, sbuf + (qb ^ 1) * kMxBuf);
+      __syncthreads();
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r)
@@ -951,7 +1019,6 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
         const int pe = 16 * w + 4 * lk + e;
         if (pe < np) Y[(size_t)(p0 + pe) * n + 16 * r + li] = (double)acc2[r][e];
       }
-    __syncthreads();  // sZ is rewritten by the next item
   }
 }
 
