@@ -125,8 +125,9 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
  *                            leaf (exterior entries are not read)
  *   fe_out  n_leaves x K^2   extended data f^e (written)
  *   V_out   n_leaves x K^2   V[f^e] at every leaf node (written)
+ * fe_out must be 16-byte aligned (it is read back in 16-byte pieces).
  * Asynchronous: returns after enqueueing.  Errors: VFX_EINVAL for null
- * pointers, VFX_EHIP if a launch fails.
+ * or misaligned pointers, VFX_EHIP if a launch fails.
  */
 int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
                 double* V_out, void* stream);

@@ -629,59 +629,73 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
 // work item is a tile of <= 64 list-1 pairs of one configuration:
 //   Z = X W_c^T  (pairs x R_c: the source leaf values times the row factor),
 //   Y = Z Q_c^T  (pairs x n),
-// both as FP64 MFMA tile products with the operands staged through LDS in
-// double-buffered K blocks; Z stays in LDS between the two.  Wave w owns the
-// pairs 16w..16w+15 of the tile.  Persistent, XCD-aware item order as in
-// k_gemm (items are configuration-major, so an XCD's L2 holds the factors
-// of the few configurations it works on).
-constexpr int kLrLDX = 64 + 4, kLrLDW = kNearLrMax + 4, kLrLDZ = kNearLrMax + 1;
+// both as FP64 MFMA tile products; Z stays in LDS between the two.  Wave w
+// owns the pairs 16w..16w+15 of the tile.  Phase 1 takes its A operands
+// (the wave's own source rows) straight from memory into registers, with the
+// contraction order permuted so that a lane reads 64 contiguous bytes per
+// block; the factor W_c, shared by the four waves, goes through LDS in
+// double-buffered blocks of 32 source nodes.  Persistent, XCD-aware item
+// order as in k_gemm (items are configuration-major, so an XCD's L2 holds
+// the factors of the few configurations it works on).
+constexpr int kLrKB = 32, kLrLDW = 66, kLrLDZ = kNearLrMax + 1;
 
 // Phase 1 for MT1 = R_c/16 rank tiles (compile-time, so the MFMA sequence
-// has no per-tile branches); leaves Z in sZ[pair][rank].
+// has no per-tile branches); leaves Z in sZ[pair][rank].  MFMA step s of
+// block kb pairs source node 32kb + 8(l/16) + s with lane l, on both sides.
+// sW rows are 66 doubles apart: the two lane groups of a half-wave read rows
+// 8 apart, which then fall into opposite halves of the banks.
 template <int KD, int MT1>
-__device__ __forceinline__ void near_lr_phase1(const double* __restrict__ xsrc, bool a_ok,
-                                               const double* __restrict__ Wc, double* sX, double* sW, double* sZ) {
-  constexpr int KB = 16, LM = kNearLrMax;
+__device__ __forceinline__ void near_lr_phase1(const double* __restrict__ xrow, const double* __restrict__ Wc,
+                                               double* sW, double* sZ) {
+  constexpr int LM = kNearLrMax, NKB = KD / kLrKB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int aj = tid & 63, ak = (tid >> 6) * 4;  // entry aj, k = ak..ak+3
-  const int ba = tid & 63, bk = tid >> 6;        // factor: rank ba, k = bk + 4e
-  const bool b_ok = ba < 16 * MT1;
-  double ra[4], rw[4];
-  auto gload = [&](int kb) {
-    const int k0 = kb * KB;
+  double2 a[2][4], rw[4];
+  auto gload_a = [&](int kb, double2* d) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) rw[e] = b_ok ? Wc[(k0 + bk + 4 * e) * LM + ba] : 0.0;
+    for (int e = 0; e < 4; ++e) d[e] = *(const double2*)(xrow + kLrKB * kb + 2 * e);
   };
-  auto lstore = [&](int buf) {
+  // factor block: 32 rows of 64 ranks, 16-byte pieces q = tid + 256 e
+  auto gload_w = [&](int kb) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sX[(buf * KB + ak + e) * kLrLDX + aj] = ra[e];
+    for (int e = 0; e < 4; ++e) {
+      const int q = tid + 256 * e, row = q >> 5, col = 2 * (q & 31);
+      rw[e] = col < 16 * MT1 ? *(const double2*)(Wc + (size_t)(kLrKB * kb + row) * LM + col) : double2{0, 0};
+    }
+  };
+  auto lstore_w = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sW[(buf * KB + bk + 4 * e) * kLrLDW + ba] = rw[e];
+    for (int e = 0; e < 4; ++e) {
+      const int q = tid + 256 * e, row = q >> 5, col = 2 * (q & 31);
+      *(double2*)(sW + (buf * kLrKB + row) * kLrLDW + col) = rw[e];
+    }
   };
   vfx_d4 acc[MT1];
 #pragma unroll
   for (int r = 0; r < MT1; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
-  constexpr int NKB = KD / KB;
-  gload(0);
-  lstore(0);
+  gload_a(0, a[0]);
+  gload_w(0);
+  __syncthreads();  // the previous item is done with sW and sZ
+  lstore_w(0);
   __syncthreads();
+#pragma unroll
   for (int kb = 0; kb < NKB; ++kb) {
     const int buf = kb & 1;
-    if (kb + 1 < NKB) gload(kb + 1);
+    if (kb + 1 < NKB) {
+      gload_a(kb + 1, a[buf ^ 1]);
+      gload_w(kb + 1);
+    }
+    const double* sb = sW + (buf * kLrKB + 8 * lk) * kLrLDW + li;
 #pragma unroll
-    for (int ks = 0; ks < KB / 4; ++ks) {
-      const int k = 4 * ks + lk;
-      const double a = sX[(buf * KB + k) * kLrLDX + 16 * w + li];
+    for (int s = 0; s < 8; ++s) {
+      const double av = (s & 1) ? a[buf][s >> 1].y : a[buf][s >> 1].x;
       double bv[MT1];
 #pragma unroll
-      for (int r = 0; r < MT1; ++r) bv[r] = sW[(buf * KB + k) * kLrLDW + 16 * r + li];
+      for (int r = 0; r < MT1; ++r) bv[r] = sb[s * kLrLDW + 16 * r];
 #pragma unroll
-      for (int r = 0; r < MT1; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[r], acc[r], 0, 0, 0);
+      for (int r = 0; r < MT1; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[r], acc[r], 0, 0, 0);
     }
-    if (kb + 1 < NKB) lstore(buf ^ 1);
+    if (kb + 1 < NKB) lstore_w(buf ^ 1);
     __syncthreads();
   }
   // Z rows of this wave's pairs: D[lk + 4e][16 r + li]
@@ -701,15 +715,13 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
   X += blockIdx.y * sx;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
   constexpr int LM = kNearLrMax;  // 64
-  constexpr int KB = 16;          // source nodes per phase-1 block
   constexpr int QB = 8;           // rank indices per phase-2 block
   constexpr int NRT = KD / 16;    // output row tiles
-  static_assert(2 * QB * KD <= 2 * KB * (kLrLDX + kLrLDW), "phase-2 staging must fit the phase-1 buffers");
-  __shared__ double sbuf[2 * KB * (kLrLDX + kLrLDW)];
+  static_assert(2 * QB * KD <= 2 * kLrKB * kLrLDW, "phase-2 staging must fit the phase-1 buffer");
+  __shared__ __attribute__((aligned(16))) double sbuf[2 * kLrKB * kLrLDW];
   __shared__ double sZ[64 * kLrLDZ];
-  double* sX = sbuf;                    // [2][KB][kLrLDX]
-  double* sW = sbuf + 2 * KB * kLrLDX;  // [2][KB][kLrLDW]
-  double* sQ = sbuf;                    // [2][QB][KD] (phase 2)
+  double* sW = sbuf;  // [2][kLrKB][kLrLDW] (phase 1)
+  double* sQ = sbuf;  // [2][QB][KD] (phase 2)
   const int nb = gridDim.x, bb = blockIdx.x;
   const int x = bb & 7;
   const int q = nitems >> 3, rr = nitems & 7;
@@ -723,15 +735,15 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
     const int R = lr_R[c];
     const double* Wc = W + (size_t)c * KD * LM;
     const double* Qc = Q + (size_t)c * LM * KD;
-    const int aj = tid & 63;
-    const bool a_ok = aj < np;
-    const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
-    __syncthreads();  // the previous item is done with sbuf and sZ
+    // this lane's A-operand pair (a pair past the tile's end reads the first
+    // pair's row; its results are not stored)
+    const int ent = 16 * w + li;
+    const double* xrow = X + (size_t)src[p0 + (ent < np ? ent : 0)] * KD + 8 * lk;
     switch (R >> 4) {
-      case 1: near_lr_phase1<KD, 1>(xsrc, a_ok, Wc, sX, sW, sZ); break;
-      case 2: near_lr_phase1<KD, 2>(xsrc, a_ok, Wc, sX, sW, sZ); break;
-      case 3: near_lr_phase1<KD, 3>(xsrc, a_ok, Wc, sX, sW, sZ); break;
-      default: near_lr_phase1<KD, 4>(xsrc, a_ok, Wc, sX, sW, sZ); break;
+      case 1: near_lr_phase1<KD, 1>(xrow, Wc, sW, sZ); break;
+      case 2: near_lr_phase1<KD, 2>(xrow, Wc, sW, sZ); break;
+      case 3: near_lr_phase1<KD, 3>(xrow, Wc, sW, sZ); break;
+      default: near_lr_phase1<KD, 4>(xrow, Wc, sW, sZ); break;
     }
     // ---- phase 2: Y = Z Q^T
     // Q block: QB ranks x KD rows; thread tid stages rows tid, tid + 256, ...
