@@ -33,11 +33,13 @@ HBM_PEAK_GBS = 8000.0
 # that dominates it.  The roofline object describes the slowest phase that
 # is a single kernel launch (the others hold several launches, and their
 # event-timed spans include waits for the other stream).
-SINGLE_KERNEL_PHASES = ("extension", "down", "near_lowrank", "near_dense", "far")
+SINGLE_KERNEL_PHASES = ("extension", "down", "near_lowrank", "near_dense", "far", "p2l", "m2p")
 PHASE_KERNEL = {
     "extension": ("k_extension", "// Extension of one cut leaf per work-group"),
     "p2m_up": ("k_up", "// Upward pass without the level-by-level chain."),
-    "m2l_p2l": ("k_m2l_lanes", "// M2L: one lane per list-2 entry"),
+    "m2l": ("k_m2l_lanes", "// M2L: one lane per list-2 entry"),
+    "p2l": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
+    "m2p": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
     "down": ("k_down", "// Downward pass without the level-by-level chain"),
     "near_lowrank": ("k_near_lr", "// Near field in low-rank form"),
     "near_dense": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
@@ -75,7 +77,9 @@ def algorithmic_work(case):
         "extension": (2.0 * nG * nI + ncut * (2 * nG * 144 + 4 * 144 * 12) + ext_targets * (2 * 12 * 12 * K + 2 * 12 * n),
                       8.0 * (nG * nI + nI + ncut * 144 + (L + ext_targets) * n)),
         "p2m_up": (8.0 * P * n * L / 2 + 8.0 * P * P / 2 * n_pairs_ud, 8.0 * L * n + 16.0 * B * P),
-        "m2l_p2l": (8.0 * P * P * N2 + 4.0 * P * n * N4, 16.0 * 2 * B * P + 8.0 * N4 * n),
+        # M2L sums the list-4 products of P2L with the list-2 translations
+        "m2l": (8.0 * P * P * N2, 16.0 * 2 * B * P + 16.0 * N4 * P),
+        "p2l": (4.0 * P * n * N4, 8.0 * L * n + 16.0 * N4 * P),
         "down": (8.0 * P * P / 2 * n_pairs_ud, 16.0 * (B + L) * P),
         # low-rank near field: W (r x n) then Q (n x r) per pair, true ranks;
         # bytes: every leaf's samples once, one n-vector written per pair,
@@ -83,7 +87,10 @@ def algorithmic_work(case):
         "near_lowrank": (float((counts * 4.0 * n * rank)[lr].sum()),
                          8.0 * (L * n + n * n_lr) + 8.0 * 2 * n * 64 * int(lr.sum())),
         "near_dense": (2.0 * n * n * n_dense, 8.0 * (L * n + n * n_dense) + 8.0 * n * n * int((~lr).sum())),
-        "far": (8.0 * P * n * L + (8.0 * P + 40) * n * N3, 8.0 * n * st["n_list1"] + 8.0 * L * n + 16.0 * (L + N3) * P),
+        # list-1 and list-3 sums and L2P; M2P as a table product (2P real
+        # coefficients per list-3 box)
+        "far": (8.0 * P * n * L + n * (st["n_list1"] + N3), 8.0 * n * (st["n_list1"] + N3) + 8.0 * L * n + 16.0 * L * P),
+        "m2p": (2.0 * n * 2 * P * N3, 16.0 * N3 * P + 8.0 * n * N3 + 8.0 * 2 * P * n * 20),
     }
     return work
 

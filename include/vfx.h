@@ -246,16 +246,19 @@ int vfx_graph_destroy(vfx_graph* graph);
  * every vfx_execute records its events (at most 4096 executes are recorded;
  * enabling again restarts the count).  The query synchronises on the last
  * recorded event and returns, averaged over the recorded executes, the
- * milliseconds of eight phases:
+ * milliseconds of ten phases:
  *   ms[0] extension (f^e assembly and the cut-leaf kernel)
- *   ms[1] P2M and the upward pass        ms[2] P2L and M2L
+ *   ms[1] P2M and the upward pass
+ *   ms[2] M2L (with the wait for P2L)
  *   ms[3] downward pass (leaf local expansions)
  *   ms[4] near field, low-rank operators (side stream)
  *   ms[5] near field, dense operators (side stream)
- *   ms[6] far field (near-field reduction, L2P, M2P)   ms[7] total
- * and ms[8] (if n_out >= 9) the number of executes averaged.  Phases on the
- * two streams overlap, so they do not add up to the total.  n_out must be
- * >= 8. */
+ *   ms[6] far field (list-1 and list-3 sums, L2P)   ms[7] total
+ *   ms[8] P2L, list-4 products (side stream)
+ *   ms[9] M2P, list-3 products (side stream)
+ * and ms[10] (if n_out >= 11) the number of executes averaged.  Phases on
+ * the two streams overlap, so they do not add up to the total.  n_out must
+ * be >= 10. */
 int vfx_plan_set_timing(vfx_plan* plan, int enable);
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
 
@@ -283,6 +286,12 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
  *            rank; both zero for configurations applied densely)
  *        22 (`index` ignored): 66 values, the padded rank R (0 = dense) of
  *            each configuration, then its rank
+ *        23: M2P (list 3) GEMM operand of slot `index` (0..35; the slot of
+ *            a box one level finer than the target leaf, centre offset
+ *            (ox, oy) in units of its half side, ((ox+5)/2)*6 + (oy+5)/2),
+ *            rows x n, [k][i], rows as for table 19: row 0 log|z|, rows
+ *            2k and 2k+1 Re z^-k and -Im z^-k (k >= 1), z = node i of the
+ *            leaf minus the box centre in units of the box side
  * VFX_EINVAL if `which`, `index` or `count` does not match. */
 int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count);
 /* Interaction list `which` (1..4) of a plan as CSR arrays (host):

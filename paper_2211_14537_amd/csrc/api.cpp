@@ -371,7 +371,7 @@ int vfx_plan_set_timing(vfx_plan* plan, int enable) {
 }
 
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
-  constexpr int NP = 8;  // phases
+  constexpr int NP = 10;  // phases
   if (!plan || !ms || n_out < NP) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
   vfx::Plan& p = plan->p;
   constexpr int NE = vfx::Plan::kEvents;
@@ -379,9 +379,9 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
   hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * NE + 9]);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
   // phase k runs from event a[k] to event b[k]
-  static const int a_[NP] = {0, 1, 2, 3, 5, 6, 8, 0};
-  static const int b_[NP] = {1, 2, 3, 4, 6, 7, 9, 9};
-  double acc[NP] = {0, 0, 0, 0, 0, 0, 0, 0};
+  static const int a_[NP] = {0, 1, 2, 3, 5, 6, 8, 0, 10, 11};
+  static const int b_[NP] = {1, 2, 3, 4, 6, 7, 9, 9, 5, 12};
+  double acc[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < p.n_timed; ++r) {
     const hipEvent_t* ev = &p.ev[(size_t)r * NE];
     for (int k = 0; k < NP; ++k) {
@@ -457,6 +457,11 @@ int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64
       size = (int64_t)rk.size();
       break;
     }
+    case 23:
+      if (index < 0 || index >= vfx::kP2LSlots) break;
+      src = T.m2p_gemm.data() + (size_t)index * T.p2l_rows * n;
+      size = (int64_t)T.p2l_rows * n;
+      break;
     case 9: case 10: case 11: case 12: case 13: case 14: case 15: case 16: case 17: case 18: case 19: {
       const std::vector<double>* v[] = {&T.pas_m2l, &T.m2l_tpow, &T.m2l_tneg, &T.m2l_logd, &T.pas_m2m,
                                         &T.m2m_in,  &T.m2m_out,  &T.pas_l2l,  &T.l2l_in,   &T.l2l_out,

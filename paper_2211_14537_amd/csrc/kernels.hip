@@ -36,6 +36,7 @@ constexpr int kMaxG = 136;
 constexpr int kMaxK = 16;
 constexpr int kMaxKb = 16;
 constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+constexpr double kLn2 = 0.69314718055994530941723212145817657;
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -493,14 +494,15 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
 }
 
 // -------------------------------------------------------------------------
-// Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M).
+// Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M, M2P).
 // Entries (pairs) are grouped by table configuration c; a work-group takes a
 // tile of <= TE entries (64 or 16) of one configuration and a block of MTB
 // row tiles (16 table rows each) and computes, for every entry e,
 //   Y[e][row] = sum_k A_c[k][row] X[src(e)][k]
 // (the table applied to the source leaf's K^2 values).
 //   A: [c][k][row], R = 16*MT rows (rows fastest, MT a multiple of MTB);
-//   X: [src][k]; Y: [e][row].
+//   X: [src][k] with row stride ldx, values k >= kx taken as zero (M2P reads
+//   the 2P coefficients of a multipole); Y: [e][row].
 // The K dimension is processed in blocks of 16 with both operands staged in
 // double-buffered LDS: the global loads of block kb+1 are in flight while the
 // waves run their MFMAs on block kb.  With TE = 64, wave w owns entries
@@ -521,7 +523,7 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
                                               const double* __restrict__ A, const double* __restrict__ X,
                                               double* __restrict__ Y, int P2, double root_size,
                                               const int* __restrict__ leaf_box, const int* __restrict__ box_level,
-                                              long sx, long sy) {
+                                              long sx, long sy, int ldx, int kx) {
   static_assert(TE == 64 || MTB % 4 == 0, "TE = 16 splits the row tiles over the four waves");
   X += blockIdx.y * sx;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
@@ -557,12 +559,12 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
   // table block KB x LDB: thread tid stages the values tid, tid + 256, ...
   // (v = k * LDB + row), so consecutive lanes touch consecutive rows
   const bool a_ok = aj < np;
-  const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * KD;
+  const double* xsrc = X + (size_t)(a_ok ? src[p0 + aj] : 0) * ldx;
   double ra[AE], rbv[BE];
   auto gload = [&](int kb) {
     const int k0 = kb * KB;
 #pragma unroll
-    for (int e = 0; e < AE; ++e) ra[e] = a_ok ? xsrc[k0 + ak + e] : 0.0;
+    for (int e = 0; e < AE; ++e) ra[e] = (a_ok && k0 + ak + e < kx) ? xsrc[k0 + ak + e] : 0.0;
 #pragma unroll
     for (int e = 0; e < BE; ++e) {
       const int v = tid + 256 * e, bk = v / LDB, br = v - bk * LDB;
@@ -1256,78 +1258,111 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
 }
 
 // -------------------------------------------------------------------------
-// Far field and the near-field reduction, one work-group per leaf, thread i =
-// node i: L2P of the leaf's full local expansion by Horner in the scaled node
-// position, M2P for list 3 by Horner in h_w/z, the list-1 sums of the
-// near-field GEMM (in list order, deterministic) and the log(h) a_0 terms
-// of the near field.  The expansions used are the same for the whole
-// work-group (uniform addresses: scalar loads and SGPR operands).
-template <int PM, bool EXACT>
-__global__ void __launch_bounds__(256) k_far(int K, int Prt, double root_size, const int* __restrict__ leaf_box,
-                                             const int* __restrict__ box_level, const double* __restrict__ box_cx,
-                                             const double* __restrict__ box_cy, const double* __restrict__ t,
-                                             const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
-                                             const double2* __restrict__ locf, const double2* __restrict__ mpole,
-                                             const int* __restrict__ l1_ptr, const int* __restrict__ l1_srcbox,
-                                             const int* __restrict__ l1_slot, const double* __restrict__ Y,
-                                             double* __restrict__ V, long slf, long smp, long sny, long sv) {
-  const int P = EXACT ? PM : Prt;
-  locf += blockIdx.y * slf;  // right-hand side blockIdx.y
+// Far field and the near-field reduction, one wave per leaf; lane l holds
+// the nodes l + 64j, j < NPL (NPL = ceil(K^2/64)): L2P of the leaf's full
+// local expansion by Horner in the scaled node position, the list-1 sums of
+// the near-field products and the list-3 sums of the M2P products (in list
+// order, deterministic), and the log terms: log(h) a_0 of each list-1 source
+// and log(h/2) a_0 of each list-3 box.  Every per-leaf quantity (the local
+// expansion, the list slots) comes in with one vector load, lane k holding
+// item k, and is broadcast with readlane, so no step waits on a chain of
+// scalar loads.  One wave per leaf keeps the whole grid resident at once.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)u, l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int PM, bool EXACT, int NPL>
+__global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, const int* __restrict__ leaf_box,
+                                            const int* __restrict__ box_level, const double* __restrict__ t,
+                                            const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
+                                            const int* __restrict__ l3_slot, const double* __restrict__ Y3,
+                                            const double2* __restrict__ locf, const double2* __restrict__ mpole,
+                                            const int* __restrict__ l1_ptr, const int* __restrict__ l1_srcbox,
+                                            const int* __restrict__ l1_slot, const double* __restrict__ Y,
+                                            double* __restrict__ V, long slf, long smp, long sny, long sy3, long sv) {
+  const int P = EXACT ? PM : Prt;  // <= 64
+  locf += blockIdx.y * slf;        // right-hand side blockIdx.y
   mpole += blockIdx.y * smp;
   Y += blockIdx.y * sny;
+  Y3 += blockIdx.y * sy3;
   V += blockIdx.y * sv;
   const int n = K * K;
   const int leaf = blockIdx.x;
-  const int i = threadIdx.x;
+  const int lane = threadIdx.x;
   const int b = leaf_box[leaf];
   const int lev = box_level[b];
   const double h = box_side(root_size, lev);
-  const int ii = i < n ? i : 0;
-  const double tx = 0.5 * t[ii / K], ty = 0.5 * t[ii % K];
-  // near field: list-1 partial sums and the log terms (a leaf has at most
-  // one list-1 entry per configuration)
+  // per-lane items: list-1 entry `lane` (at most one per configuration,
+  // fewer than 64), list-3 entry `lane` (at most 20), local coefficient `lane`
   const int e0 = l1_ptr[leaf], n1 = l1_ptr[leaf + 1] - e0;
-  double yn = 0.0, lg = 0.0;
-#pragma unroll 4
-  for (int e = 0; e < n1; ++e) {
-    yn += Y[(size_t)l1_slot[e0 + e] * n + ii];
-    lg += mpole[(size_t)l1_srcbox[e0 + e] * P].x;
+  const int f0 = l3_ptr[leaf], n3 = l3_ptr[leaf + 1] - f0;
+  const int my_slot = lane < n1 ? l1_slot[e0 + lane] : 0;
+  const double my_a0 = lane < n1 ? mpole[(size_t)l1_srcbox[e0 + lane] * P].x : 0.0;
+  const int my_slot3 = lane < n3 ? l3_slot[f0 + lane] : 0;
+  const double my_b0 = lane < n3 ? mpole[(size_t)l3_src[f0 + lane] * P].x : 0.0;
+  const double2 my_c = (lev >= 2 && lane < P) ? locf[(size_t)leaf * P + lane] : double2{0.0, 0.0};
+  int node[NPL];
+  double tx[NPL], ty[NPL], acc[NPL];
+#pragma unroll
+  for (int j = 0; j < NPL; ++j) {
+    node[j] = lane + 64 * j < n ? lane + 64 * j : 0;
+    tx[j] = 0.5 * t[node[j] / K];
+    ty[j] = 0.5 * t[node[j] % K];
   }
-  double acc = h * h * yn + log(h) * lg;
+  // near field (list 1) and M2P (list 3) sums, log terms
+  {
+    double yn[NPL], y3[NPL], lg = 0.0, lg3 = 0.0;
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) yn[j] = y3[j] = 0.0;
+#pragma unroll 4
+    for (int e = 0; e < n1; ++e) {
+      const double* y = Y + (size_t)__builtin_amdgcn_readlane(my_slot, e) * n;
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
+      lg += readlane_d(my_a0, e);
+    }
+#pragma unroll 4
+    for (int q = 0; q < n3; ++q) {
+      const double* y = Y3 + (size_t)__builtin_amdgcn_readlane(my_slot3, q) * n;
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) y3[j] += y[node[j]];
+      lg3 += readlane_d(my_b0, q);
+    }
+    const double lh = log(h);
+    const double lt = lh * lg + (lh - kLn2) * lg3;
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) acc[j] = h * h * yn[j] + y3[j] + lt;
+  }
   // L2P
   if (lev >= 2) {
-    const double2* c = locf + (size_t)leaf * P;
-    double2 u = c[P - 1];
+    double ur[NPL], ui[NPL];
+    {
+      const double cx = readlane_d(my_c.x, P - 1), cy = readlane_d(my_c.y, P - 1);
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) {
+        ur[j] = cx;
+        ui[j] = cy;
+      }
+    }
 #pragma unroll
     for (int l = P - 2; l >= 0; --l) {
-      const double ur = u.x * tx - u.y * ty, ui = u.x * ty + u.y * tx;
-      u = make_double2(ur + c[l].x, ui + c[l].y);
-    }
-    acc += u.x;
-  }
-  // M2P for list 3
-  const double xi = box_cx[b] + h * tx;
-  const double yi = box_cy[b] + h * ty;
-  const int f0 = l3_ptr[leaf], n3 = l3_ptr[leaf + 1] - f0;
-  for (int j = 0; j < n3; ++j) {
-    const int w = l3_src[f0 + j];
-    const double hw = box_side(root_size, box_level[w]);
-    const double2* a = mpole + (size_t)w * P;
-    const double zx = xi - box_cx[w], zy = yi - box_cy[w];
-    const double r2 = zx * zx + zy * zy;
-    // zeta = hw / z
-    const double iv = hw / r2;
-    const double zr = zx * iv, zi = -zy * iv;
-    double sr = 0.0, si = 0.0;  // Horner: sum_{k>=1} a_k zeta^k
+      const double cx = readlane_d(my_c.x, l), cy = readlane_d(my_c.y, l);
 #pragma unroll
-    for (int kk = P - 1; kk >= 1; --kk) {
-      const double ar = sr + a[kk].x, ai = si + a[kk].y;
-      sr = ar * zr - ai * zi;
-      si = ar * zi + ai * zr;
+      for (int j = 0; j < NPL; ++j) {
+        const double r = ur[j] * tx[j] - ui[j] * ty[j] + cx;
+        ui[j] = ur[j] * ty[j] + ui[j] * tx[j] + cy;
+        ur[j] = r;
+      }
     }
-    acc += a[0].x * 0.5 * log(r2) + sr;
+#pragma unroll
+    for (int j = 0; j < NPL; ++j) acc[j] += ur[j];
   }
-  if (i < n) V[(size_t)leaf * n + i] = kInv2Pi * acc;
+#pragma unroll
+  for (int j = 0; j < NPL; ++j)
+    if (lane + 64 * j < n) V[(size_t)leaf * n + lane + 64 * j] = kInv2Pi * acc[j];
 }
 
 // -------------------------------------------------------------------------
@@ -1449,6 +1484,7 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.lr_Qb, T.lr_Qb);
   UP(D.self_Ab, T.self_Ab);
   UP(D.p2l_gemm, T.p2l_gemm);
+  UP(D.m2p_gemm, T.m2p_gemm);
   UP(D.p2m_gemm, T.p2m_gemm);
   UP(D.pas_m2l, T.pas_m2l);
   UP(D.pas_m2l_t, T.pas_m2l_t);
@@ -1491,7 +1527,7 @@ void free_tables_device(Context* c) {
   DeviceTables& D = c->D;
   void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,   D.A,
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
-                  D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
+                  D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2p_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
                   D.lr_R,     D.lr_W,     D.lr_Q,     D.lr_Wb,    D.lr_Qb,    D.self_Ab};
   for (void* p : ptrs)
@@ -1508,11 +1544,11 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   const Tables& T = p->ctx->T;
   const size_t P = T.p + 1, R = (size_t)nrhs;
   if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
-  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs};
+  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y};
   for (void* q : old)
     if (q) (void)hipFree(q);
   D.mpole = D.local = D.up_part = D.locf = nullptr;
-  D.near_y = D.p2l_y = nullptr;
+  D.near_y = D.p2l_y = D.m2p_y = nullptr;
   D.xs = nullptr;
   D.cap = 0;
   VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P * R));
@@ -1520,6 +1556,7 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   VFX_HIP(hipMemset(D.local, 0, sizeof(double2) * (size_t)H.B * P * R));
   if (!H.np_src.empty()) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n * R));
   if (!H.p4_src.empty()) VFX_HIP(hipMalloc((void**)&D.p2l_y, sizeof(double) * H.p4_src.size() * T.p2l_rows * R));
+  if (!H.p3_src.empty()) VFX_HIP(hipMalloc((void**)&D.m2p_y, sizeof(double) * H.p3_src.size() * T.n * R));
   if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P * R));
   VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P * R));
   if (H.precision == 1) VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 3 * (size_t)H.L * T.n * R));
@@ -1585,6 +1622,11 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.t4_cfg, H.t4_cfg);
   UP(D.t4_first, H.t4_first);
   UP(D.t4_count, H.t4_count);
+  UP(D.p3_src, H.p3_src);
+  UP(D.l3_slot, H.l3_slot);
+  UP(D.t3_cfg, H.t3_cfg);
+  UP(D.t3_first, H.t3_first);
+  UP(D.t3_count, H.t3_count);
   UP(D.t0_cfg, H.t0_cfg);
   UP(D.t0_first, H.t0_first);
   UP(D.t0_count, H.t0_count);
@@ -1611,6 +1653,8 @@ int upload_plan(Plan* p, std::string& err) {
   VFX_HIP(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
   VFX_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
   VFX_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
+  VFX_HIP(hipEventCreateWithFlags(&p->p2l_ev, hipEventDisableTiming));
+  VFX_HIP(hipEventCreateWithFlags(&p->up_ev, hipEventDisableTiming));
   D.ready = true;
   return VFX_OK;
 }
@@ -1628,7 +1672,8 @@ void free_plan_device(Plan* p) {
                   D.up_pos,    D.up_split,   D.up_grp,   D.up_part,  D.anc_ptr,  D.anc,
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
                   D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg, D.fac_ws,
-                  D.ml_first,  D.ml_count,   D.xs};
+                  D.ml_first,  D.ml_count,   D.xs,       D.p3_src,   D.l3_slot,  D.t3_cfg,   D.t3_first,
+                  D.t3_count,  D.m2p_y};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -1639,19 +1684,22 @@ void free_plan_device(Plan* p) {
   if (p->side) (void)hipStreamSynchronize(p->side);
   if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   if (p->join_ev) (void)hipEventDestroy(p->join_ev);
+  if (p->p2l_ev) (void)hipEventDestroy(p->p2l_ev);
+  if (p->up_ev) (void)hipEventDestroy(p->up_ev);
   if (p->side) (void)hipStreamDestroy(p->side);
-  p->fork_ev = p->join_ev = nullptr;
+  p->fork_ev = p->join_ev = p->p2l_ev = p->up_ev = nullptr;
   p->side = nullptr;
 }
 
 template <int KD, int EPI, int TE, int MTB>
 static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, const int* count, const int* src,
                         const double* A, const double* X, double* Y, int P2, double root, const int* leaf_box,
-                        const int* box_level, hipStream_t s, int max_wgs, unsigned R, long sx, long sy) {
+                        const int* box_level, hipStream_t s, int max_wgs, unsigned R, long sx, long sy,
+                        int ldx = KD, int kx = KD) {
   const int items = ntiles * (MT / MTB);
   const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
   hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src,
-                     A, X, Y, P2, root, leaf_box, box_level, sx, sy);
+                     A, X, Y, P2, root, leaf_box, box_level, sx, sy, ldx, kx);
 }
 
 // Dense near-field tables: MT = n/16 row tiles (1, 4, 9 or 16 for K = 4, 8,
@@ -1703,6 +1751,33 @@ static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int*
 #undef VFX_EXP_CASE
 }
 
+// M2P tables: contraction over the 2P real coefficients of a multipole
+// (padded to KD = 64 or 128), n = K^2 rows in blocks as for the dense near
+// field.
+static void m2p_gemm(int n, int kd, int P2, int ntiles, const int* cfg, const int* first, const int* count,
+                     const int* src, const double* A, const double* X, double* Y, hipStream_t s, unsigned R, long sx,
+                     long sy) {
+  if (ntiles <= 0) return;
+  const int MT = n / 16;
+#define VFX_M2P(KDV, MTBV)                                                                                        \
+  launch_gemm<KDV, 0, 64, MTBV>(ntiles, MT, cfg, first, count, src, A, X, Y, 0, 0, nullptr, nullptr, s, 0, R, sx, \
+                                sy, P2, P2)
+#define VFX_M2P_N(KDV)            \
+  switch (n) {                    \
+    case 16: VFX_M2P(KDV, 1); break;  \
+    case 64: VFX_M2P(KDV, 4); break;  \
+    case 144: VFX_M2P(KDV, 9); break; \
+    default: VFX_M2P(KDV, 4); break;  \
+  }
+  if (kd == 64) {
+    VFX_M2P_N(64)
+  } else {
+    VFX_M2P_N(128)
+  }
+#undef VFX_M2P_N
+#undef VFX_M2P
+}
+
 constexpr int kNearWgs = 512;
 
 int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut, double* fe, double* V,
@@ -1732,6 +1807,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   // per-right-hand-side strides (elements) of the batched buffers
   const long sFL = (long)L * n, sFC = (long)H.ncut * T.nX, sMP = (long)H.B * P;
   const long sNY = (long)H.np_src.size() * n, sPL = (long)H.p4_src.size() * T.p2l_rows;
+  const long sM3 = (long)H.p3_src.size() * n;
   const long sUP = (long)H.up_slots * P, sLF = (long)L * P;
   const unsigned R = (unsigned)nrhs;
     constexpr int kMaxTimed = 4096;
@@ -1776,24 +1852,30 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
                        f_cut, fe, nrhs, sFC, sFL);
   VFX_HIP(hipGetLastError());
   MARK(1, s);
-  // fork: near field on the side stream, concurrent with P2M, the upward
-  // pass, P2L/M2L and the downward pass on the caller's stream.  Its grids
-  // are bounded (about two work-groups per CU, looping over the tiles).
+  // fork: P2L and the near field on the side stream, concurrent with P2M,
+  // the upward pass, M2L and the downward pass on the caller's stream.  The
+  // near-field grids are bounded (about two work-groups per CU, looping over
+  // the tiles).
   VFX_HIP(hipEventRecord(p->fork_ev, s));
   VFX_HIP(hipStreamWaitEvent(p->side, p->fork_ev, 0));
+  // P2L first on the side stream (it needs only f^e; M2L on the caller's
+  // stream waits for it), then the near field
+  MARK(10, p->side);
+  if (H.nlev > 2)
+    expansion_gemm<0, 64>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src,
+                          DT.p2l_gemm, fe, D.p2l_y, p->side, R, sFL, sPL);
+  VFX_HIP(hipGetLastError());
+  VFX_HIP(hipEventRecord(p->p2l_ev, p->side));
   MARK(5, p->side);
   if (!H.nl_cfg.empty()) {
     const int items = (int)H.nl_cfg.size();
     hipLaunchKernelGGL(k_near_lr<256>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
                        D.nl_cfg, D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y, sFL, sNY);
   }
-  MARK(6, p->side);
-  near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
-            p->tune.near_wgs, p->tune.dense_mtb, R, sFL, sNY);
+  const long total = (long)L * n;
   if (H.precision == 1) {
     // pairs in mixed precision: bf16 slices of the leaf data, then the
-    // low-rank and the dense (self) kernels
-    const long total = (long)L * n;
+    // low-rank kernel (here) and the dense one for the self operator (below)
     hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192), R), dim3(256), 0, p->side,
                        total, fe, D.xs);
     if (!H.ml_cfg.empty()) {
@@ -1802,16 +1884,19 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
                          1, D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs, total,
                          D.near_y, sNY);
     }
-    if (!H.mt_cfg.empty()) {
-      const int items = 4 * (int)H.mt_cfg.size();
-      hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
-                         4, D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
-                         D.near_y, sNY);
-    }
+  }
+  VFX_HIP(hipGetLastError());
+  MARK(6, p->side);
+  near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
+            p->tune.near_wgs, p->tune.dense_mtb, R, sFL, sNY);
+  if (H.precision == 1 && !H.mt_cfg.empty()) {
+    const int items = 4 * (int)H.mt_cfg.size();
+    hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items, 4,
+                       D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
+                       D.near_y, sNY);
   }
   VFX_HIP(hipGetLastError());
   MARK(7, p->side);
-  VFX_HIP(hipEventRecord(p->join_ev, p->side));
   // multipoles of the leaves
   expansion_gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
                         DT.p2m_gemm, fe, (double*)D.mpole, s, R, sFL, 2 * sMP, 2 * P, T.root_size, D.leaf_box,
@@ -1840,10 +1925,20 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
                          D.mpole, sUP, sMP);
   }
   VFX_HIP(hipGetLastError());
+  VFX_HIP(hipEventRecord(p->up_ev, s));  // multipoles complete
   MARK(2, s);
+  // M2P for list 3 on the side stream, after its near-field work and once
+  // the multipoles are complete (enqueued here, after up_ev is recorded, so
+  // the wait refers to this execute's upward pass)
+  VFX_HIP(hipStreamWaitEvent(p->side, p->up_ev, 0));
+  MARK(11, p->side);
+  m2p_gemm(n, T.p2l_rows, 2 * P, (int)H.t3_cfg.size(), D.t3_cfg, D.t3_first, D.t3_count, D.p3_src, DT.m2p_gemm,
+           (const double*)D.mpole, D.m2p_y, p->side, R, 2 * sMP, sM3);
+  VFX_HIP(hipGetLastError());
+  MARK(12, p->side);
+  VFX_HIP(hipEventRecord(p->join_ev, p->side));
   if (H.nlev > 2) {
-    expansion_gemm<0, 64>(n, (int)H.t4_cfg.size(), T.p2l_rows / 16, D.t4_cfg, D.t4_first, D.t4_count, D.p4_src,
-                          DT.p2l_gemm, fe, D.p2l_y, s, R, sFL, sPL);
+    VFX_HIP(hipStreamWaitEvent(s, p->p2l_ev, 0));  // list-4 products from the side stream
     const int ng = (int)H.m2l_grp.size() - 1;
     if (ng > 0) {
 #define VFX_M2L(PMV)                                                                                             \
@@ -1897,20 +1992,30 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(8, s);
-#define VFX_FAR(PMV, EX)                                                                                       \
-  hipLaunchKernelGGL((k_far<PMV, EX>), dim3(L, R), dim3(n < 64 ? 64 : n), 0, s, T.K, P, T.root_size,          \
-                     D.leaf_box, D.box_level, D.box_cx, D.box_cy, DT.t, D.l3_ptr, D.l3_src, D.locf, D.mpole,     \
-                     D.l1_ptr, D.l1_srcbox, D.l1_slot, D.near_y, V, sLF, sMP, sNY, sFL)
-  if (P == 21)
-    VFX_FAR(21, true);
-  else if (P == 25)
-    VFX_FAR(25, true);
-  else if (P == 31)
-    VFX_FAR(31, true);
-  else if (P == 41)
-    VFX_FAR(41, true);
-  else
-    VFX_FAR(64, false);
+#define VFX_FAR(PMV, EX, NPLV)                                                                                 \
+  hipLaunchKernelGGL((k_far<PMV, EX, NPLV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,          \
+                     D.box_level, DT.t, D.l3_ptr, D.l3_src, D.l3_slot, D.m2p_y, D.locf, D.mpole, D.l1_ptr,         \
+                     D.l1_srcbox, D.l1_slot, D.near_y, V, sLF, sMP, sNY, sM3, sFL)
+#define VFX_FAR_N(PMV, EX)  \
+  if (npl == 4)             \
+    VFX_FAR(PMV, EX, 4);    \
+  else if (npl == 3)        \
+    VFX_FAR(PMV, EX, 3);    \
+  else                      \
+    VFX_FAR(PMV, EX, 1);
+  const int npl = (n + 63) / 64;  // 1, 3 or 4 for K = 4, 8, 12, 16
+  if (P == 21) {
+    VFX_FAR_N(21, true)
+  } else if (P == 25) {
+    VFX_FAR_N(25, true)
+  } else if (P == 31) {
+    VFX_FAR_N(31, true)
+  } else if (P == 41) {
+    VFX_FAR_N(41, true)
+  } else {
+    VFX_FAR_N(64, false)
+  }
+#undef VFX_FAR_N
 #undef VFX_FAR
   VFX_HIP(hipGetLastError());
   MARK(9, s);

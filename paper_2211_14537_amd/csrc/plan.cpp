@@ -12,6 +12,7 @@
 // cut square taking precedence on ties; the extension restriction forbids a
 // coarser leaf in such a list.
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cstring>
 #include <unordered_map>
@@ -237,7 +238,7 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
   H.l1_ptr.assign(L + 1, 0);
   H.l3_ptr.assign(L + 1, 0);
   std::vector<std::vector<std::pair<int, int>>> l1(L);
-  std::vector<std::vector<int>> l3(L);
+  std::vector<std::vector<std::pair<int, int>>> l3(L);
   for (int leaf = 0; leaf < L; ++leaf) {
     const int b = H.leaf_box[leaf];
     const int l = H.box_level[b], x = H.box_ix[b], y = H.box_iy[b];
@@ -263,7 +264,12 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
                 const int ox4 = (2 * kx + 1) - 2 * (2 * x + 1), oy4 = (2 * ky + 1) - 2 * (2 * y + 1);
                 l1[leaf].push_back({H.box_leaf[ch], 21 + near_config_fine_index(ox4, oy4)});
               } else {
-                l3[leaf].push_back(ch);
+                const int ox = (2 * kx + 1) - 2 * (2 * x + 1), oy = (2 * ky + 1) - 2 * (2 * y + 1);
+                if (std::max(std::abs(ox), std::abs(oy)) != 5) {
+                  err = "internal: bad list-3 configuration";
+                  return VFX_EINVAL;
+                }
+                l3[leaf].push_back({ch, ((ox + 5) / 2) * 6 + (oy + 5) / 2});
               }
             }
           }
@@ -293,7 +299,10 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
       H.l1_cfg.push_back(pr.second);
     }
     H.l3_ptr[leaf + 1] = H.l3_ptr[leaf] + (int)l3[leaf].size();
-    for (int s : l3[leaf]) H.l3_src.push_back(s);
+    for (auto& pr : l3[leaf]) {
+      H.l3_src.push_back(pr.first);
+      H.l3_cfg.push_back(pr.second);
+    }
   }
   // ---- list-1 pairs grouped by configuration -----------------------------
   for (int leaf = 0; leaf < L; ++leaf)
@@ -455,6 +464,27 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         H.t4_cfg.push_back(c);
         H.t4_first.push_back(f);
         H.t4_count.push_back(std::min(64, cnt[c + 1] - f));
+      }
+  }
+  // ---- list-3 entries grouped by M2P slot --------------------------------
+  {
+    const int N3 = H.l3_ptr[L];
+    std::vector<int> cnt(kP2LSlots + 1, 0);
+    for (int e = 0; e < N3; ++e) cnt[H.l3_cfg[e] + 1]++;
+    for (int c = 0; c < kP2LSlots; ++c) cnt[c + 1] += cnt[c];
+    H.p3_src.assign(N3, 0);
+    H.l3_slot.assign(N3, 0);
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (int e = 0; e < N3; ++e) {
+      const int s = pos[H.l3_cfg[e]]++;
+      H.p3_src[s] = H.l3_src[e];
+      H.l3_slot[e] = s;
+    }
+    for (int c = 0; c < kP2LSlots; ++c)
+      for (int f = cnt[c]; f < cnt[c + 1]; f += 64) {
+        H.t3_cfg.push_back(c);
+        H.t3_first.push_back(f);
+        H.t3_count.push_back(std::min(64, cnt[c + 1] - f));
       }
   }
   // P2M: every leaf, one configuration

@@ -772,6 +772,33 @@ static void build_pascal(Tables& T) {
       T.p2m_gemm[(size_t)j * R + 2 * k] = T.p2m[2 * ((size_t)k * n + j)];
       T.p2m_gemm[(size_t)j * R + 2 * k + 1] = T.p2m[2 * ((size_t)k * n + j) + 1];
     }
+  // M2P (list 3) as a real GEMM operand.  A list-3 box w of a leaf b in a
+  // level-restricted tree is a child of a colleague of b that does not touch
+  // b: one level finer, centre offset (ox, oy) h_w/2 with odd ox, oy in
+  // {-5..5} and max(|ox|,|oy|) = 5 (20 of the 36 slots of the P2L grid).
+  // In units of h_w, node i of b sits at z_i = (t_a - ox/2, t_b - oy/2) from
+  // the centre of w, and the scaled expansion of w gives there
+  //   Re sum_{k>=1} a_k z_i^-k + a_0 log|z_i| + a_0 log h_w,
+  // so column 2k of the table holds Re z^-k, column 2k+1 -Im z^-k (k >= 1),
+  // column 0 log|z| (the a_0 log h_w part is added per leaf).
+  // Layout [slot][k][i], k < p2l_rows (zero past 2P), i < n.
+  T.m2p_gemm.assign((size_t)kP2LSlots * R * n, 0.0);
+  for (int slot = 0; slot < kP2LSlots; ++slot) {
+    const int ox = 2 * (slot / 6) - 5, oy = 2 * (slot % 6) - 5;
+    if (std::abs(ox) != 5 && std::abs(oy) != 5) continue;
+    double* Ts = &T.m2p_gemm[(size_t)slot * R * n];
+    for (int i = 0; i < n; ++i) {
+      const std::complex<long double> z((long double)T.t[i / T.K] - 0.5L * ox, (long double)T.t[i % T.K] - 0.5L * oy);
+      const std::complex<long double> iz = 1.0L / z;
+      Ts[i] = (double)std::log(std::abs(z));
+      std::complex<long double> zk = 1.0L;
+      for (int k = 1; k < P; ++k) {
+        zk *= iz;
+        Ts[(size_t)(2 * k) * n + i] = (double)zk.real();
+        Ts[(size_t)(2 * k + 1) * n + i] = (double)-zk.imag();
+      }
+    }
+  }
 }
 
 void build_tables(Tables& T) {

@@ -32,6 +32,9 @@ constexpr int kM2LSlots = 49;
 // in units h/2, odd values in {-5..5} with max(|ox|,|oy|) = 5; index
 // ((ox+5)/2)*6 + (oy+5)/2.
 constexpr int kP2LSlots = 36;
+// M2P (list 3): a box one level finer than the target leaf, centre offset
+// in units of its own half side, odd values in {-5..5} with
+// max(|ox|,|oy|) = 5; the same 36-slot index ((ox+5)/2)*6 + (oy+5)/2.
 
 int near_config_coarse_index(int ox2, int oy2);  // -1 if invalid
 int near_config_fine_index(int ox4, int oy4);
@@ -83,6 +86,8 @@ struct Tables {
   std::vector<double> p2l_gemm;
   // P2M as a real GEMM operand: [j][row], rows as for P2L
   std::vector<double> p2m_gemm;
+  // M2P (list 3) as a real GEMM operand: [slot][k][i], k < p2l_rows
+  std::vector<double> m2p_gemm;
 };
 
 // Host precompute (quadrature.cpp, stencil.cpp)
@@ -107,7 +112,7 @@ struct DeviceTables {
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
-  double* p2m_gemm = nullptr;
+  double *p2m_gemm = nullptr, *m2p_gemm = nullptr;
   double *pas_m2l_t = nullptr, *pas_m2m_t = nullptr, *pas_l2l_t = nullptr;
   double2 *m2l_tpow = nullptr, *m2l_tneg = nullptr, *m2m_in = nullptr, *m2m_out = nullptr, *l2l_in = nullptr,
           *l2l_out = nullptr;
@@ -132,7 +137,7 @@ struct HostPlan {
   std::vector<int> l2_tgt;                   // target box of each list-2 entry
   std::vector<int> m2l_grp;                  // groups of consecutive boxes (level >= 2):
                                              // <= 64 list-2 entries, <= 8 boxes
-  std::vector<int> l3_ptr, l3_src;           // per leaf (source boxes)
+  std::vector<int> l3_ptr, l3_src, l3_cfg;   // per leaf (source boxes, M2P slot)
   // direct upward pass: non-leaf boxes at level >= 2, their leaf-descendant
   // pairs, wave groups {pos0, pos1, e0, e1, slot} and split boxes
   // {box, slot0, nslots}
@@ -152,6 +157,8 @@ struct HostPlan {
   int precision = 0, mixed_min_level = 0;
   // list-4 entries regrouped by P2L slot, the same way
   std::vector<int> p4_src, l4_slot, t4_cfg, t4_first, t4_count;
+  // list-3 entries regrouped by M2P slot, the same way
+  std::vector<int> p3_src, l3_slot, t3_cfg, t3_first, t3_count;
   // P2M over all leaves as one GEMM configuration
   std::vector<int> leaf_ids, t0_cfg, t0_first, t0_count;
   std::vector<int> cut_leaf;                 // ncut
@@ -193,6 +200,8 @@ struct DevicePlan {
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
   double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
+  int *p3_src = nullptr, *l3_slot = nullptr, *t3_cfg = nullptr, *t3_first = nullptr, *t3_count = nullptr;
+  double* m2p_y = nullptr;   // per-entry M2P values at the target nodes, n_list3 x n
   int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
   double* ext_geo = nullptr;
   uint16_t* pinv_idx = nullptr;
@@ -205,12 +214,16 @@ struct Plan {
   Context* ctx = nullptr;
   HostPlan H;
   DevicePlan D;
-  // the near-field GEMM runs on a side stream (default priority), forked
-  // after the extension and joined before the far-field kernel
+  // P2L, the near field and M2P run on a side stream (default priority),
+  // forked after the extension; M2L waits for P2L (p2l_ev), the far-field
+  // kernel for the whole side stream (join_ev)
   hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr, p2l_ev = nullptr;
+  // the side stream's M2P waits for the multipoles (up_ev, after the upward
+  // pass on the caller's stream)
+  hipEvent_t up_ev = nullptr;
   // per-phase timing: one set of kEvents events per timed execute
-  static constexpr int kEvents = 10;
+  static constexpr int kEvents = 13;
   // launch parameters chosen by vfx_plan_autotune
   struct Tune {
     int near_wgs = 512;  // work-group cap of the persistent near-field kernels

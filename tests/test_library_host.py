@@ -9,6 +9,8 @@
   (every source reached exactly once, through the near field or exactly one
   far-field path);
 * its extension lists equal the oracle's;
+* its list-3 (M2P) operands reproduce a point source exactly, and list-3
+  boxes sit where those operands assume;
 * invalid input is rejected with the documented status codes.
 """
 import os
@@ -220,3 +222,54 @@ def test_near_lowrank_factors_match_oracle_quadrature():
         vo = volume.potential_boxes(tx, ty, [ox], [oy], [s], volume.leaf_coefficients(f[None], K), K)
         err = np.abs((f @ W) @ Q - 2 * np.pi * vo).max()
         assert err < 1e-13 * max(1.0, np.abs(2 * np.pi * vo).max()), (c, err)
+
+
+def test_m2p_tables_reproduce_a_point_source():
+    """List-3 M2P operands: applied to the scaled multipole of a unit point
+    charge inside the source box (a_0 = 1, a_k = -s^k/k with s the charge's
+    offset from the box centre in units of the box side), each of the 20
+    slots gives log|z - s| at the target leaf's nodes (z in units of the box
+    side) up to the truncation |s/z|^P; the other 16 slots and the padding
+    rows are zero."""
+    K, p = 16, 24
+    n, P = K * K, p + 1
+    rows = 64 * ((2 * P + 63) // 64)
+    ctx = vfx.Context(K, p)
+    t = cheb.nodes(K)
+    s = 0.3 - 0.2j
+    m = np.zeros(rows)
+    m[0] = 1.0
+    for k in range(1, P):
+        a = -s ** k / k
+        m[2 * k], m[2 * k + 1] = a.real, a.imag
+    used = 0
+    for slot in range(36):
+        ox, oy = 2 * (slot // 6) - 5, 2 * (slot % 6) - 5
+        T = ctx.debug_table(23, slot, rows * n).reshape(rows, n)
+        if max(abs(ox), abs(oy)) != 5:
+            assert np.abs(T).max() == 0, slot
+            continue
+        used += 1
+        assert np.abs(T[2 * P:]).max() == 0 and np.abs(T[1]).max() == 0
+        z = (t[:, None] - ox / 2) + 1j * (t[None, :] - oy / 2)
+        ref = np.log(np.abs(z - s)).ravel()
+        assert np.abs(m @ T - ref).max() < 1e-13, slot
+    assert used == 20
+
+
+def test_list3_boxes_are_one_level_finer():
+    """Every list-3 box of a level-restricted tree is a child of a colleague
+    of the leaf, one level finer and not touching it (the M2P slots assume
+    it)."""
+    cfg, ctx, tr, plan = _plan_for("starfish_small")
+    bx = plan.boxes()
+    lv, ix, iy = bx["level"], bx["ix"], bx["iy"]
+    ptr, src, _ = plan.lists(3)
+    lb, lx, ly = (np.asarray(tr[k]) for k in ("level", "ix", "iy"))
+    assert len(src) > 0
+    for leaf in range(len(ptr) - 1):
+        for w in src[ptr[leaf]:ptr[leaf + 1]]:
+            assert lv[w] == lb[leaf] + 1
+            ox = (2 * ix[w] + 1) - 2 * (2 * lx[leaf] + 1)
+            oy = (2 * iy[w] + 1) - 2 * (2 * ly[leaf] + 1)
+            assert max(abs(ox), abs(oy)) == 5
