@@ -253,6 +253,7 @@ __global__ void __launch_bounds__(256) k_extension(
 }
 
 typedef double vfx_d4 __attribute__((ext_vector_type(4)));
+typedef double vfx_d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -623,6 +624,132 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
     }
   }
   }  // work items
+}
+
+// -------------------------------------------------------------------------
+// Table GEMMs with 64-entry tiles and K a multiple of 32 (near field dense
+// operators, P2L, M2P for K = 8 and 16): the same products as k_gemm with a
+// deeper pipeline.  A work item is a tile of <= 64 entries of one
+// configuration and a block of MTB row tiles; wave w owns the entries
+// 16w..16w+15.  The entry operands go straight from memory into a ring of
+// three register blocks (contraction order permuted so that a lane reads 64
+// contiguous bytes per block: MFMA step s of block kb pairs k = 32kb +
+// 8(l/16) + s with lane l on both sides); the table block (32 k x 16 MTB
+// rows), shared by the four waves, goes through a ring of two register
+// blocks into double-buffered LDS.  Every global load is issued two
+// compute phases before its data is needed.  LDS rows are 16 MTB + 2
+// doubles apart, so the two lane groups of a half-wave (rows 8 apart) fall
+// into opposite halves of the banks.  Persistent, XCD-aware item order as in
+// k_gemm.
+// calls f(integral_constant<int, I>) for I = I0 .. N-1 (ring indices in an
+// unrolled pipeline stay compile-time constants)
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+template <int KD, int MTB>
+__global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __restrict__ t_cfg,
+                                               const int* __restrict__ t_first, const int* __restrict__ t_count,
+                                               const int* __restrict__ src, const double* __restrict__ A,
+                                               const double* __restrict__ X, double* __restrict__ Y, long sx,
+                                               long sy, int ldx, int kx) {
+  static_assert(KD % 32 == 0, "contraction in blocks of 32");
+  X += blockIdx.y * sx;  // right-hand side blockIdx.y
+  Y += blockIdx.y * sy;
+  constexpr int KB = 32, NKB = KD / KB;
+  constexpr int NC = 16 * MTB, LDB = NC + 2;  // table columns per block, LDS row stride
+  constexpr int BP = NC / 2;                  // 16-byte pieces per table row
+  __shared__ __attribute__((aligned(16))) double sB[2 * KB * LDB];
+  const int nrb = MT / MTB;
+  const int nb = gridDim.x, bb = blockIdx.x;
+  const int x = bb & 7;
+  const int q = nitems >> 3, rr = nitems & 7;
+  const int xfirst = x * q + min(x, rr), xcount = q + (x < rr ? 1 : 0);
+  const int xwgs = (nb - x + 7) >> 3;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int R = 16 * MT;
+  for (int j = bb >> 3; j < xcount; j += xwgs) {
+    const int item = xfirst + j;
+    const int tile = item / nrb, rb = item - tile * nrb;
+    const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
+    const int row0 = NC * rb;
+    const double* Ac = A + (size_t)c * KD * R + row0;
+    // this lane's entry (an entry past the tile's end reads the first
+    // entry's row; its results are not stored)
+    const int ent = 16 * w + li;
+    const double* xrow = X + (size_t)src[p0 + (ent < np ? ent : 0)] * ldx + 8 * lk;
+    vfx_d2 ra[3][4], rbuf[2][MTB];
+    auto ga = [&](auto kbc, auto slot) __attribute__((always_inline)) {
+      constexpr int kb = decltype(kbc)::value, sl = decltype(slot)::value;
+      static_for<0, 4>([&](auto ec) __attribute__((always_inline)) {
+        constexpr int e = decltype(ec)::value;
+        ra[sl][e] =
+            (KB * kb + 8 * lk + 2 * e < kx) ? *(const vfx_d2*)(xrow + KB * kb + 2 * e) : vfx_d2{0.0, 0.0};
+      });
+    };
+    auto gb = [&](auto kbc, auto slot) __attribute__((always_inline)) {
+      constexpr int kb = decltype(kbc)::value, sl = decltype(slot)::value;
+      static_for<0, MTB>([&](auto ec) __attribute__((always_inline)) {
+        constexpr int e = decltype(ec)::value;
+        const int qq = tid + 256 * e, row = qq / BP, col = 2 * (qq % BP);
+        rbuf[sl][e] = *(const vfx_d2*)(Ac + (size_t)(KB * kb + row) * R + col);
+      });
+    };
+    auto sb = [&](auto buf, auto slot) __attribute__((always_inline)) {
+      constexpr int bf = decltype(buf)::value, sl = decltype(slot)::value;
+      static_for<0, MTB>([&](auto ec) __attribute__((always_inline)) {
+        constexpr int e = decltype(ec)::value;
+        const int qq = tid + 256 * e, row = qq / BP, col = 2 * (qq % BP);
+        *(vfx_d2*)(sB + (bf * KB + row) * LDB + col) = rbuf[sl][e];
+      });
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    vfx_d4 acc[MTB];
+#pragma unroll
+    for (int r = 0; r < MTB; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
+    ga(I0{}, I0{});
+    gb(I0{}, I0{});
+    if constexpr (NKB > 1) {
+      ga(I1{}, I1{});
+      gb(I1{}, I1{});
+    }
+    __syncthreads();  // the previous item is done with sB
+    sb(I0{}, I0{});
+    __syncthreads();
+    static_for<0, NKB>([&](auto kbc) __attribute__((always_inline)) {
+      constexpr int kb = decltype(kbc)::value;
+      if constexpr (kb + 2 < NKB) {
+        ga(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, (kb + 2) % 3>{});
+        gb(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, kb % 2>{});
+      }
+      const double* sbk = sB + ((kb % 2) * KB + 8 * lk) * LDB + li;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const double av = (s & 1) ? ra[kb % 3][s >> 1].y : ra[kb % 3][s >> 1].x;
+        double bv[MTB];
+#pragma unroll
+        for (int r = 0; r < MTB; ++r) bv[r] = sbk[s * LDB + 16 * r];
+#pragma unroll
+        for (int r = 0; r < MTB; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[r], acc[r], 0, 0, 0);
+      }
+      if constexpr (kb + 1 < NKB) sb(std::integral_constant<int, (kb + 1) % 2>{}, std::integral_constant<int, (kb + 1) % 2>{});
+      __syncthreads();
+    });
+    // outputs D[lk + 4e][16 r + li]: entry 16w + lk + 4e, row row0 + 16r + li
+#pragma unroll
+    for (int r = 0; r < MTB; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int en = 16 * w + lk + 4 * e;
+        if (en < np) Y[(size_t)(p0 + en) * R + row0 + 16 * r + li] = acc[r][e];
+      }
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -1698,8 +1825,12 @@ static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, co
                         int ldx = KD, int kx = KD) {
   const int items = ntiles * (MT / MTB);
   const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
-  hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src,
-                     A, X, Y, P2, root, leaf_box, box_level, sx, sy, ldx, kx);
+  if constexpr (EPI == 0 && TE == 64 && KD % 32 == 0)
+    hipLaunchKernelGGL((k_tgemm<KD, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src, A, X, Y,
+                       sx, sy, ldx, kx);
+  else
+    hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count,
+                       src, A, X, Y, P2, root, leaf_box, box_level, sx, sy, ldx, kx);
 }
 
 // Dense near-field tables: MT = n/16 row tiles (1, 4, 9 or 16 for K = 4, 8,
