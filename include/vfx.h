@@ -255,7 +255,7 @@ int vfx_graph_destroy(vfx_graph* graph);
  *   ms[5] near field, dense operators (side stream)
  *   ms[6] far field (list-1 and list-3 sums, L2P)   ms[7] total
  *   ms[8] P2L, list-4 products (side stream)
- *   ms[9] M2P, list-3 products (side stream)
+ *   ms[9] M2P, list-3 products (after the upward pass)
  * and ms[10] (if n_out >= 11) the number of executes averaged.  Phases on
  * the two streams overlap, so they do not add up to the total.  n_out must
  * be >= 10. */

@@ -628,7 +628,7 @@ __global__ void __launch_bounds__(256) k_gemm(int nitems, int MT, const int* __r
 
 // -------------------------------------------------------------------------
 // Table GEMMs with 64-entry tiles and K a multiple of 32 (near field dense
-// operators, P2L, M2P for K = 8 and 16): the same products as k_gemm with a
+// operators, P2L, M2P, P2M for K = 8 and 16): the same products as k_gemm with a
 // deeper pipeline.  A work item is a tile of <= 64 entries of one
 // configuration and a block of MTB row tiles; wave w owns the entries
 // 16w..16w+15.  The entry operands go straight from memory into a ring of
@@ -651,12 +651,13 @@ __device__ __forceinline__ void static_for(F&& f) {
   }
 }
 
-template <int KD, int MTB>
+template <int KD, int MTB, int EPI>
 __global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __restrict__ t_cfg,
                                                const int* __restrict__ t_first, const int* __restrict__ t_count,
                                                const int* __restrict__ src, const double* __restrict__ A,
                                                const double* __restrict__ X, double* __restrict__ Y, long sx,
-                                               long sy, int ldx, int kx) {
+                                               long sy, int ldx, int kx, int P2, double root_size,
+                                               const int* __restrict__ leaf_box, const int* __restrict__ box_level) {
   static_assert(KD % 32 == 0, "contraction in blocks of 32");
   X += blockIdx.y * sx;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
@@ -742,13 +743,24 @@ __global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __
       __syncthreads();
     });
     // outputs D[lk + 4e][16 r + li]: entry 16w + lk + 4e, row row0 + 16r + li
+    // (EPI = 1: rows < 2P of a leaf, scaled by h^2, into its multipole)
 #pragma unroll
-    for (int r = 0; r < MTB; ++r)
+    for (int e = 0; e < 4; ++e) {
+      const int en = 16 * w + lk + 4 * e;
+      if (en >= np) continue;
+      if constexpr (EPI == 0) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int en = 16 * w + lk + 4 * e;
-        if (en < np) Y[(size_t)(p0 + en) * R + row0 + 16 * r + li] = acc[r][e];
+        for (int r = 0; r < MTB; ++r) Y[(size_t)(p0 + en) * R + row0 + 16 * r + li] = acc[r][e];
+      } else {
+        const int b = leaf_box[src[p0 + en]];
+        const double h = box_side(root_size, box_level[b]);
+#pragma unroll
+        for (int r = 0; r < MTB; ++r) {
+          const int row = row0 + 16 * r + li;
+          if (row < P2) Y[(size_t)b * P2 + row] = h * h * acc[r][e];
+        }
       }
+    }
   }
 }
 
@@ -760,82 +772,150 @@ __global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __
 //   Y = Z Q_c^T  (pairs x n),
 // both as FP64 MFMA tile products; Z stays in LDS between the two.  Wave w
 // owns the pairs 16w..16w+15 of the tile.  Phase 1 takes its A operands
-// (the wave's own source rows) straight from memory into registers, with the
-// contraction order permuted so that a lane reads 64 contiguous bytes per
-// block; the factor W_c, shared by the four waves, goes through LDS in
-// double-buffered blocks of 32 source nodes.  Persistent, XCD-aware item
+// (the wave's own source rows) straight from memory into a ring of three
+// register blocks, with the contraction order permuted so that a lane reads
+// 32 contiguous bytes per block of 16 source nodes; the factor W_c, shared
+// by the four waves, goes through a ring of two register blocks into
+// double-buffered LDS.  Phase 2 runs in two halves of n/2 target rows (half
+// the accumulators), with Q_c staged the same way, 8 ranks per block.
+// Every global load is issued two compute phases before its data is needed.
+// With about 51 KB of LDS and <= 168 VGPRs three work-groups share a CU, so
+// a few hundred tiles are all resident at once.  Persistent, XCD-aware item
 // order as in k_gemm (items are configuration-major, so an XCD's L2 holds
 // the factors of the few configurations it works on).
-constexpr int kLrKB = 32, kLrLDW = 66, kLrLDZ = kNearLrMax + 1;
+// LDS row strides: W rows 68 doubles (lane groups of a half-wave read rows
+// 4 apart: 4 x 68 x 8 bytes = 128 mod 256, opposite halves of the banks);
+// Q rows 144 doubles (rows 1 apart: 144 x 8 = 128 mod 256).
+constexpr int kLrKB = 16, kLrLDW = 68, kLrLDZ = kNearLrMax + 1, kLrQB = 8, kLrLDQ = 144;
 
-// Phase 1 for MT1 = R_c/16 rank tiles (compile-time, so the MFMA sequence
-// has no per-tile branches); leaves Z in sZ[pair][rank].  MFMA step s of
-// block kb pairs source node 32kb + 8(l/16) + s with lane l, on both sides.
-// sW rows are 66 doubles apart: the two lane groups of a half-wave read rows
-// 8 apart, which then fall into opposite halves of the banks.
 template <int KD, int MT1>
-__device__ __forceinline__ void near_lr_phase1(const double* __restrict__ xrow, const double* __restrict__ Wc,
-                                               double* sW, double* sZ) {
-  constexpr int LM = kNearLrMax, NKB = KD / kLrKB;
+__device__ __forceinline__ void near_lr_item(const double* __restrict__ xrow, const double* __restrict__ Wc,
+                                             const double* __restrict__ Qc, double* sbuf, double* sZ,
+                                             double* __restrict__ Yp, int np) {
+  constexpr int LM = kNearLrMax, NKB = KD / kLrKB, R = 16 * MT1;
+  constexpr int NQB = R / kLrQB, HR = KD / 2, NRT2 = HR / 16;
+  static_assert(2 * kLrKB * kLrLDW <= 2 * kLrQB * kLrLDQ && HR <= kLrLDQ, "staging buffer sizes");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  double2 a[2][4], rw[4];
-  auto gload_a = [&](int kb, double2* d) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) d[e] = *(const double2*)(xrow + kLrKB * kb + 2 * e);
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  // ---- phase 1: Z = X W^T; MFMA step s of block kb pairs source node
+  // 16kb + 4(l/16) + s with lane l on both sides
+  vfx_d2 ra[3][2], rw[2][2];
+  auto ga = [&](auto kbc, auto slc) __attribute__((always_inline)) {
+    constexpr int kb = decltype(kbc)::value, sl = decltype(slc)::value;
+    ra[sl][0] = *(const vfx_d2*)(xrow + kLrKB * kb);
+    ra[sl][1] = *(const vfx_d2*)(xrow + kLrKB * kb + 2);
   };
-  // factor block: 32 rows of 64 ranks, 16-byte pieces q = tid + 256 e
-  auto gload_w = [&](int kb) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
+  auto gw = [&](auto kbc, auto slc) __attribute__((always_inline)) {
+    constexpr int kb = decltype(kbc)::value, sl = decltype(slc)::value;
+    static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
+      constexpr int e = decltype(ec)::value;
       const int q = tid + 256 * e, row = q >> 5, col = 2 * (q & 31);
-      rw[e] = col < 16 * MT1 ? *(const double2*)(Wc + (size_t)(kLrKB * kb + row) * LM + col) : double2{0, 0};
-    }
+      rw[sl][e] = col < R ? *(const vfx_d2*)(Wc + (size_t)(kLrKB * kb + row) * LM + col) : vfx_d2{0.0, 0.0};
+    });
   };
-  auto lstore_w = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
+  auto sw = [&](auto bufc, auto slc) __attribute__((always_inline)) {
+    constexpr int bf = decltype(bufc)::value, sl = decltype(slc)::value;
+    static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
+      constexpr int e = decltype(ec)::value;
       const int q = tid + 256 * e, row = q >> 5, col = 2 * (q & 31);
-      *(double2*)(sW + (buf * kLrKB + row) * kLrLDW + col) = rw[e];
-    }
+      *(vfx_d2*)(sbuf + (bf * kLrKB + row) * kLrLDW + col) = rw[sl][e];
+    });
   };
   vfx_d4 acc[MT1];
 #pragma unroll
   for (int r = 0; r < MT1; ++r) acc[r] = vfx_d4{0, 0, 0, 0};
-  gload_a(0, a[0]);
-  gload_w(0);
-  __syncthreads();  // the previous item is done with sW and sZ
-  lstore_w(0);
+  ga(I0{}, I0{});
+  gw(I0{}, I0{});
+  ga(I1{}, I1{});
+  gw(I1{}, I1{});
+  __syncthreads();  // the previous item is done with sbuf and sZ
+  sw(I0{}, I0{});
   __syncthreads();
-#pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) {
-    const int buf = kb & 1;
-    if (kb + 1 < NKB) {
-      gload_a(kb + 1, a[buf ^ 1]);
-      gload_w(kb + 1);
+  static_for<0, NKB>([&](auto kbc) __attribute__((always_inline)) {
+    constexpr int kb = decltype(kbc)::value;
+    if constexpr (kb + 2 < NKB) {
+      ga(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, (kb + 2) % 3>{});
+      gw(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, kb % 2>{});
     }
-    const double* sb = sW + (buf * kLrKB + 8 * lk) * kLrLDW + li;
+    const double* sb = sbuf + ((kb % 2) * kLrKB + 4 * lk) * kLrLDW + li;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const double av = (s & 1) ? a[buf][s >> 1].y : a[buf][s >> 1].x;
+    for (int s = 0; s < 4; ++s) {
+      const double av = ra[kb % 3][s >> 1][s & 1];
       double bv[MT1];
 #pragma unroll
       for (int r = 0; r < MT1; ++r) bv[r] = sb[s * kLrLDW + 16 * r];
 #pragma unroll
       for (int r = 0; r < MT1; ++r) acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[r], acc[r], 0, 0, 0);
     }
-    if (kb + 1 < NKB) lstore_w(buf ^ 1);
+    if constexpr (kb + 1 < NKB)
+      sw(std::integral_constant<int, (kb + 1) % 2>{}, std::integral_constant<int, (kb + 1) % 2>{});
     __syncthreads();
-  }
+  });
   // Z rows of this wave's pairs: D[lk + 4e][16 r + li]
 #pragma unroll
   for (int r = 0; r < MT1; ++r)
 #pragma unroll
     for (int e = 0; e < 4; ++e) sZ[(16 * w + lk + 4 * e) * kLrLDZ + 16 * r + li] = acc[r][e];
+  // ---- phase 2: Y = Z Q^T in two halves of HR rows; Q block = 8 ranks x HR
+  // rows, thread tid stages 16-byte pieces tid and tid + 256
+  vfx_d2 rq[2][2];
+  static_for<0, 2>([&](auto hc) __attribute__((always_inline)) {
+    constexpr int h = decltype(hc)::value;
+    auto gq = [&](auto qbc, auto slc) __attribute__((always_inline)) {
+      constexpr int qb = decltype(qbc)::value, sl = decltype(slc)::value;
+      static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
+        constexpr int e = decltype(ec)::value;
+        const int v = tid + 256 * e, rank = v / (HR / 2), col = 2 * (v % (HR / 2));
+        rq[sl][e] = *(const vfx_d2*)(Qc + (size_t)(kLrQB * qb + rank) * KD + HR * h + col);
+      });
+    };
+    auto sq = [&](auto bufc, auto slc) __attribute__((always_inline)) {
+      constexpr int bf = decltype(bufc)::value, sl = decltype(slc)::value;
+      static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
+        constexpr int e = decltype(ec)::value;
+        const int v = tid + 256 * e, rank = v / (HR / 2), col = 2 * (v % (HR / 2));
+        *(vfx_d2*)(sbuf + (bf * kLrQB + rank) * kLrLDQ + col) = rq[sl][e];
+      });
+    };
+    vfx_d4 acc2[NRT2];
+#pragma unroll
+    for (int r = 0; r < NRT2; ++r) acc2[r] = vfx_d4{0, 0, 0, 0};
+    gq(I0{}, I0{});
+    if constexpr (NQB > 1) gq(I1{}, I1{});
+    __syncthreads();  // phase 1 (or the previous half) is done with sbuf; sZ complete
+    sq(I0{}, I0{});
+    __syncthreads();
+    static_for<0, NQB>([&](auto qbc) __attribute__((always_inline)) {
+      constexpr int qb = decltype(qbc)::value;
+      if constexpr (qb + 2 < NQB)
+        gq(std::integral_constant<int, qb + 2>{}, std::integral_constant<int, qb % 2>{});
+#pragma unroll
+      for (int ks = 0; ks < kLrQB / 4; ++ks) {
+        const int kk = 4 * ks + lk;
+        const double a = sZ[(16 * w + li) * kLrLDZ + kLrQB * qb + kk];
+        const double* sq_row = sbuf + ((qb % 2) * kLrQB + kk) * kLrLDQ + li;
+#pragma unroll
+        for (int r = 0; r < NRT2; ++r)
+          acc2[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sq_row[16 * r], acc2[r], 0, 0, 0);
+      }
+      if constexpr (qb + 1 < NQB)
+        sq(std::integral_constant<int, (qb + 1) % 2>{}, std::integral_constant<int, (qb + 1) % 2>{});
+      __syncthreads();
+    });
+#pragma unroll
+    for (int r = 0; r < NRT2; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ent = 16 * w + lk + 4 * e;
+        if (ent < np) Yp[(size_t)ent * KD + HR * h + 16 * r + li] = acc2[r][e];
+      }
+  });
 }
 
 template <int KD>
-__global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __restrict__ t_cfg,
+__global__ void __launch_bounds__(256, 3) k_near_lr(int nitems, const int* __restrict__ t_cfg,
                                                     const int* __restrict__ t_first, const int* __restrict__ t_count,
                                                     const int* __restrict__ src, const int* __restrict__ lr_R,
                                                     const double* __restrict__ W, const double* __restrict__ Q,
@@ -844,13 +924,8 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
   X += blockIdx.y * sx;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
   constexpr int LM = kNearLrMax;  // 64
-  constexpr int QB = 8;           // rank indices per phase-2 block
-  constexpr int NRT = KD / 16;    // output row tiles
-  static_assert(2 * QB * KD <= 2 * kLrKB * kLrLDW, "phase-2 staging must fit the phase-1 buffer");
-  __shared__ __attribute__((aligned(16))) double sbuf[2 * kLrKB * kLrLDW];
+  __shared__ __attribute__((aligned(16))) double sbuf[2 * kLrQB * kLrLDQ];
   __shared__ double sZ[64 * kLrLDZ];
-  double* sW = sbuf;  // [2][kLrKB][kLrLDW] (phase 1)
-  double* sQ = sbuf;  // [2][QB][KD] (phase 2)
   const int nb = gridDim.x, bb = blockIdx.x;
   const int x = bb & 7;
   const int q = nitems >> 3, rr = nitems & 7;
@@ -861,65 +936,18 @@ __global__ void __launch_bounds__(256, 2) k_near_lr(int nitems, const int* __res
   for (int j = bb >> 3; j < xcount; j += xwgs) {
     const int tile = xfirst + j;
     const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
-    const int R = lr_R[c];
     const double* Wc = W + (size_t)c * KD * LM;
     const double* Qc = Q + (size_t)c * LM * KD;
     // this lane's A-operand pair (a pair past the tile's end reads the first
     // pair's row; its results are not stored)
     const int ent = 16 * w + li;
-    const double* xrow = X + (size_t)src[p0 + (ent < np ? ent : 0)] * KD + 8 * lk;
-    switch (R >> 4) {
-      case 1: near_lr_phase1<KD, 1>(xrow, Wc, sW, sZ); break;
-      case 2: near_lr_phase1<KD, 2>(xrow, Wc, sW, sZ); break;
-      case 3: near_lr_phase1<KD, 3>(xrow, Wc, sW, sZ); break;
-      default: near_lr_phase1<KD, 4>(xrow, Wc, sW, sZ); break;
-    }
-    // ---- phase 2: Y = Z Q^T
-    // Q block: QB ranks x KD rows; thread tid stages rows tid, tid + 256, ...
-    // of every rank (consecutive lanes, consecutive addresses)
-    constexpr int QE = QB * KD / 256;
-    double rq[QE];
-    auto gload2 = [&](int qb) {
-#pragma unroll
-      for (int e = 0; e < QE; ++e) {
-        const int v = tid + 256 * e;  // v = rank * KD + row within the block
-        rq[e] = Qc[(size_t)qb * QB * KD + v];
-      }
-    };
-    auto lstore2 = [&](int buf) {
-#pragma unroll
-      for (int e = 0; e < QE; ++e) sQ[buf * QB * KD + tid + 256 * e] = rq[e];
-    };
-    vfx_d4 acc2[NRT];
-#pragma unroll
-    for (int r = 0; r < NRT; ++r) acc2[r] = vfx_d4{0, 0, 0, 0};
-    const int nqb = R / QB;
-    gload2(0);
-    __syncthreads();  // phase-1 reads of sbuf done; sZ complete
-    lstore2(0);
-    __syncthreads();
-    for (int qb = 0; qb < nqb; ++qb) {
-      const int buf = qb & 1;
-      if (qb + 1 < nqb) gload2(qb + 1);
-#pragma unroll
-      for (int ks = 0; ks < QB / 4; ++ks) {
-        const int kk = 4 * ks + lk;
-        const double a = sZ[(16 * w + li) * kLrLDZ + qb * QB + kk];
-#pragma unroll
-        for (int r = 0; r < NRT; ++r)
-          acc2[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sQ[(buf * QB + kk) * KD + 16 * r + li], acc2[r], 0, 0, 0);
-      }
-      if (qb + 1 < nqb) lstore2(buf ^ 1);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < NRT; ++r) {
-      const int row = 16 * r + li;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ent = 16 * w + lk + 4 * e;
-        if (ent < np) Y[(size_t)(p0 + ent) * KD + row] = acc2[r][e];
-      }
+    const double* xrow = X + (size_t)src[p0 + (ent < np ? ent : 0)] * KD + 4 * lk;
+    double* Yp = Y + (size_t)p0 * KD;
+    switch (lr_R[c] >> 4) {
+      case 1: near_lr_item<KD, 1>(xrow, Wc, Qc, sbuf, sZ, Yp, np); break;
+      case 2: near_lr_item<KD, 2>(xrow, Wc, Qc, sbuf, sZ, Yp, np); break;
+      case 3: near_lr_item<KD, 3>(xrow, Wc, Qc, sbuf, sZ, Yp, np); break;
+      default: near_lr_item<KD, 4>(xrow, Wc, Qc, sbuf, sZ, Yp, np); break;
     }
   }  // work items
 }
@@ -1781,7 +1809,6 @@ int upload_plan(Plan* p, std::string& err) {
   VFX_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
   VFX_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
   VFX_HIP(hipEventCreateWithFlags(&p->p2l_ev, hipEventDisableTiming));
-  VFX_HIP(hipEventCreateWithFlags(&p->up_ev, hipEventDisableTiming));
   D.ready = true;
   return VFX_OK;
 }
@@ -1812,9 +1839,8 @@ void free_plan_device(Plan* p) {
   if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   if (p->join_ev) (void)hipEventDestroy(p->join_ev);
   if (p->p2l_ev) (void)hipEventDestroy(p->p2l_ev);
-  if (p->up_ev) (void)hipEventDestroy(p->up_ev);
   if (p->side) (void)hipStreamDestroy(p->side);
-  p->fork_ev = p->join_ev = p->p2l_ev = p->up_ev = nullptr;
+  p->fork_ev = p->join_ev = p->p2l_ev = nullptr;
   p->side = nullptr;
 }
 
@@ -1825,9 +1851,9 @@ static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, co
                         int ldx = KD, int kx = KD) {
   const int items = ntiles * (MT / MTB);
   const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
-  if constexpr (EPI == 0 && TE == 64 && KD % 32 == 0)
-    hipLaunchKernelGGL((k_tgemm<KD, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src, A, X, Y,
-                       sx, sy, ldx, kx);
+  if constexpr (TE == 64 && KD % 32 == 0)
+    hipLaunchKernelGGL((k_tgemm<KD, MTB, EPI>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src, A,
+                       X, Y, sx, sy, ldx, kx, P2, root, leaf_box, box_level);
   else
     hipLaunchKernelGGL((k_gemm<KD, EPI, TE, MTB>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count,
                        src, A, X, Y, P2, root, leaf_box, box_level, sx, sy, ldx, kx);
@@ -1856,8 +1882,10 @@ static void near_gemm(int n, int ntiles, const int* cfg, const int* first, const
 #undef VFX_NG
 }
 
-// P2L (EPI 0, TE 64) and P2M (EPI 1, TE 16) tables: rows padded to a
-// multiple of 64, so MT is 4 or 8 and one row block covers it.
+// P2L (EPI 0, TE 64) and P2M (EPI 1, TE 64) tables: rows padded to a
+// multiple of 64, so MT is 4 or 8; P2L takes them in one row block, P2M
+// (one tile per 64 leaves, few tiles) one row tile per work item on the
+// pipelined kernel, for more items in flight.
 template <int EPI, int TE>
 static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count,
                            const int* src, const double* A, const double* X, double* Y, hipStream_t s, unsigned R,
@@ -1866,7 +1894,10 @@ static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int*
   if (ntiles <= 0) return;
 #define VFX_EXP_CASE(KDV)                                                                                       \
   do {                                                                                                          \
-    if (MT == 4)                                                                                                \
+    if (EPI == 1 && KDV % 32 == 0)                                                                              \
+      launch_gemm<KDV, EPI, TE, 1>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
+                                   R, sx, sy);                                                                  \
+    else if (MT == 4)                                                                                           \
       launch_gemm<KDV, EPI, TE, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
                                    R, sx, sy);                                                                  \
     else                                                                                                        \
@@ -1898,7 +1929,7 @@ static void m2p_gemm(int n, int kd, int P2, int ntiles, const int* cfg, const in
     case 16: VFX_M2P(KDV, 1); break;  \
     case 64: VFX_M2P(KDV, 4); break;  \
     case 144: VFX_M2P(KDV, 9); break; \
-    default: VFX_M2P(KDV, 4); break;  \
+    default: VFX_M2P(KDV, 8); break;  \
   }
   if (kd == 64) {
     VFX_M2P_N(64)
@@ -2028,8 +2059,9 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   }
   VFX_HIP(hipGetLastError());
   MARK(7, p->side);
+  VFX_HIP(hipEventRecord(p->join_ev, p->side));
   // multipoles of the leaves
-  expansion_gemm<1, 16>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
+  expansion_gemm<1, 64>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
                         DT.p2m_gemm, fe, (double*)D.mpole, s, R, sFL, 2 * sMP, 2 * P, T.root_size, D.leaf_box,
                         D.box_level);
   if (!H.up_grp.empty()) {
@@ -2056,18 +2088,13 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
                          D.mpole, sUP, sMP);
   }
   VFX_HIP(hipGetLastError());
-  VFX_HIP(hipEventRecord(p->up_ev, s));  // multipoles complete
   MARK(2, s);
-  // M2P for list 3 on the side stream, after its near-field work and once
-  // the multipoles are complete (enqueued here, after up_ev is recorded, so
-  // the wait refers to this execute's upward pass)
-  VFX_HIP(hipStreamWaitEvent(p->side, p->up_ev, 0));
-  MARK(11, p->side);
+  // M2P for list 3 on the caller's stream, right after the upward pass
+  // (the side stream carries P2L and the near field, the longer share)
   m2p_gemm(n, T.p2l_rows, 2 * P, (int)H.t3_cfg.size(), D.t3_cfg, D.t3_first, D.t3_count, D.p3_src, DT.m2p_gemm,
-           (const double*)D.mpole, D.m2p_y, p->side, R, 2 * sMP, sM3);
+           (const double*)D.mpole, D.m2p_y, s, R, 2 * sMP, sM3);
   VFX_HIP(hipGetLastError());
-  MARK(12, p->side);
-  VFX_HIP(hipEventRecord(p->join_ev, p->side));
+  MARK(11, s);
   if (H.nlev > 2) {
     VFX_HIP(hipStreamWaitEvent(s, p->p2l_ev, 0));  // list-4 products from the side stream
     const int ng = (int)H.m2l_grp.size() - 1;

@@ -490,10 +490,10 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
   // P2M: every leaf, one configuration
   H.leaf_ids.resize(L);
   for (int i = 0; i < L; ++i) H.leaf_ids[i] = i;
-  for (int f = 0; f < L; f += 16) {
+  for (int f = 0; f < L; f += 64) {
     H.t0_cfg.push_back(0);
     H.t0_first.push_back(f);
-    H.t0_count.push_back(std::min(16, L - f));
+    H.t0_count.push_back(std::min(64, L - f));
   }
 
   // ---- extension lists ---------------------------------------------------

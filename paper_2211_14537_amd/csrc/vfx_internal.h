@@ -214,16 +214,13 @@ struct Plan {
   Context* ctx = nullptr;
   HostPlan H;
   DevicePlan D;
-  // P2L, the near field and M2P run on a side stream (default priority),
-  // forked after the extension; M2L waits for P2L (p2l_ev), the far-field
-  // kernel for the whole side stream (join_ev)
+  // P2L and the near field run on a side stream (default priority), forked
+  // after the extension; M2L waits for P2L (p2l_ev), the far-field kernel
+  // for the whole side stream (join_ev)
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr, p2l_ev = nullptr;
-  // the side stream's M2P waits for the multipoles (up_ev, after the upward
-  // pass on the caller's stream)
-  hipEvent_t up_ev = nullptr;
   // per-phase timing: one set of kEvents events per timed execute
-  static constexpr int kEvents = 13;
+  static constexpr int kEvents = 12;
   // launch parameters chosen by vfx_plan_autotune
   struct Tune {
     int near_wgs = 512;  // work-group cap of the persistent near-field kernels
