@@ -174,7 +174,7 @@ int vfx_mlp_infer_f16(const uint16_t* theta_h, const uint16_t* x_h, int64_t batc
 int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, const double* py, double* out,
                void* stream);
 
-/* Precision of the near field (NEXT: mixed precision).  mode 0: FP64
+/* Precision of the near field.  mode 0: FP64
  * everywhere (the default).  mode 1: the list-1 interactions whose source
  * leaf is at level >= min_level are applied with the operands split into
  * three bf16 slices (about 24 significant bits) on the bf16 matrix cores
@@ -188,7 +188,7 @@ int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, 
 int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level);
 
 /* Plan with the per-cut-leaf least-squares operators computed on the GPU
- * (NEXT: GPU plan stage).  flags = VFX_PLAN_DEFER_FACTOR: the host builds
+ * (the plan stage on the GPU).  flags = VFX_PLAN_DEFER_FACTOR: the host builds
  * only the lists and the interior index sets, and vfx_plan_factor_gpu then
  * computes every P_i = A_{X^I,G}^+ on the device, one work-group per cut
  * leaf: Householder QR of the N_I x N_G rows of A (the paper's QR per cut
@@ -202,7 +202,7 @@ int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level);
 int vfx_plan_create_ex(vfx_ctx* ctx, const vfx_tree* tree, int flags, vfx_plan** out);
 int vfx_plan_factor_gpu(vfx_plan* plan, void* stream);
 
-/* Many right-hand sides on one tree (NEXT: batched execution).  Inputs and
+/* Many right-hand sides on one tree (batched execution).  Inputs and
  * outputs are stacked: f_leaf, fe_out, V_out are nrhs x n_leaves x K^2 and
  * f_cut is nrhs x n_cut x |X| (device, row-major).  Every kernel of the
  * path runs once for the whole batch with the right-hand side as a grid
@@ -216,7 +216,7 @@ int vfx_plan_factor_gpu(vfx_plan* plan, void* stream);
 int vfx_execute_batch(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
                       double* V_out, void* stream);
 
-/* Launch-parameter autotuner (NEXT): times `reps` executes of the given batch
+/* Launch-parameter autotuner: times `reps` executes of the given batch
  * for each candidate (work-group cap of the persistent near-field kernels
  * 256/512/768/1024; row tiles per block of the dense near-field GEMM 4/8 at
  * K = 16) with HIP events on `stream` and keeps the fastest for later
@@ -227,13 +227,16 @@ int vfx_plan_autotune(vfx_plan* plan, int nrhs, const double* f_leaf, const doub
                       double* V_out, void* stream, int reps, int32_t* choice);
 
 /* HIP graph capture of a sequence of executes, possibly of many plans
- * (NEXT: many uneven trees in one launch): vfx_graph_begin starts a capture
+ * (many uneven trees in one launch): vfx_graph_begin starts a capture
  * on `stream`; vfx_execute / vfx_execute_batch calls on that stream are
  * recorded (each plan must have executed once before, with at least as many
  * right-hand sides, and have timing off); vfx_graph_end ends the capture and
  * instantiates the graph; vfx_graph_launch replays all of it with one launch
  * on a stream; vfx_graph_destroy frees it.  The graph holds no memset
- * nodes.  VFX_EHIP if the runtime refuses a step. */
+ * nodes.  Every execute of a capture goes to `stream` itself: executes on
+ * other streams forked from it by events are not supported (such a capture
+ * has ended in a crash inside hipStreamEndCapture).  VFX_EHIP if the
+ * runtime refuses a step. */
 int vfx_graph_begin(void* stream);
 int vfx_graph_end(void* stream, vfx_graph** out);
 int vfx_graph_launch(vfx_graph* graph, void* stream);

@@ -223,7 +223,7 @@ struct Plan {
   static constexpr int kEvents = 12;
   // launch parameters chosen by vfx_plan_autotune
   struct Tune {
-    int near_wgs = 512;  // work-group cap of the persistent near-field kernels
+    int near_wgs = 768;  // work-group cap of the persistent near-field kernels (3 per CU)
     int dense_mtb = 4;   // row tiles per block of the dense near-field GEMM (K = 16)
   } tune;
   bool timing = false;
