@@ -374,8 +374,8 @@ def build_case(name, p):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="starfish_adaptive")
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")

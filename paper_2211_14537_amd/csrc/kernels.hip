@@ -767,60 +767,66 @@ __global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __
 // -------------------------------------------------------------------------
 // Near field in low-rank form, for the configurations c whose operator
 // factorises as Q_c W_c (rank R_c <= 64, padded to a multiple of 16).  A
-// work item is a tile of <= 64 list-1 pairs of one configuration:
+// work item is a tile of <= 32 list-1 pairs of one configuration:
 //   Z = X W_c^T  (pairs x R_c: the source leaf values times the row factor),
 //   Y = Z Q_c^T  (pairs x n),
-// both as FP64 MFMA tile products; Z stays in LDS between the two.  Wave w
-// owns the pairs 16w..16w+15 of the tile.  Phase 1 takes its A operands
-// (the wave's own source rows) straight from memory into a ring of three
-// register blocks, with the contraction order permuted so that a lane reads
-// 32 contiguous bytes per block of 16 source nodes; the factor W_c, shared
-// by the four waves, goes through a ring of two register blocks into
-// double-buffered LDS.  Phase 2 runs in two halves of n/2 target rows (half
-// the accumulators), with Q_c staged the same way, 8 ranks per block.
-// Every global load is issued two compute phases before its data is needed.
-// With about 51 KB of LDS and <= 168 VGPRs three work-groups share a CU, so
-// a few hundred tiles are all resident at once.  Persistent, XCD-aware item
-// order as in k_gemm (items are configuration-major, so an XCD's L2 holds
-// the factors of the few configurations it works on).
-// LDS row strides: W rows 68 doubles (lane groups of a half-wave read rows
-// 4 apart: 4 x 68 x 8 bytes = 128 mod 256, opposite halves of the banks);
-// Q rows 144 doubles (rows 1 apart: 144 x 8 = 128 mod 256).
-constexpr int kLrKB = 16, kLrLDW = 68, kLrLDZ = kNearLrMax + 1, kLrQB = 8, kLrLDQ = 144;
+// both as FP64 MFMA tile products.  Wave w = pg + 2 hf works on the pair
+// group pg (pairs 16pg..16pg+15): in phase 1 on the source nodes of half hf
+// (the two partial Z of a pair group meet in LDS), in phase 2 on the target
+// rows of half hf.  So a wave carries half of a 16-pair share of the work,
+// and a few hundred tiles spread evenly over the SIMDs.  Phase 1 takes its A
+// operands (the wave's own source rows) straight from memory into a ring of
+// three register blocks, with the contraction order permuted so that a lane
+// reads 16 contiguous bytes per block of 8 nodes; W_c, shared by the four
+// waves, goes through a ring of two register blocks into double-buffered
+// LDS (both halves' rows of a block at once), and Q_c the same way, 4 ranks
+// per block.  Every global load is issued two compute phases before its
+// data is needed.  With about 51 KB of LDS and <= 168 VGPRs three
+// work-groups share a CU.  Persistent, XCD-aware item order as in k_gemm
+// (items are configuration-major, so an XCD's L2 holds the factors of the
+// few configurations it works on).
+// LDS row strides: W rows 72 doubles (the lane groups of a half-wave read
+// rows 2 apart: 2 x 72 x 8 bytes = 128 mod 256, opposite halves of the
+// banks); Q rows 272 doubles (rows 1 apart: 272 x 8 = 128 mod 256).
+constexpr int kLrKB = 8, kLrLDW = 72, kLrLDZ = kNearLrMax + 1, kLrQB = 4, kLrLDQ = 272;
+constexpr int kLrTile = 32;
 
 template <int KD, int MT1>
 __device__ __forceinline__ void near_lr_item(const double* __restrict__ xrow, const double* __restrict__ Wc,
                                              const double* __restrict__ Qc, double* sbuf, double* sZ,
                                              double* __restrict__ Yp, int np) {
-  constexpr int LM = kNearLrMax, NKB = KD / kLrKB, R = 16 * MT1;
-  constexpr int NQB = R / kLrQB, HR = KD / 2, NRT2 = HR / 16;
-  static_assert(2 * kLrKB * kLrLDW <= 2 * kLrQB * kLrLDQ && HR <= kLrLDQ, "staging buffer sizes");
+  constexpr int LM = kNearLrMax, HK = KD / 2, NKB = HK / kLrKB, R = 16 * MT1;
+  constexpr int NQB = R / kLrQB, NRT2 = HK / 16;
+  static_assert(2 * 2 * kLrKB * kLrLDW >= 2 * kLrQB * kLrLDQ && KD <= kLrLDQ, "staging buffer sizes");
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int pg = w & 1, hf = w >> 1;
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
-  // ---- phase 1: Z = X W^T; MFMA step s of block kb pairs source node
-  // 16kb + 4(l/16) + s with lane l on both sides
-  vfx_d2 ra[3][2], rw[2][2];
+  // ---- phase 1: partial Z over the source nodes of half hf; MFMA step s of
+  // block kb pairs node HK hf + 8kb + 2(l/16) + s with lane l on both sides
+  vfx_d2 ra[3], rw[2][2];
   auto ga = [&](auto kbc, auto slc) __attribute__((always_inline)) {
     constexpr int kb = decltype(kbc)::value, sl = decltype(slc)::value;
-    ra[sl][0] = *(const vfx_d2*)(xrow + kLrKB * kb);
-    ra[sl][1] = *(const vfx_d2*)(xrow + kLrKB * kb + 2);
+    ra[sl] = *(const vfx_d2*)(xrow + kLrKB * kb);
   };
+  // W block: rows 8kb..8kb+7 of both halves (LDS rows 0..7 half 0, 8..15
+  // half 1), 16-byte pieces q = tid + 256 e
   auto gw = [&](auto kbc, auto slc) __attribute__((always_inline)) {
     constexpr int kb = decltype(kbc)::value, sl = decltype(slc)::value;
     static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
       constexpr int e = decltype(ec)::value;
-      const int q = tid + 256 * e, row = q >> 5, col = 2 * (q & 31);
-      rw[sl][e] = col < R ? *(const vfx_d2*)(Wc + (size_t)(kLrKB * kb + row) * LM + col) : vfx_d2{0.0, 0.0};
+      const int q = tid + 256 * e, r16 = q >> 5, col = 2 * (q & 31);
+      const int row = (r16 >> 3) * HK + kLrKB * kb + (r16 & 7);
+      rw[sl][e] = col < R ? *(const vfx_d2*)(Wc + (size_t)row * LM + col) : vfx_d2{0.0, 0.0};
     });
   };
   auto sw = [&](auto bufc, auto slc) __attribute__((always_inline)) {
     constexpr int bf = decltype(bufc)::value, sl = decltype(slc)::value;
     static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
       constexpr int e = decltype(ec)::value;
-      const int q = tid + 256 * e, row = q >> 5, col = 2 * (q & 31);
-      *(vfx_d2*)(sbuf + (bf * kLrKB + row) * kLrLDW + col) = rw[sl][e];
+      const int q = tid + 256 * e, r16 = q >> 5, col = 2 * (q & 31);
+      *(vfx_d2*)(sbuf + (bf * 2 * kLrKB + r16) * kLrLDW + col) = rw[sl][e];
     });
   };
   vfx_d4 acc[MT1];
@@ -839,10 +845,10 @@ __device__ __forceinline__ void near_lr_item(const double* __restrict__ xrow, co
       ga(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, (kb + 2) % 3>{});
       gw(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, kb % 2>{});
     }
-    const double* sb = sbuf + ((kb % 2) * kLrKB + 4 * lk) * kLrLDW + li;
+    const double* sb = sbuf + ((kb % 2) * 2 * kLrKB + kLrKB * hf + 2 * lk) * kLrLDW + li;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const double av = ra[kb % 3][s >> 1][s & 1];
+    for (int s = 0; s < 2; ++s) {
+      const double av = ra[kb % 3][s];
       double bv[MT1];
 #pragma unroll
       for (int r = 0; r < MT1; ++r) bv[r] = sb[s * kLrLDW + 16 * r];
@@ -853,65 +859,59 @@ __device__ __forceinline__ void near_lr_item(const double* __restrict__ xrow, co
       sw(std::integral_constant<int, (kb + 1) % 2>{}, std::integral_constant<int, (kb + 1) % 2>{});
     __syncthreads();
   });
-  // Z rows of this wave's pairs: D[lk + 4e][16 r + li]
+  // partial Z of half hf for the pair group's rows: D[lk + 4e][16 r + li]
+  double* sZh = sZ + hf * kLrTile * kLrLDZ;
 #pragma unroll
   for (int r = 0; r < MT1; ++r)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sZ[(16 * w + lk + 4 * e) * kLrLDZ + 16 * r + li] = acc[r][e];
-  // ---- phase 2: Y = Z Q^T in two halves of HR rows; Q block = 8 ranks x HR
-  // rows, thread tid stages 16-byte pieces tid and tid + 256
+    for (int e = 0; e < 4; ++e) sZh[(16 * pg + lk + 4 * e) * kLrLDZ + 16 * r + li] = acc[r][e];
+  // ---- phase 2: rows HK hf.. of Y = Z Q^T, Z = the sum of the two partials;
+  // Q block = 4 ranks x n rows, pieces v = tid + 256 e
   vfx_d2 rq[2][2];
-  static_for<0, 2>([&](auto hc) __attribute__((always_inline)) {
-    constexpr int h = decltype(hc)::value;
-    auto gq = [&](auto qbc, auto slc) __attribute__((always_inline)) {
-      constexpr int qb = decltype(qbc)::value, sl = decltype(slc)::value;
-      static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
-        constexpr int e = decltype(ec)::value;
-        const int v = tid + 256 * e, rank = v / (HR / 2), col = 2 * (v % (HR / 2));
-        rq[sl][e] = *(const vfx_d2*)(Qc + (size_t)(kLrQB * qb + rank) * KD + HR * h + col);
-      });
-    };
-    auto sq = [&](auto bufc, auto slc) __attribute__((always_inline)) {
-      constexpr int bf = decltype(bufc)::value, sl = decltype(slc)::value;
-      static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
-        constexpr int e = decltype(ec)::value;
-        const int v = tid + 256 * e, rank = v / (HR / 2), col = 2 * (v % (HR / 2));
-        *(vfx_d2*)(sbuf + (bf * kLrQB + rank) * kLrLDQ + col) = rq[sl][e];
-      });
-    };
-    vfx_d4 acc2[NRT2];
-#pragma unroll
-    for (int r = 0; r < NRT2; ++r) acc2[r] = vfx_d4{0, 0, 0, 0};
-    gq(I0{}, I0{});
-    if constexpr (NQB > 1) gq(I1{}, I1{});
-    __syncthreads();  // phase 1 (or the previous half) is done with sbuf; sZ complete
-    sq(I0{}, I0{});
-    __syncthreads();
-    static_for<0, NQB>([&](auto qbc) __attribute__((always_inline)) {
-      constexpr int qb = decltype(qbc)::value;
-      if constexpr (qb + 2 < NQB)
-        gq(std::integral_constant<int, qb + 2>{}, std::integral_constant<int, qb % 2>{});
-#pragma unroll
-      for (int ks = 0; ks < kLrQB / 4; ++ks) {
-        const int kk = 4 * ks + lk;
-        const double a = sZ[(16 * w + li) * kLrLDZ + kLrQB * qb + kk];
-        const double* sq_row = sbuf + ((qb % 2) * kLrQB + kk) * kLrLDQ + li;
-#pragma unroll
-        for (int r = 0; r < NRT2; ++r)
-          acc2[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sq_row[16 * r], acc2[r], 0, 0, 0);
-      }
-      if constexpr (qb + 1 < NQB)
-        sq(std::integral_constant<int, (qb + 1) % 2>{}, std::integral_constant<int, (qb + 1) % 2>{});
-      __syncthreads();
+  auto gq = [&](auto qbc, auto slc) __attribute__((always_inline)) {
+    constexpr int qb = decltype(qbc)::value, sl = decltype(slc)::value;
+    static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
+      constexpr int e = decltype(ec)::value;
+      const int v = tid + 256 * e, rank = v / (KD / 2), col = 2 * (v % (KD / 2));
+      rq[sl][e] = *(const vfx_d2*)(Qc + (size_t)(kLrQB * qb + rank) * KD + col);
     });
+  };
+  auto sq = [&](auto bufc, auto slc) __attribute__((always_inline)) {
+    constexpr int bf = decltype(bufc)::value, sl = decltype(slc)::value;
+    static_for<0, 2>([&](auto ec) __attribute__((always_inline)) {
+      constexpr int e = decltype(ec)::value;
+      const int v = tid + 256 * e, rank = v / (KD / 2), col = 2 * (v % (KD / 2));
+      *(vfx_d2*)(sbuf + (bf * kLrQB + rank) * kLrLDQ + col) = rq[sl][e];
+    });
+  };
+  vfx_d4 acc2[NRT2];
 #pragma unroll
-    for (int r = 0; r < NRT2; ++r)
+  for (int r = 0; r < NRT2; ++r) acc2[r] = vfx_d4{0, 0, 0, 0};
+  gq(I0{}, I0{});
+  if constexpr (NQB > 1) gq(I1{}, I1{});
+  __syncthreads();  // phase 1 is done with sbuf; both partial Z complete
+  sq(I0{}, I0{});
+  __syncthreads();
+  const double* z0 = sZ + (16 * pg + li) * kLrLDZ + lk;
+  const double* z1 = z0 + kLrTile * kLrLDZ;
+  static_for<0, NQB>([&](auto qbc) __attribute__((always_inline)) {
+    constexpr int qb = decltype(qbc)::value;
+    if constexpr (qb + 2 < NQB) gq(std::integral_constant<int, qb + 2>{}, std::integral_constant<int, qb % 2>{});
+    const double a = z0[kLrQB * qb] + z1[kLrQB * qb];
+    const double* qrow = sbuf + ((qb % 2) * kLrQB + lk) * kLrLDQ + HK * hf + li;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int ent = 16 * w + lk + 4 * e;
-        if (ent < np) Yp[(size_t)ent * KD + HR * h + 16 * r + li] = acc2[r][e];
-      }
+    for (int r = 0; r < NRT2; ++r) acc2[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, qrow[16 * r], acc2[r], 0, 0, 0);
+    if constexpr (qb + 1 < NQB)
+      sq(std::integral_constant<int, (qb + 1) % 2>{}, std::integral_constant<int, (qb + 1) % 2>{});
+    __syncthreads();
   });
+#pragma unroll
+  for (int r = 0; r < NRT2; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ent = 16 * pg + lk + 4 * e;
+      if (ent < np) Yp[(size_t)ent * KD + HK * hf + 16 * r + li] = acc2[r][e];
+    }
 }
 
 template <int KD>
@@ -924,8 +924,8 @@ __global__ void __launch_bounds__(256, 3) k_near_lr(int nitems, const int* __res
   X += blockIdx.y * sx;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
   constexpr int LM = kNearLrMax;  // 64
-  __shared__ __attribute__((aligned(16))) double sbuf[2 * kLrQB * kLrLDQ];
-  __shared__ double sZ[64 * kLrLDZ];
+  __shared__ __attribute__((aligned(16))) double sbuf[2 * 2 * kLrKB * kLrLDW];
+  __shared__ double sZ[2 * kLrTile * kLrLDZ];
   const int nb = gridDim.x, bb = blockIdx.x;
   const int x = bb & 7;
   const int q = nitems >> 3, rr = nitems & 7;
@@ -939,9 +939,9 @@ __global__ void __launch_bounds__(256, 3) k_near_lr(int nitems, const int* __res
     const double* Wc = W + (size_t)c * KD * LM;
     const double* Qc = Q + (size_t)c * LM * KD;
     // this lane's A-operand pair (a pair past the tile's end reads the first
-    // pair's row; its results are not stored)
-    const int ent = 16 * w + li;
-    const double* xrow = X + (size_t)src[p0 + (ent < np ? ent : 0)] * KD + 4 * lk;
+    // pair's row; its results are not stored) and its half of the nodes
+    const int ent = 16 * (w & 1) + li;
+    const double* xrow = X + (size_t)src[p0 + (ent < np ? ent : 0)] * KD + (KD / 2) * (w >> 1) + 2 * lk;
     double* Yp = Y + (size_t)p0 * KD;
     switch (lr_R[c] >> 4) {
       case 1: near_lr_item<KD, 1>(xrow, Wc, Qc, sbuf, sZ, Yp, np); break;

@@ -100,10 +100,13 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
         fi = lr ? &H.ml_first : &H.mt_first;
         co = lr ? &H.ml_count : &H.mt_count;
       }
-      for (int f = cnt[g]; f < cnt[g + 1]; f += kTile) {
+      // FP64 low-rank tiles hold 32 pairs (the kernel splits a tile's work
+      // over its four waves), the others 64
+      const int tile = (cls == 0 && lr) ? kTile / 2 : kTile;
+      for (int f = cnt[g]; f < cnt[g + 1]; f += tile) {
         cf->push_back(c);
         fi->push_back(f);
-        co->push_back(std::min(kTile, cnt[g + 1] - f));
+        co->push_back(std::min(tile, cnt[g + 1] - f));
       }
     }
   }
