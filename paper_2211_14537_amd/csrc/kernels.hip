@@ -438,6 +438,36 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
   const double lg0 = act ? a0 * (logd[o] + log(box_side(root_size, box_level[tgt]))) : 0.0;
   double2 tl = make_double2(1.0, 0.0);
   constexpr int NC = (P + 7) / 8;
+  // this lane's output role in every chunk: box bb = b0 + seg, outputs
+  // l = 8c + lc; its list-2 range and the P2L contributions (h^2 times the
+  // list-4 products, and log(h) a_0 of each list-4 leaf for l = 0) are
+  // gathered once, here, so the chunk tails only sum LDS and store
+  const int lc = lane & 7, seg = lane >> 3;
+  const int bb = b0 + seg;
+  const bool own = bb < b1;
+  int r0 = 0, r1 = 0;
+  double p2r[NC], p2i[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) p2r[c] = p2i[c] = 0.0;
+  if (own) {
+    r0 = l2_ptr[bb] - e0;
+    r1 = l2_ptr[bb + 1] - e0;
+    const double h = box_side(root_size, box_level[bb]);
+    const double h2 = h * h;
+    const int q0 = l4_ptr[bb], q1 = l4_ptr[bb + 1];
+    double lgs = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      const double* y = p2l_y + (size_t)l4_slot[q] * p2l_rows + 2 * lc;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (8 * c + lc < P) {
+          p2r[c] += h2 * y[16 * c];
+          p2i[c] += h2 * y[16 * c + 1];
+        }
+      if (lc == 0) lgs += mpole[(size_t)leaf_box[l4_src[q]] * P].x;
+    }
+    p2r[0] += log(h) * lgs;  // zero unless lc == 0 (output l = 0)
+  }
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     __syncthreads();
@@ -476,20 +506,10 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
       s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const int lc = lane & 7, seg = lane >> 3;
-    const int bb = b0 + seg, l = 8 * c + lc;
-    if (bb < b1 && l < P) {
-      const double2 sv = seg_sum(s_o + lc * 64, l2_ptr[bb] - e0, l2_ptr[bb + 1] - e0);
-      double re = sv.x, im = sv.y;
-      const double h = box_side(root_size, box_level[bb]);
-      const double h2 = h * h;
-      for (int q = l4_ptr[bb]; q < l4_ptr[bb + 1]; ++q) {
-        const double* y = p2l_y + (size_t)l4_slot[q] * p2l_rows + 2 * l;
-        re += h2 * y[0];
-        im += h2 * y[1];
-        if (l == 0) re += log(h) * mpole[(size_t)leaf_box[l4_src[q]] * P].x;
-      }
-      local[(size_t)bb * P + l] = make_double2(re, im);
+    const int l = 8 * c + lc;
+    if (own && l < P) {
+      const double2 sv = seg_sum(s_o + lc * 64, r0, r1);
+      local[(size_t)bb * P + l] = make_double2(sv.x + p2r[c], sv.y + p2i[c]);
     }
   }
 }
