@@ -57,3 +57,28 @@ def test_full_size_starfish(gpu_device):
     rel = np.abs(V.ravel()[sel] - vo).max() / np.abs(vo).max()
     say(f"    V: rel Linf = {rel:.3e} over {sel.size} nodes")
     assert rel <= 1e-10
+
+
+def test_full_size_wedge_mixed(gpu_device):
+    """wedge_adaptive (14254 leaves, 3.65e6 nodes) on given data: the FP64
+    path within 1e-10 and the all-mixed near field (bf16 slices, FP32
+    accumulation) within 2e-6 of the oracle at sampled nodes."""
+    say("[full size] wedge_adaptive p=24, FP64 and mixed")
+    case = setup("wedge_adaptive", all_regular=True)
+    assert len(case["tree"]["level"]) == 14254
+    lv = np.asarray(case["tree"]["level"])
+    n = case["K"] ** 2
+    X, Y = case["otree"].leaf_nodes(case["K"])
+    rng = np.random.default_rng(11)
+    sel = set(rng.choice(X.size, 64, replace=False).tolist())
+    sel.update(range(int(np.argmax(lv)) * n, (int(np.argmax(lv)) + 1) * n))
+    sel = np.array(sorted(sel))
+    vo = oracle_potential(case, case["f_leaf"], X.ravel()[sel], Y.ravel()[sel])
+    _, V64 = run_gpu(case)
+    rel64 = np.abs(V64.ravel()[sel] - vo).max() / np.abs(vo).max()
+    case["plan"].set_precision(1, 0)
+    _, Vmx = run_gpu(case)
+    relmx = np.abs(Vmx.ravel()[sel] - vo).max() / np.abs(vo).max()
+    say(f"    rel Linf over {sel.size} nodes: FP64 {rel64:.3e}, mixed {relmx:.3e}")
+    assert rel64 <= 1e-10
+    assert relmx <= 2e-6
