@@ -237,6 +237,108 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
       }
   H.kind.assign(tree->kind, tree->kind + L);
 
+  // ---- extension lists ---------------------------------------------------
+  H.owner.assign(L, -1);
+  std::vector<int64_t> best(L, -1);
+  const int sh = lmax;  // centres in units of root/2^(lmax+1): (2x+1) << (lmax-l)
+  auto cen = [&](int b, int64_t* cx, int64_t* cy) {
+    *cx = (int64_t)(2 * H.box_ix[b] + 1) << (sh - H.box_level[b]);
+    *cy = (int64_t)(2 * H.box_iy[b] + 1) << (sh - H.box_level[b]);
+  };
+  std::vector<int> stack, cand;
+  for (int leaf = 0; leaf < L; ++leaf) {
+    if (H.kind[leaf] != 2) continue;
+    H.cut_leaf.push_back(leaf);
+    H.owner[leaf] = leaf;
+    const int b = H.leaf_box[leaf];
+    const int l = H.box_level[b], x = H.box_ix[b], y = H.box_iy[b];
+    int64_t scx, scy;
+    cen(b, &scx, &scy);
+    cand.clear();
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        if (dx == 0 && dy == 0) continue;
+        const int cx = x + dx, cy = y + dy;
+        if (cx < 0 || cy < 0 || cx >= (1 << l) || cy >= (1 << l)) continue;
+        const int c = find(l, cx, cy);
+        if (c >= 0) {
+          stack.assign(1, c);
+          while (!stack.empty()) {
+            const int u = stack.back();
+            stack.pop_back();
+            if (H.box_leaf[u] >= 0)
+              cand.push_back(H.box_leaf[u]);
+            else
+              for (int q = 0; q < 4; ++q) stack.push_back(H.box_child0[u] + q);
+          }
+        } else {
+          const int p = find(l - 1, cx >> 1, cy >> 1);
+          if (p >= 0 && H.box_leaf[p] >= 0) cand.push_back(H.box_leaf[p]);
+        }
+      }
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int j : cand) {
+      if (H.kind[j] != 0) continue;
+      int64_t jx, jy;
+      cen(H.leaf_box[j], &jx, &jy);
+      const int64_t d2 = (jx - scx) * (jx - scx) + (jy - scy) * (jy - scy);
+      if (best[j] < 0 || d2 <= best[j]) {
+        best[j] = d2;
+        H.owner[j] = leaf;
+      }
+    }
+  }
+  H.ncut = (int)H.cut_leaf.size();
+  std::vector<int> cutpos(L, -1);
+  for (int c = 0; c < H.ncut; ++c) cutpos[H.cut_leaf[c]] = c;
+  std::vector<std::vector<int>> tg(H.ncut);
+  for (int c = 0; c < H.ncut; ++c) tg[c].push_back(H.cut_leaf[c]);
+  for (int j = 0; j < L; ++j) {
+    if (H.kind[j] != 0 || H.owner[j] < 0) continue;
+    const int s = H.owner[j];
+    if (H.box_level[H.leaf_box[s]] > H.box_level[H.leaf_box[j]]) {
+      err = "tree: extension restriction violated (cut leaf " + std::to_string(s) +
+            " would extend onto the coarser leaf " + std::to_string(j) + ")";
+      return VFX_ETREE;
+    }
+    tg[cutpos[s]].push_back(j);
+  }
+  H.ext_ptr.assign(H.ncut + 1, 0);
+  for (int c = 0; c < H.ncut; ++c) {
+    H.ext_ptr[c + 1] = H.ext_ptr[c] + (int)tg[c].size();
+    H.ext_tgt.insert(H.ext_tgt.end(), tg[c].begin(), tg[c].end());
+    // target grid in the cut leaf's Sbar frame (Sbar = 3x the cut leaf,
+    // same centre): node a of target j sits at o + s t_a per axis
+    const int bS = H.leaf_box[H.cut_leaf[c]];
+    const double hS = std::ldexp(T.root_size, -H.box_level[bS]);
+    for (int j : tg[c]) {
+      const int bj = H.leaf_box[j];
+      const double hj = std::ldexp(T.root_size, -H.box_level[bj]);
+      H.ext_geo.push_back((H.box_cx[bj] - H.box_cx[bS]) / (1.5 * hS));
+      H.ext_geo.push_back((H.box_cy[bj] - H.box_cy[bS]) / (1.5 * hS));
+      H.ext_geo.push_back(hj / (3.0 * hS));
+    }
+  }
+
+  // ---- sources whose data are identically zero ------------------------------
+  // f^e vanishes on an exterior leaf outside every extension list, whatever
+  // f is, so such a leaf (and a box all of whose leaves are such) adds
+  // exactly zero to every potential: it is left out as a source of lists 1-4
+  // (it stays a target).
+  std::vector<uint8_t> zero_leaf(L, 0), zero_box(B, 1);
+  for (int j = 0; j < L; ++j) zero_leaf[j] = (H.kind[j] == 0 && H.owner[j] < 0) ? 1 : 0;
+  for (int l = H.nlev - 1; l >= 0; --l)
+    for (int b = H.level_start[l]; b < H.level_start[l + 1]; ++b) {
+      if (H.box_leaf[b] >= 0) {
+        zero_box[b] = zero_leaf[H.box_leaf[b]];
+      } else {
+        uint8_t z = 1;
+        for (int q = 0; q < 4; ++q) z &= zero_box[H.box_child0[b] + q];
+        zero_box[b] = z;
+      }
+    }
+
   // ---- lists 1 and 3 (per leaf), balance check -------------------------
   H.l1_ptr.assign(L + 1, 0);
   H.l3_ptr.assign(L + 1, 0);
@@ -253,7 +355,7 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         const int c = find(l, cx, cy);
         if (c >= 0) {
           if (H.box_leaf[c] >= 0) {
-            l1[leaf].push_back({H.box_leaf[c], (dx + 1) * 3 + (dy + 1)});
+            if (!zero_leaf[H.box_leaf[c]]) l1[leaf].push_back({H.box_leaf[c], (dx + 1) * 3 + (dy + 1)});
           } else {
             for (int q = 0; q < 4; ++q) {
               const int ch = H.box_child0[c] + q;
@@ -265,14 +367,15 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
                   return VFX_ETREE;
                 }
                 const int ox4 = (2 * kx + 1) - 2 * (2 * x + 1), oy4 = (2 * ky + 1) - 2 * (2 * y + 1);
-                l1[leaf].push_back({H.box_leaf[ch], 21 + near_config_fine_index(ox4, oy4)});
+                if (!zero_leaf[H.box_leaf[ch]])
+                  l1[leaf].push_back({H.box_leaf[ch], 21 + near_config_fine_index(ox4, oy4)});
               } else {
                 const int ox = (2 * kx + 1) - 2 * (2 * x + 1), oy = (2 * ky + 1) - 2 * (2 * y + 1);
                 if (std::max(std::abs(ox), std::abs(oy)) != 5) {
                   err = "internal: bad list-3 configuration";
                   return VFX_EINVAL;
                 }
-                l3[leaf].push_back({ch, ((ox + 5) / 2) * 6 + (oy + 5) / 2});
+                if (!zero_box[ch]) l3[leaf].push_back({ch, ((ox + 5) / 2) * 6 + (oy + 5) / 2});
               }
             }
           }
@@ -291,7 +394,7 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
             err = "internal: bad coarse configuration";
             return VFX_EINVAL;
           }
-          l1[leaf].push_back({H.box_leaf[p], 9 + ci});
+          if (!zero_leaf[H.box_leaf[p]]) l1[leaf].push_back({H.box_leaf[p], 9 + ci});
         }
       }
   }
@@ -336,12 +439,12 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
             for (int q = 0; q < 4; ++q) {
               const int ch = H.box_child0[c] + q;
               const int kx = H.box_ix[ch], ky = H.box_iy[ch];
-              if (touch(l, x, y, l, kx, ky)) continue;
+              if (touch(l, x, y, l, kx, ky) || zero_box[ch]) continue;
               H.l2_src.push_back(ch);
               H.l2_off.push_back((kx - x + 3) * 7 + (ky - y + 3));
               ++n2;
             }
-          } else if (!touch(l, x, y, l - 1, px + dx, py + dy)) {
+          } else if (!touch(l, x, y, l - 1, px + dx, py + dy) && !zero_leaf[H.box_leaf[c]]) {
             const int ox2 = (4 * (px + dx) + 2) - (2 * x + 1), oy2 = (4 * (py + dy) + 2) - (2 * y + 1);
             H.l4_src.push_back(H.box_leaf[c]);
             H.l4_cfg.push_back(((ox2 + 5) / 2) * 6 + (oy2 + 5) / 2);
@@ -497,90 +600,6 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     H.t0_cfg.push_back(0);
     H.t0_first.push_back(f);
     H.t0_count.push_back(std::min(64, L - f));
-  }
-
-  // ---- extension lists ---------------------------------------------------
-  H.owner.assign(L, -1);
-  std::vector<int64_t> best(L, -1);
-  const int sh = lmax;  // centres in units of root/2^(lmax+1): (2x+1) << (lmax-l)
-  auto cen = [&](int b, int64_t* cx, int64_t* cy) {
-    *cx = (int64_t)(2 * H.box_ix[b] + 1) << (sh - H.box_level[b]);
-    *cy = (int64_t)(2 * H.box_iy[b] + 1) << (sh - H.box_level[b]);
-  };
-  std::vector<int> stack, cand;
-  for (int leaf = 0; leaf < L; ++leaf) {
-    if (H.kind[leaf] != 2) continue;
-    H.cut_leaf.push_back(leaf);
-    H.owner[leaf] = leaf;
-    const int b = H.leaf_box[leaf];
-    const int l = H.box_level[b], x = H.box_ix[b], y = H.box_iy[b];
-    int64_t scx, scy;
-    cen(b, &scx, &scy);
-    cand.clear();
-    for (int dx = -1; dx <= 1; ++dx)
-      for (int dy = -1; dy <= 1; ++dy) {
-        if (dx == 0 && dy == 0) continue;
-        const int cx = x + dx, cy = y + dy;
-        if (cx < 0 || cy < 0 || cx >= (1 << l) || cy >= (1 << l)) continue;
-        const int c = find(l, cx, cy);
-        if (c >= 0) {
-          stack.assign(1, c);
-          while (!stack.empty()) {
-            const int u = stack.back();
-            stack.pop_back();
-            if (H.box_leaf[u] >= 0)
-              cand.push_back(H.box_leaf[u]);
-            else
-              for (int q = 0; q < 4; ++q) stack.push_back(H.box_child0[u] + q);
-          }
-        } else {
-          const int p = find(l - 1, cx >> 1, cy >> 1);
-          if (p >= 0 && H.box_leaf[p] >= 0) cand.push_back(H.box_leaf[p]);
-        }
-      }
-    std::sort(cand.begin(), cand.end());
-    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    for (int j : cand) {
-      if (H.kind[j] != 0) continue;
-      int64_t jx, jy;
-      cen(H.leaf_box[j], &jx, &jy);
-      const int64_t d2 = (jx - scx) * (jx - scx) + (jy - scy) * (jy - scy);
-      if (best[j] < 0 || d2 <= best[j]) {
-        best[j] = d2;
-        H.owner[j] = leaf;
-      }
-    }
-  }
-  H.ncut = (int)H.cut_leaf.size();
-  std::vector<int> cutpos(L, -1);
-  for (int c = 0; c < H.ncut; ++c) cutpos[H.cut_leaf[c]] = c;
-  std::vector<std::vector<int>> tg(H.ncut);
-  for (int c = 0; c < H.ncut; ++c) tg[c].push_back(H.cut_leaf[c]);
-  for (int j = 0; j < L; ++j) {
-    if (H.kind[j] != 0 || H.owner[j] < 0) continue;
-    const int s = H.owner[j];
-    if (H.box_level[H.leaf_box[s]] > H.box_level[H.leaf_box[j]]) {
-      err = "tree: extension restriction violated (cut leaf " + std::to_string(s) +
-            " would extend onto the coarser leaf " + std::to_string(j) + ")";
-      return VFX_ETREE;
-    }
-    tg[cutpos[s]].push_back(j);
-  }
-  H.ext_ptr.assign(H.ncut + 1, 0);
-  for (int c = 0; c < H.ncut; ++c) {
-    H.ext_ptr[c + 1] = H.ext_ptr[c] + (int)tg[c].size();
-    H.ext_tgt.insert(H.ext_tgt.end(), tg[c].begin(), tg[c].end());
-    // target grid in the cut leaf's Sbar frame (Sbar = 3x the cut leaf,
-    // same centre): node a of target j sits at o + s t_a per axis
-    const int bS = H.leaf_box[H.cut_leaf[c]];
-    const double hS = std::ldexp(T.root_size, -H.box_level[bS]);
-    for (int j : tg[c]) {
-      const int bj = H.leaf_box[j];
-      const double hj = std::ldexp(T.root_size, -H.box_level[bj]);
-      H.ext_geo.push_back((H.box_cx[bj] - H.box_cx[bS]) / (1.5 * hS));
-      H.ext_geo.push_back((H.box_cy[bj] - H.box_cy[bS]) / (1.5 * hS));
-      H.ext_geo.push_back(hj / (3.0 * hS));
-    }
   }
 
   // ---- per-cut-leaf pseudo-inverses --------------------------------------

@@ -85,9 +85,14 @@ def _plan_for(name, all_regular=False):
     return cfg, ctx, tr, vfx.Plan(ctx, tr["level"], tr["ix"], tr["iy"], kind, None if all_regular else tr["mask"])
 
 
+@pytest.mark.parametrize("all_regular", [True, False])
 @pytest.mark.parametrize("name", ["disk_uniform3", "disk_adaptive_small", "starfish_small"])
-def test_lists_partition_sources(name):
-    cfg, ctx, tr, plan = _plan_for(name, all_regular=True)
+def test_lists_partition_sources(name, all_regular):
+    """Every source leaf whose extended data can be nonzero is reached from
+    every target exactly once (near field, or one far-field path); a leaf
+    whose f^e vanishes identically (exterior, outside every extension list)
+    is never a list-1/list-4 source nor alone under a list-2/list-3 box."""
+    cfg, ctx, tr, plan = _plan_for(name, all_regular=all_regular)
     bx = plan.boxes()
     B = bx["level"].size
     L = tr["level"].size
@@ -110,6 +115,8 @@ def test_lists_partition_sources(name):
             out += leaves_under(c)
         return out
 
+    kind = np.asarray(tr["kind"]) if not all_regular else np.ones(L, dtype=np.int8)
+    zero = (kind == 0) & (plan.ext_owner() < 0)
     p1, s1, _ = plan.lists(1)
     p2, s2, _ = plan.lists(2)
     p3, s3, _ = plan.lists(3)
@@ -125,7 +132,17 @@ def test_lists_partition_sources(name):
                 got += leaves_under(s)
             got += list(s4[p4[b]:p4[b + 1]])
             b = parent[b]
-        assert sorted(got) == list(range(L)), leaf
+        if all_regular:
+            assert sorted(got) == list(range(L)), leaf
+        else:
+            got = np.array(got, dtype=int)
+            live = np.flatnonzero(~zero)
+            assert np.array_equal(np.sort(got[~zero[got]]), live), leaf
+            assert np.unique(got).size == got.size, leaf
+    if not all_regular:
+        assert not zero[s1].any() and not zero[s4].any()
+        for w in list(s2) + list(s3):
+            assert not zero[leaves_under(w)].all()
 
 
 @pytest.mark.parametrize("name", ["disk_uniform3", "disk_adaptive_small", "starfish_small"])
