@@ -33,8 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # that dominates it.  The roofline object describes the slowest phase that
 # is a single kernel launch (the others hold several launches, and their
 # event-timed spans include waits for the other stream).
-SINGLE_KERNEL_PHASES = ("extension", "down", "near_lowrank", "near_dense", "far", "p2l", "m2p")
+SINGLE_KERNEL_PHASES = ("fe_init", "extension", "down", "near_lowrank", "near_dense", "far", "p2l", "m2p")
 PHASE_KERNEL = {
+    "fe_init": ("k_fe_init", "// Initial f^e: f on regular leaves"),
     "extension": ("k_extension", "// Extension of one cut leaf per work-group"),
     "p2m_up": ("k_up", "// Upward pass without the level-by-level chain."),
     "m2l": ("k_m2l_lanes", "// M2L: one lane per list-2 entry"),
@@ -74,8 +75,11 @@ def algorithmic_work(case):
     n_pairs_ud = int(np.maximum(lev - 2, 0).sum())
     nI = case["interior"]
     work = {
+        # the extension: P_i and f_I read, the Sbar grid data, every list
+        # target written (ext_targets counts the cut leaves themselves)
         "extension": (2.0 * nG * nI + ncut * (2 * nG * 144 + 4 * 144 * 12) + ext_targets * (2 * 12 * 12 * K + 2 * 12 * n),
-                      8.0 * (nG * nI + nI + ncut * 144 + (L + ext_targets) * n)),
+                      8.0 * (nG * nI + nI + ncut * 144 + ext_targets * n)),
+        "fe_init": (0.0, 16.0 * L * n),
         "p2m_up": (8.0 * P * n * L / 2 + 8.0 * P * P / 2 * n_pairs_ud, 8.0 * L * n + 16.0 * B * P),
         # M2L sums the list-4 products of P2L with the list-2 translations
         "m2l": (8.0 * P * P * N2, 16.0 * 2 * B * P + 16.0 * N4 * P),
@@ -107,10 +111,11 @@ def kernel_digest(marker):
     return hashlib.sha256(src[i:j if j > 0 else len(src)].encode()).hexdigest()[:16]
 
 
-def load_traffic(kernel, workload, digest):
+def load_traffic(kernel, workload, digest, nbytes):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel factor), or
-    None if there is none or the kernel source changed since."""
+    None if there is none, the kernel source changed since, or the work of a
+    launch did (the summary records the algorithmic bytes it was taken at)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -120,7 +125,7 @@ def load_traffic(kernel, workload, digest):
             for kv in line[len("traffic:"):].split():
                 k, v = kv.split("=")
                 vals[k] = v
-    if vals.get("digest") != digest:
+    if vals.get("digest") != digest or float(vals.get("algorithmic_bytes", "nan")) != float(nbytes):
         return None
     return float(vals["bytes_per_launch"])
 
@@ -458,7 +463,7 @@ def main():
         roof = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     kname, marker = PHASE_KERNEL[dom]
-    roof["traffic"] = load_traffic(kname, case["cfg"]["name"], kernel_digest(marker))
+    roof["traffic"] = load_traffic(kname, case["cfg"]["name"], kernel_digest(marker), nbytes)
     roof["kernel"] = kname
     roof["kernel_ms"] = phases[dom]
     roof["algorithmic_flops"] = flops

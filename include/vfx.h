@@ -249,8 +249,8 @@ int vfx_graph_destroy(vfx_graph* graph);
  * every vfx_execute records its events (at most 4096 executes are recorded;
  * enabling again restarts the count).  The query synchronises on the last
  * recorded event and returns, averaged over the recorded executes, the
- * milliseconds of ten phases:
- *   ms[0] extension (f^e assembly and the cut-leaf kernel)
+ * milliseconds of eleven phases:
+ *   ms[0] extension (the cut-leaf kernel)
  *   ms[1] P2M and the upward pass
  *   ms[2] M2L (with the wait for P2L)
  *   ms[3] downward pass (leaf local expansions)
@@ -259,9 +259,10 @@ int vfx_graph_destroy(vfx_graph* graph);
  *   ms[6] far field (list-1 and list-3 sums, L2P)   ms[7] total
  *   ms[8] P2L, list-4 products (side stream)
  *   ms[9] M2P, list-3 products (after the upward pass)
- * and ms[10] (if n_out >= 11) the number of executes averaged.  Phases on
+ *   ms[10] f^e initialisation (f on regular leaves, zero elsewhere)
+ * and ms[11] (if n_out >= 12) the number of executes averaged.  Phases on
  * the two streams overlap, so they do not add up to the total.  n_out must
- * be >= 10. */
+ * be >= 11. */
 int vfx_plan_set_timing(vfx_plan* plan, int enable);
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
 

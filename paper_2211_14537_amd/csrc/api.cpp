@@ -371,7 +371,7 @@ int vfx_plan_set_timing(vfx_plan* plan, int enable) {
 }
 
 int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
-  constexpr int NP = 10;  // phases
+  constexpr int NP = 11;  // phases
   if (!plan || !ms || n_out < NP) return fail(VFX_EINVAL, "vfx_plan_timings: bad argument");
   vfx::Plan& p = plan->p;
   constexpr int NE = vfx::Plan::kEvents;
@@ -379,9 +379,9 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
   hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * NE + 9]);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
   // phase k runs from event a[k] to event b[k]
-  static const int a_[NP] = {0, 1, 11, 3, 5, 6, 8, 0, 10, 2};
-  static const int b_[NP] = {1, 2, 3, 4, 6, 7, 9, 9, 5, 11};
-  double acc[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static const int a_[NP] = {12, 1, 11, 3, 5, 6, 8, 0, 10, 2, 0};
+  static const int b_[NP] = {1, 2, 3, 4, 6, 7, 9, 9, 5, 11, 12};
+  double acc[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < p.n_timed; ++r) {
     const hipEvent_t* ev = &p.ev[(size_t)r * NE];
     for (int k = 0; k < NP; ++k) {

@@ -46,6 +46,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ double box_side(double root, int level) { return ldexp(root, -level); }
 
 // -------------------------------------------------------------------------
+// Initial f^e: f on regular leaves, zero elsewhere (the extension kernel
+// then writes its target leaves).
 __global__ void k_fe_init(int n, int L, const int8_t* __restrict__ kind, const double* __restrict__ f_leaf,
                           double* __restrict__ fe) {
   const long total = (long)L * n;
@@ -2028,6 +2030,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
     int blocks = (int)std::min<long>((total + 255) / 256, 65536);
     hipLaunchKernelGGL(k_fe_init, dim3(blocks, R), dim3(256), 0, s, n, L, D.kind, f_leaf, fe);
   }
+  MARK(12, s);
   if (H.ncut > 0)
     hipLaunchKernelGGL(k_extension, dim3(H.ncut * R), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, D.pinv_ptr,
                        D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t, DT.AbarT, DT.cbar,

@@ -220,7 +220,7 @@ struct Plan {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr, p2l_ev = nullptr;
   // per-phase timing: one set of kEvents events per timed execute
-  static constexpr int kEvents = 12;
+  static constexpr int kEvents = 13;
   // launch parameters chosen by vfx_plan_autotune
   struct Tune {
     int near_wgs = 768;  // work-group cap of the persistent near-field kernels (3 per CU)

@@ -298,7 +298,8 @@ class Plan:
     def set_timing(self, on=True):
         _check(lib().vfx_plan_set_timing(self._h, 1 if on else 0))
 
-    PHASES = ("extension", "p2m_up", "m2l", "down", "near_lowrank", "near_dense", "far", "total", "p2l", "m2p")
+    PHASES = ("extension", "p2m_up", "m2l", "down", "near_lowrank", "near_dense", "far", "total", "p2l", "m2p",
+              "fe_init")
 
     def timings(self):
         """Per-phase milliseconds averaged over the executes recorded since
