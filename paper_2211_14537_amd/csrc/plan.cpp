@@ -493,7 +493,8 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
     const int nU = (int)H.up_box.size();
     std::vector<std::vector<int>> lst(nU);
     for (int b = 0; b < B; ++b) {
-      if (H.box_leaf[b] < 0) continue;
+      // a leaf whose data vanish identically adds nothing to any multipole
+      if (H.box_leaf[b] < 0 || zero_leaf[H.box_leaf[b]]) continue;
       for (int a = H.box_parent[b]; a >= 0 && H.box_level[a] >= 2; a = H.box_parent[a]) lst[pos[a]].push_back(b);
     }
     H.up_ptr.assign(nU + 1, 0);
