@@ -30,20 +30,22 @@ HBM_PEAK_GBS = 8000.0
 
 # phase -> (kernel name as in a kernel trace, marker comment that opens its
 # source block in kernels.hip); a phase of several kernels names the one
-# that dominates it.  The roofline object describes the slowest phase that
-# is a single kernel launch (the others hold several launches, and their
-# event-timed spans include waits for the other stream).
+# that dominates it.  The roofline object describes, among the phases that
+# are a single kernel launch (the others hold several launches, and their
+# event-timed spans include waits for the other stream), the one with the
+# most algorithmic work (the longest time at the roofline): event times of
+# kernels that share the GPU with the other stream vary from run to run.
 SINGLE_KERNEL_PHASES = ("fe_init", "extension", "down", "near_lowrank", "near_dense", "far", "p2l", "m2p")
 PHASE_KERNEL = {
     "fe_init": ("k_fe_init", "// Initial f^e: f on regular leaves"),
     "extension": ("k_extension", "// Extension of one cut leaf per work-group"),
     "p2m_up": ("k_up", "// Upward pass without the level-by-level chain."),
     "m2l": ("k_m2l_lanes", "// M2L: one lane per list-2 entry"),
-    "p2l": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
-    "m2p": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
+    "p2l": ("k_tgemm", "// Table GEMMs with 64-entry tiles"),
+    "m2p": ("k_tgemm", "// Table GEMMs with 64-entry tiles"),
     "down": ("k_down", "// Downward pass without the level-by-level chain"),
     "near_lowrank": ("k_near_lr", "// Near field in low-rank form"),
-    "near_dense": ("k_gemm", "// Batched table GEMMs on the FP64 matrix cores"),
+    "near_dense": ("k_tgemm", "// Table GEMMs with 64-entry tiles"),
     "far": ("k_far", "// Far field and the near-field reduction"),
 }
 
@@ -452,7 +454,7 @@ def main():
     # slice split), which this FP64 roofline does not describe
     single = [k for k in SINGLE_KERNEL_PHASES
               if args.precision == "fp64" or k not in ("near_lowrank", "near_dense")]
-    dom = max(single, key=lambda k: phases[k])
+    dom = max(single, key=lambda k: max(work[k][0] / (FP64_PEAK_TFLOPS * 1e12), work[k][1] / (HBM_PEAK_GBS * 1e9)))
     flops, nbytes = work[dom]
     sec = phases[dom] * 1e-3
     t_mfma = flops / (FP64_PEAK_TFLOPS * 1e12)

@@ -1260,12 +1260,16 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
     }
   }
   const double2 a0 = s[0];
-  double2 wl = make_double2(1.0, 0.0);
   const int NC = (P + 7) / 8;
+  // work-group z computes the outputs l = 8c .. 8c+7 (chunk c = blockIdx.z,
+  // a compile-time constant inside the matching branch)
+  static_for<0, (PM + 7) / 8>([&](auto cc) __attribute__((always_inline)) {
+    constexpr int c = decltype(cc)::value;
+    if (c != (int)blockIdx.z || c >= NC) return;
+    // w^(l-1) before output l: the same product sequence as a running power
+    double2 wl = make_double2(1.0, 0.0);
 #pragma unroll
-  for (int c = 0; c < (PM + 7) / 8; ++c) {
-    if (c >= NC) break;
-    __syncthreads();
+    for (int i = 1; i < 8 * c; ++i) wl = cmul(wl, w);
     // the eight outputs of the chunk accumulate side by side (k outer)
     double ur[8], ui[8];
 #pragma unroll
@@ -1311,7 +1315,7 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
       else
         part[(size_t)slot * P + l] = make_double2(re, im);
     }
-  }
+  });
 }
 
 // Multipoles of the split boxes: slices added in slice order.
@@ -1386,12 +1390,15 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
       pw = cmul(pw, w);
     }
   }
-  double2 ql = make_double2(1.0, 0.0);
   const int NC = (P + 7) / 8;
+  // work-group z computes the outputs l = 8c .. 8c+7 (chunk c = blockIdx.z)
+  static_for<0, (PM + 7) / 8>([&](auto cc) __attribute__((always_inline)) {
+    constexpr int c = decltype(cc)::value;
+    if (c != (int)blockIdx.z || c >= NC) return;
+    // q^l before output l: the same product sequence as a running power
+    double2 ql = make_double2(1.0, 0.0);
 #pragma unroll
-  for (int c = 0; c < (PM + 7) / 8; ++c) {
-    if (c >= NC) break;
-    __syncthreads();
+    for (int i = 0; i < 8 * c; ++i) ql = cmul(ql, q);
     // the eight outputs of the chunk accumulate side by side (k outer)
     double ur[8], ui[8];
 #pragma unroll
@@ -1431,7 +1438,7 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
       }
       locf[(size_t)f * P + l] = v;
     }
-  }
+  });
 }
 
 // -------------------------------------------------------------------------
@@ -2090,7 +2097,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   if (!H.up_grp.empty()) {
     const int ng = (int)H.up_grp.size() / 5;
 #define VFX_UP(PMV, EX)                                                                                            \
-  hipLaunchKernelGGL((k_up<PMV, EX>), dim3(ng, R), dim3(64), 0, s, P, T.root_size, D.up_grp, D.up_box, D.up_ptr,  \
+  hipLaunchKernelGGL((k_up<PMV, EX>), dim3(ng, R, (P + 7) / 8), dim3(64), 0, s, P, T.root_size, D.up_grp, D.up_box, D.up_ptr,  \
                      D.up_src, D.up_pos, D.box_level, D.box_cx, D.box_cy, DT.pas_m2m_t, D.mpole, D.up_part, sMP,  \
                      sUP)
     if (P == 21)
@@ -2152,7 +2159,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   {
     const int ng = (int)H.dn_grp.size() - 1;
 #define VFX_DOWN(PMV, EX)                                                                                          \
-  hipLaunchKernelGGL((k_down<PMV, EX>), dim3(ng, R), dim3(64), 0, s, P, T.root_size, D.dn_grp, D.anc_ptr, D.anc,   \
+  hipLaunchKernelGGL((k_down<PMV, EX>), dim3(ng, R, (P + 7) / 8), dim3(64), 0, s, P, T.root_size, D.dn_grp, D.anc_ptr, D.anc,   \
                      D.anc_leaf, D.leaf_box, D.box_level, D.box_cx, D.box_cy, DT.pas_l2l_t, D.local, D.locf, sMP,  \
                      sLF)
     if (P == 21)
