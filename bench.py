@@ -397,7 +397,10 @@ def main():
                     help="many right-hand sides on one tree (workload starfish_batch): vfx_execute_batch")
     ap.add_argument("--trees", type=int, default=0,
                     help="many uneven trees (1e3-1e5 nodes) captured in one HIP graph, against eager launches")
-    ap.add_argument("--autotune", action="store_true", help="autotune the near-field launch parameters first")
+    ap.add_argument("--autotune", action="store_true", default=True,
+                    help="autotune the near-field launch parameters before the timed steps (default)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the library's default launch parameters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -425,6 +428,8 @@ def main():
     stream = torch.cuda.current_stream()
     for _ in range(max(args.warmup, 1)):
         plan.execute(fl, fc, fe, V, stream)
+    torch.cuda.synchronize()
+    choice = plan.autotune(1, fl, fc, fe, V, reps=5) if args.autotune else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -485,6 +490,7 @@ def main():
                    "precision": "fp64" if args.precision == "fp64" else
                    f"mixed: near field of sources at level >= {args.min_level} in bf16 slices, FP32 accumulation"},
         "phases_ms": {k: round(v, 4) for k, v in phases.items() if k != "count"},
+        "autotune": choice,
         "plan_s": st["plan_seconds"], "tables_s": case["t_ctx"], "plan_stage": plan_stage,
         "roofline": roof,
     }

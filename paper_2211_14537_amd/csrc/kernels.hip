@@ -1958,7 +1958,7 @@ static void m2p_gemm(int n, int kd, int P2, int ntiles, const int* cfg, const in
     case 16: VFX_M2P(KDV, 1); break;  \
     case 64: VFX_M2P(KDV, 4); break;  \
     case 144: VFX_M2P(KDV, 9); break; \
-    default: VFX_M2P(KDV, 8); break;  \
+    default: VFX_M2P(KDV, 4); break;  \
   }
   if (kd == 64) {
     VFX_M2P_N(64)
