@@ -397,10 +397,10 @@ def main():
                     help="many right-hand sides on one tree (workload starfish_batch): vfx_execute_batch")
     ap.add_argument("--trees", type=int, default=0,
                     help="many uneven trees (1e3-1e5 nodes) captured in one HIP graph, against eager launches")
-    ap.add_argument("--autotune", action="store_true", default=True,
-                    help="autotune the near-field launch parameters before the timed steps (default)")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="keep the library's default launch parameters")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the near-field launch parameters before the timed steps")
+    ap.add_argument("--launch", default=None,
+                    help="near-field launch parameters W,M (work-group cap, dense row tiles) instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -429,7 +429,12 @@ def main():
     for _ in range(max(args.warmup, 1)):
         plan.execute(fl, fc, fe, V, stream)
     torch.cuda.synchronize()
-    choice = plan.autotune(1, fl, fc, fe, V, reps=5) if args.autotune else None
+    if args.launch:
+        w_, m_ = (int(v) for v in args.launch.split(","))
+        plan.set_launch(w_, m_)
+        choice = {"near_wgs": w_, "dense_mtb": m_, "set": True}
+    else:
+        choice = plan.autotune(1, fl, fc, fe, V, reps=20) if args.autotune else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

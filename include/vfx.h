@@ -226,6 +226,13 @@ int vfx_execute_batch(vfx_plan* plan, int nrhs, const double* f_leaf, const doub
 int vfx_plan_autotune(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
                       double* V_out, void* stream, int reps, int32_t* choice);
 
+/* Set the same two launch parameters directly (for example the choice an
+ * earlier autotune made): the work-group cap of the persistent near-field
+ * kernels (1..65535; default 512, two work-groups per CU) and the row
+ * tiles per block of the dense near-field GEMM (4 or 8).  Results are
+ * bitwise independent of them.  VFX_EINVAL outside those ranges. */
+int vfx_plan_set_launch(vfx_plan* plan, int near_wgs, int dense_mtb);
+
 /* HIP graph capture of a sequence of executes, possibly of many plans
  * (many uneven trees in one launch): vfx_graph_begin starts a capture
  * on `stream`; vfx_execute / vfx_execute_batch calls on that stream are

@@ -255,6 +255,14 @@ int vfx_plan_autotune(vfx_plan* plan, int nrhs, const double* f_leaf, const doub
   return rc;
 }
 
+int vfx_plan_set_launch(vfx_plan* plan, int near_wgs, int dense_mtb) {
+  if (!plan || near_wgs < 1 || near_wgs > 65535 || (dense_mtb != 4 && dense_mtb != 8))
+    return fail(VFX_EINVAL, "vfx_plan_set_launch: near_wgs must be in 1..65535 and dense_mtb 4 or 8");
+  plan->p.tune.near_wgs = near_wgs;
+  plan->p.tune.dense_mtb = dense_mtb;
+  return VFX_OK;
+}
+
 struct vfx_graph {
   hipGraph_t g = nullptr;
   hipGraphExec_t e = nullptr;

@@ -223,7 +223,8 @@ struct Plan {
   static constexpr int kEvents = 13;
   // launch parameters chosen by vfx_plan_autotune
   struct Tune {
-    int near_wgs = 768;  // work-group cap of the persistent near-field kernels (3 per CU)
+    int near_wgs = 512;  // work-group cap of the persistent near-field kernels (2 per CU,
+                         // leaving room for the caller's stream beside them)
     int dense_mtb = 4;   // row tiles per block of the dense near-field GEMM (K = 16)
   } tune;
   bool timing = false;

@@ -54,7 +54,7 @@ EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points
             "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
             "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_execute_batch", "vfx_plan_create_ex",
             "vfx_plan_factor_gpu",
-            "vfx_plan_autotune", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
+            "vfx_plan_autotune", "vfx_plan_set_launch", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
             "vfx_mlp_param_count", "vfx_mlp_forward", "vfx_mlp_grad", "vfx_mlp_adam", "vfx_f32_to_f16",
             "vfx_mlp_infer_f16",
             "vfx_last_error",
@@ -92,6 +92,7 @@ def lib():
         L.vfx_plan_create_ex.argtypes = [vp, ctypes.POINTER(_Tree), ctypes.c_int, ctypes.POINTER(vp)]
         L.vfx_plan_factor_gpu.argtypes = [vp, vp]
         L.vfx_plan_autotune.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_int, i32p]
+        L.vfx_plan_set_launch.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.vfx_graph_begin.argtypes = [vp]
         L.vfx_graph_end.argtypes = [vp, ctypes.POINTER(vp)]
         L.vfx_graph_launch.argtypes = [vp, vp]
@@ -274,6 +275,10 @@ class Plan:
         _check(lib().vfx_plan_autotune(self._h, int(nrhs), *a, ctypes.c_void_p(st.cuda_stream), int(reps),
                                        _ptr(ch, ctypes.c_int32)))
         return {"near_wgs": int(ch[0]), "dense_mtb": int(ch[1])}
+
+    def set_launch(self, near_wgs, dense_mtb):
+        """Set the near-field launch parameters directly."""
+        _check(lib().vfx_plan_set_launch(self._h, int(near_wgs), int(dense_mtb)))
 
     def interp(self, V, px, py, out, stream=None):
         """Interpolate leaf-grid data V (n_leaves x K^2) to the points

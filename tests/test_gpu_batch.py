@@ -158,4 +158,9 @@ def test_autotune_keeps_results(gpu_device):
     case["plan"].execute_batch(2, FL, FC, FE, V)
     torch.cuda.synchronize()
     assert np.array_equal(V.cpu().numpy(), V0)
+    for w, m in ((1, 8), (37, 4), (4096, 8)):  # set directly: same results
+        case["plan"].set_launch(w, m)
+        case["plan"].execute_batch(2, FL, FC, FE, V)
+        torch.cuda.synchronize()
+        assert np.array_equal(V.cpu().numpy(), V0), (w, m)
     say(f"    autotune choice {ch}; results unchanged")
