@@ -182,3 +182,32 @@ def test_gpu_factorised_plan(gpu_device, name):
     w_h = _check_extension(case, fe_h, ref, info, 2.0)
     say(f"    {name}: GPU-factored worst error/bound {w:.3f} (host-factored {w_h:.3f})")
     assert np.array_equal(fe_d[tr["kind"] == 1], case["f_leaf"][tr["kind"] == 1])
+
+
+@pytest.mark.parametrize("K", [4, 12])
+def test_volume_parity_other_grids(gpu_device, K):
+    """K = 4 and 12 (K^2 not a multiple of 32: the near-field, P2L and P2M
+    tables go through the one-block-prefetch GEMM kernel, and the far field
+    holds 1 or 3 nodes per lane) on the adaptive disk tree, given data."""
+    from oracle import geometry
+    from paper_2211_14537_amd import tree as T
+    from paper_2211_14537_amd import vfx
+    from workloads import get_config
+    say(f"[volume parity] disk_adaptive_small K={K} p=30")
+    cfg = get_config("disk_adaptive_small")
+    cfg["K"] = K
+    ctx = vfx.Context(K, 30, root=cfg["root"])
+    tr = T.build_tree(cfg, ctx.stencil_points())
+    f_leaf, _ = T.sample_inputs(cfg, tr, ctx.stencil_points())
+    kind = np.ones_like(tr["kind"])
+    plan = vfx.Plan(ctx, tr["level"], tr["ix"], tr["iy"], kind)
+    ot = geometry.Tree(tr["level"], tr["ix"], tr["iy"], cfg["root"])
+    case = dict(cfg=cfg, K=K, ctx=ctx, tree=tr, f_leaf=f_leaf, f_cut=np.zeros((0, ctx.n_stencil)), plan=plan,
+                otree=ot, kind=kind)
+    fe, V = run_gpu(case)
+    assert np.array_equal(fe, f_leaf)
+    sel, tx, ty = sample_targets(case, 300, leaves=(0, ot.n - 1))
+    vo = oracle_potential(case, f_leaf, tx, ty)
+    rel = np.abs(V.ravel()[sel] - vo).max() / np.abs(vo).max()
+    say(f"    {len(tr['level'])} leaves, rel Linf = {rel:.3e} over {sel.size} nodes")
+    assert rel <= 1e-10
