@@ -517,8 +517,10 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
 }
 
 // -------------------------------------------------------------------------
-// Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M, M2P).
-// Entries (pairs) are grouped by table configuration c; a work-group takes a
+// Batched table GEMMs on the FP64 matrix cores (near field, P2L, P2M, M2P)
+// for contraction lengths that are not a multiple of 32 (K = 4 and 12, whose
+// K^2 is 16 and 144); the others run on k_tgemm below, which has a deeper
+// pipeline.  Entries (pairs) are grouped by table configuration c; a work-group takes a
 // tile of <= TE entries (64 or 16) of one configuration and a block of MTB
 // row tiles (16 table rows each) and computes, for every entry e,
 //   Y[e][row] = sum_k A_c[k][row] X[src(e)][k]
@@ -1968,8 +1970,6 @@ static void m2p_gemm(int n, int kd, int P2, int ntiles, const int* cfg, const in
 #undef VFX_M2P_N
 #undef VFX_M2P
 }
-
-constexpr int kNearWgs = 512;
 
 int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut, double* fe, double* V,
                    hipStream_t s, std::string& err) {
