@@ -594,13 +594,17 @@ int build_host_plan(const Tables& T, const vfx_tree* tree, HostPlan& H, std::str
         H.t3_count.push_back(std::min(64, cnt[c + 1] - f));
       }
   }
-  // P2M: every leaf, one configuration
-  H.leaf_ids.resize(L);
-  for (int i = 0; i < L; ++i) H.leaf_ids[i] = i;
-  for (int f = 0; f < L; f += 64) {
+  // P2M: every leaf with possibly nonzero data, one configuration
+  // (a leaf whose data vanish identically is no source of anything, so its
+  // multipole is neither formed nor read)
+  H.leaf_ids.clear();
+  for (int i = 0; i < L; ++i)
+    if (!zero_leaf[i]) H.leaf_ids.push_back(i);
+  const int NL0 = (int)H.leaf_ids.size();
+  for (int f = 0; f < NL0; f += 64) {
     H.t0_cfg.push_back(0);
     H.t0_first.push_back(f);
-    H.t0_count.push_back(std::min(64, L - f));
+    H.t0_count.push_back(std::min(64, NL0 - f));
   }
 
   // ---- per-cut-leaf pseudo-inverses --------------------------------------
