@@ -1068,8 +1068,10 @@ __device__ __forceinline__ void mx_bfrag(const uint16_t* sb, int r, vfx_s8 b[3])
 // Phase 1: acc[r] = (this lane's pair row of X) . (B rows 16r..16r+15),
 // r < MT1 (compile-time), over n = 256 contraction values in 8 blocks of 32;
 // B from `wbase` ([s][row][256], slice stride wslice, rows row0..), staged
-// through the double buffer sbuf; the A fragments come straight from the
-// pair's bf16 slices (they are this wave's own rows).
+// through a ring of two register blocks into the double buffer sbuf; the A
+// fragments (this wave's own rows) come straight from the pair's bf16
+// slices into a ring of three register blocks.  Every global load is issued
+// two compute phases before its data is needed.
 template <int MT1>
 __device__ __forceinline__ void mx_phase1(const uint16_t* __restrict__ xrow, long xs_slice,
                                           const uint16_t* __restrict__ wbase, size_t wslice, int row0,
@@ -1077,31 +1079,38 @@ __device__ __forceinline__ void mx_phase1(const uint16_t* __restrict__ xrow, lon
   constexpr int n = 256, NKB = n / 32;
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc[r] = vfx_f4{0, 0, 0, 0};
-  MxStage st;
-  vfx_s8 a[2][3];
-  mx_gload(st, wbase, wslice, n, row0, 0, 16 * MT1);
+  MxStage st[2];
+  vfx_s8 a[3][3];
+  auto ga = [&](auto kbc, auto slc) __attribute__((always_inline)) {
+    constexpr int kb = decltype(kbc)::value, sl = decltype(slc)::value;
 #pragma unroll
-  for (int s = 0; s < 3; ++s) a[0][s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice);
+    for (int s = 0; s < 3; ++s) a[sl][s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice + 32 * kb);
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  ga(I0{}, I0{});
+  mx_gload(st[0], wbase, wslice, n, row0, 0, 16 * MT1);
+  ga(I1{}, I1{});
+  mx_gload(st[1], wbase, wslice, n, row0, 32, 16 * MT1);
   __syncthreads();  // the previous user of sbuf is done
-  mx_lstore(st, sbuf);
+  mx_lstore(st[0], sbuf);
   __syncthreads();
-  for (int kb = 0; kb < NKB; ++kb) {
-    const int q = kb & 1;
-    if (kb + 1 < NKB) {
-      mx_gload(st, wbase, wslice, n, row0, 32 * (kb + 1), 16 * MT1);
-#pragma unroll
-      for (int s = 0; s < 3; ++s) a[q ^ 1][s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice + 32 * (kb + 1));
+  static_for<0, NKB>([&](auto kbc) __attribute__((always_inline)) {
+    constexpr int kb = decltype(kbc)::value;
+    if constexpr (kb + 2 < NKB) {
+      ga(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, (kb + 2) % 3>{});
+      mx_gload(st[kb % 2], wbase, wslice, n, row0, 32 * (kb + 2), 16 * MT1);
     }
-    const uint16_t* sb = sbuf + q * kMxBuf;
+    const uint16_t* sb = sbuf + (kb % 2) * kMxBuf;
 #pragma unroll
     for (int r = 0; r < MT1; ++r) {
       vfx_s8 b[3];
       mx_bfrag(sb, r, b);
-      acc[r] = mfma_x3(a[q], b, acc[r]);
+      acc[r] = mfma_x3(a[kb % 3], b, acc[r]);
     }
-    if (kb + 1 < NKB) mx_lstore(st, sbuf + (q ^ 1) * kMxBuf);
+    if constexpr (kb + 1 < NKB) mx_lstore(st[(kb + 1) % 2], sbuf + ((kb + 1) % 2) * kMxBuf);
     __syncthreads();
-  }
+  });
 }
 
 // One work item: a tile of <= 64 pairs of one configuration (wave w owns
