@@ -981,8 +981,9 @@ __global__ void __launch_bounds__(256, 3) k_near_lr(int nitems, const int* __res
 // slices, x ~ x0 + x1 + x2 (about 24 significant bits); a product keeps the
 // six slice pairs down to order 2^-24, x0 y0 + x0 y1 + x1 y0 + x0 y2 +
 // x1 y1 + x2 y0, on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) with
-// FP32 accumulation, and results are written as FP64 (the far-field kernel
-// sums them with the FP64 terms in FP64).  MFMA operands are loaded straight
+// FP32 accumulation.  Results are stored as they were accumulated, in FP32
+// (half the bytes of the FP64 pairs' results); the far-field kernel widens
+// them and sums them with the FP64 terms in FP64.  MFMA operands are loaded straight
 // from memory: a lane's eight consecutive contraction values are 16
 // contiguous bytes (tables stored contraction-fastest).
 // v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16]
@@ -1124,7 +1125,7 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
                                                  const int* __restrict__ src, const int* __restrict__ lr_R,
                                                  const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ Qb,
                                                  const uint16_t* __restrict__ xs, long xs_slice,
-                                                 double* __restrict__ Y, long sy) {
+                                                 float* __restrict__ Y, long sy) {
   xs += blockIdx.y * 3 * xs_slice;  // right-hand side blockIdx.y
   Y += blockIdx.y * sy;
   constexpr int n = 256, LM = kNearLrMax, LDZ = LM + 4;
@@ -1161,7 +1162,7 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int pe = 16 * w + 4 * lk + e;
-          if (pe < np) Y[(size_t)(p0 + pe) * n + 64 * rb + 16 * r + li] = (double)acc[r][e];
+          if (pe < np) Y[(size_t)(p0 + pe) * n + 64 * rb + 16 * r + li] = acc[r][e];
         }
       continue;
     }
@@ -1219,7 +1220,7 @@ __global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int*
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int pe = 16 * w + 4 * lk + e;
-        if (pe < np) Y[(size_t)(p0 + pe) * n + 16 * r + li] = (double)acc2[r][e];
+        if (pe < np) Y[(size_t)(p0 + pe) * n + 16 * r + li] = acc2[r][e];
       }
   }
 }
@@ -1477,11 +1478,13 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
                                             const double2* __restrict__ locf, const double2* __restrict__ mpole,
                                             const int* __restrict__ l1_ptr, const int* __restrict__ l1_srcbox,
                                             const int* __restrict__ l1_slot, const double* __restrict__ Y,
-                                            double* __restrict__ V, long slf, long smp, long sny, long sy3, long sv) {
+                                            const float* __restrict__ Y32, double* __restrict__ V, long slf,
+                                            long smp, long sny, long sy3, long sv) {
   const int P = EXACT ? PM : Prt;  // <= 64
   locf += blockIdx.y * slf;        // right-hand side blockIdx.y
   mpole += blockIdx.y * smp;
   Y += blockIdx.y * sny;
+  Y32 += blockIdx.y * sny;
   Y3 += blockIdx.y * sy3;
   V += blockIdx.y * sv;
   const int n = K * K;
@@ -1514,9 +1517,16 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
     for (int j = 0; j < NPL; ++j) yn[j] = y3[j] = 0.0;
 #pragma unroll 4
     for (int e = 0; e < n1; ++e) {
-      const double* y = Y + (size_t)__builtin_amdgcn_readlane(my_slot, e) * n;
+      const int sl = __builtin_amdgcn_readlane(my_slot, e);
+      if (sl >= 0) {
+        const double* y = Y + (size_t)sl * n;
 #pragma unroll
-      for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
+        for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
+      } else {  // a pair applied in mixed precision: FP32 result
+        const float* y = Y32 + (size_t)(-1 - sl) * n;
+#pragma unroll
+        for (int j = 0; j < NPL; ++j) yn[j] += (double)y[node[j]];
+      }
       lg += readlane_d(my_a0, e);
     }
 #pragma unroll 4
@@ -1739,11 +1749,12 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   const Tables& T = p->ctx->T;
   const size_t P = T.p + 1, R = (size_t)nrhs;
   if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
-  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y};
+  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.near_y32};
   for (void* q : old)
     if (q) (void)hipFree(q);
   D.mpole = D.local = D.up_part = D.locf = nullptr;
   D.near_y = D.p2l_y = D.m2p_y = nullptr;
+  D.near_y32 = nullptr;
   D.xs = nullptr;
   D.cap = 0;
   VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P * R));
@@ -1755,6 +1766,8 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P * R));
   VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P * R));
   if (H.precision == 1) VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 3 * (size_t)H.L * T.n * R));
+  if (H.precision == 1 && !H.np_src.empty())
+    VFX_HIP(hipMalloc((void**)&D.near_y32, sizeof(float) * H.np_src.size() * T.n * R));
   D.cap = nrhs;
   return VFX_OK;
 }
@@ -1867,7 +1880,7 @@ void free_plan_device(Plan* p) {
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
                   D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg, D.fac_ws,
                   D.ml_first,  D.ml_count,   D.xs,       D.p3_src,   D.l3_slot,  D.t3_cfg,   D.t3_first,
-                  D.t3_count,  D.m2p_y};
+                  D.t3_count,  D.m2p_y,    D.near_y32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -2083,7 +2096,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
       const int items = (int)H.ml_cfg.size();
       hipLaunchKernelGGL(k_near_mx<true>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
                          1, D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs, total,
-                         D.near_y, sNY);
+                         D.near_y32, sNY);
     }
   }
   VFX_HIP(hipGetLastError());
@@ -2094,7 +2107,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
     const int items = 4 * (int)H.mt_cfg.size();
     hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items, 4,
                        D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
-                       D.near_y, sNY);
+                       D.near_y32, sNY);
   }
   VFX_HIP(hipGetLastError());
   MARK(7, p->side);
@@ -2192,7 +2205,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
 #define VFX_FAR(PMV, EX, NPLV)                                                                                 \
   hipLaunchKernelGGL((k_far<PMV, EX, NPLV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,          \
                      D.box_level, DT.t, D.l3_ptr, D.l3_src, D.l3_slot, D.m2p_y, D.locf, D.mpole, D.l1_ptr,         \
-                     D.l1_srcbox, D.l1_slot, D.near_y, V, sLF, sMP, sNY, sM3, sFL)
+                     D.l1_srcbox, D.l1_slot, D.near_y, D.near_y32, V, sLF, sMP, sNY, sM3, sFL)
 #define VFX_FAR_N(PMV, EX)  \
   if (npl == 4)             \
     VFX_FAR(PMV, EX, 4);    \

@@ -80,7 +80,8 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
       const int s = pos[2 * H.l1_cfg[e] + (mixed(H.l1_src[e]) ? 1 : 0)]++;
       H.np_src[s] = H.l1_src[e];
       H.np_tgt[s] = leaf;
-      H.l1_slot[e] = s;
+      // a mixed pair's result lives in the FP32 partials: slot -1 - s
+      H.l1_slot[e] = mixed(H.l1_src[e]) ? -1 - s : s;
     }
   for (auto* v : {&H.nt_cfg, &H.nt_first, &H.nt_count, &H.nl_cfg, &H.nl_first, &H.nl_count, &H.mt_cfg,
                   &H.mt_first, &H.mt_count, &H.ml_cfg, &H.ml_first, &H.ml_count})

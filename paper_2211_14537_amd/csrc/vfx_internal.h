@@ -197,6 +197,7 @@ struct DevicePlan {
   bool factored = false;   // pinv_val holds the P_i
   double* fac_ws = nullptr;  // scratch of the GPU factorisation
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
+  float* near_y32 = nullptr;  // the same for the pairs applied in mixed precision (FP32 results)
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
   double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
