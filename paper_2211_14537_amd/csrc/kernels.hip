@@ -1463,6 +1463,8 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
 // expansion, the list slots) comes in with one vector load, lane k holding
 // item k, and is broadcast with readlane, so no step waits on a chain of
 // scalar loads.  One wave per leaf keeps the whole grid resident at once.
+// With MX, a negative list-1 slot -1 - s names a pair applied in mixed
+// precision, whose products are read from the FP32 buffer and widened.
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)u, l);
@@ -1470,7 +1472,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <int PM, bool EXACT, int NPL>
+template <int PM, bool EXACT, int NPL, bool MX>
 __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, const int* __restrict__ leaf_box,
                                             const int* __restrict__ box_level, const double* __restrict__ t,
                                             const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
@@ -1484,7 +1486,7 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
   locf += blockIdx.y * slf;        // right-hand side blockIdx.y
   mpole += blockIdx.y * smp;
   Y += blockIdx.y * sny;
-  Y32 += blockIdx.y * sny;
+  if (MX) Y32 += blockIdx.y * sny;
   Y3 += blockIdx.y * sy3;
   V += blockIdx.y * sv;
   const int n = K * K;
@@ -1518,7 +1520,7 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
 #pragma unroll 4
     for (int e = 0; e < n1; ++e) {
       const int sl = __builtin_amdgcn_readlane(my_slot, e);
-      if (sl >= 0) {
+      if (!MX || sl >= 0) {
         const double* y = Y + (size_t)sl * n;
 #pragma unroll
         for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
@@ -2202,18 +2204,21 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(8, s);
-#define VFX_FAR(PMV, EX, NPLV)                                                                                 \
-  hipLaunchKernelGGL((k_far<PMV, EX, NPLV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,          \
+#define VFX_FAR(PMV, EX, NPLV, MXV)                                                                            \
+  hipLaunchKernelGGL((k_far<PMV, EX, NPLV, MXV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,          \
                      D.box_level, DT.t, D.l3_ptr, D.l3_src, D.l3_slot, D.m2p_y, D.locf, D.mpole, D.l1_ptr,         \
                      D.l1_srcbox, D.l1_slot, D.near_y, D.near_y32, V, sLF, sMP, sNY, sM3, sFL)
-#define VFX_FAR_N(PMV, EX)  \
-  if (npl == 4)             \
-    VFX_FAR(PMV, EX, 4);    \
-  else if (npl == 3)        \
-    VFX_FAR(PMV, EX, 3);    \
-  else                      \
-    VFX_FAR(PMV, EX, 1);
+#define VFX_FAR_N(PMV, EX)      \
+  if (npl == 4 && mx)           \
+    VFX_FAR(PMV, EX, 4, true);  \
+  else if (npl == 4)            \
+    VFX_FAR(PMV, EX, 4, false); \
+  else if (npl == 3)            \
+    VFX_FAR(PMV, EX, 3, false); \
+  else                          \
+    VFX_FAR(PMV, EX, 1, false);
   const int npl = (n + 63) / 64;  // 1, 3 or 4 for K = 4, 8, 12, 16
+  const bool mx = D.near_y32 != nullptr;  // some pairs' results are FP32 (K = 16 only)
   if (P == 21) {
     VFX_FAR_N(21, true)
   } else if (P == 25) {
