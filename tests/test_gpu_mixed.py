@@ -25,7 +25,7 @@ def test_mixed_volume_against_oracle(gpu_device):
     _, V64 = run_gpu(case)
     e64 = _rel(case, V64, sel, vo)
     errs = {}
-    for lmin in (0, 5):
+    for lmin in (0, 3, 4):  # the tree's leaves reach level 4
         case["plan"].set_precision(1, lmin)
         fe, V = run_gpu(case)
         assert np.array_equal(fe, case["f_leaf"])
@@ -36,7 +36,28 @@ def test_mixed_volume_against_oracle(gpu_device):
     assert np.array_equal(Vb, V64)  # back to FP64: bitwise the FP64 result
     assert e64 <= 1e-11
     assert errs[0] <= 2e-6
-    assert errs[5] <= errs[0] * 1.01 + 1e-15
+    assert int(np.max(case["tree"]["level"])) == 4
+    for lmin in (3, 4):
+        assert e64 < errs[lmin] <= errs[0] * 1.01 + 1e-15
+
+
+def test_mixed_mode_with_no_mixed_pair_is_bitwise_fp64(gpu_device):
+    """Mode 1 with a level threshold below every leaf mixes no list-1 pair:
+    the pairs keep the FP64 tiles and kernels, and the far-field variant of
+    mixed plans (which tells FP64 from FP32 pair results by the sign of the
+    slot) must then sum them exactly as the FP64 plan does, bit for bit;
+    with one more level of threshold the two paths differ."""
+    case = setup("starfish_small", p=24, all_regular=True)
+    lv = int(np.max(case["tree"]["level"]))
+    _, V64 = run_gpu(case)
+    case["plan"].set_precision(1, lv + 1)
+    _, V = run_gpu(case)
+    assert np.array_equal(V, V64)
+    case["plan"].set_precision(1, lv)
+    _, Vf = run_gpu(case)
+    d = float(np.abs(Vf - V64).max() / np.abs(V64).max())
+    say(f"    mixed only at level {lv}: rel Linf vs FP64 path {d:.3e}")
+    assert 0 < d <= 2e-6
 
 
 def test_mixed_end_to_end(gpu_device):
