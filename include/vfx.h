@@ -174,6 +174,20 @@ int vfx_mlp_infer_f16(const uint16_t* theta_h, const uint16_t* x_h, int64_t batc
 int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, const double* py, double* out,
                void* stream);
 
+/* Net charge A^e = integral of f^e over the tree, per right-hand side: the
+ * coefficient of the log|x| growth of the volume potential, which the
+ * exterior problem's boundary solve offsets in its constraint on the
+ * densities (\S6, the exterior problem).  Each leaf contributes h^2 times
+ * the tensor first-kind Chebyshev (Fejer) rule of the unit square applied to
+ * its K x K samples.  fe: device, nrhs x n_leaves x K^2 as vfx_execute(_batch)
+ * writes it; out: device, nrhs doubles (written).  The sum runs over a fixed
+ * partition of the leaves, so the result is bitwise repeatable.  Asynchronous
+ * on `stream`; the plan keeps a buffer of 256 partial sums per right-hand
+ * side, allocated by the first call that needs it (under stream capture that
+ * call must already have happened).  VFX_EINVAL for null pointers or
+ * nrhs < 1. */
+int vfx_net_charge(vfx_plan* plan, const double* fe, int nrhs, double* out, void* stream);
+
 /* Precision of the near field.  mode 0: FP64
  * everywhere (the default).  mode 1: the list-1 interactions whose source
  * leaf is at level >= min_level are applied with the operands split into

@@ -97,3 +97,22 @@ def potential(tree, fe, K, tx, ty, sources=None, **kw):
     idx = idx[np.any(fe[idx] != 0.0, axis=1)]
     coef = leaf_coefficients(fe[idx], K)
     return potential_boxes(tx, ty, cx[idx], cy[idx], h[idx], coef, K, **kw)
+
+
+def net_charge(tree, fe, K):
+    """Net charge A^e = int f^e over the leaves of ``tree`` (Section 6, the
+    exterior problem: the volume potential of f^e grows like A^e log|x|).
+    Each leaf integrates its tensor Chebyshev interpolant exactly: the
+    K-point first-kind (Fejer) rule in each variable, mapped from [-1,1]^2 to
+    the leaf of side h (Jacobian (h/2)^2).  fe has shape (L, K*K), or
+    (nrhs, L, K*K); the leaf contributions are summed exactly rounded."""
+    import math
+    w = cheb.fejer1_weights(K)
+    W = np.outer(w, w).ravel()
+    h = tree.h()
+    fe = np.asarray(fe, dtype=np.float64).reshape(-1, tree.n, K * K)
+    out = []
+    for r in range(fe.shape[0]):
+        per_leaf = (0.5 * h) ** 2 * (fe[r] @ W)
+        out.append(math.fsum(per_leaf.tolist()))
+    return np.array(out)

@@ -333,6 +333,24 @@ int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, 
   return VFX_OK;
 }
 
+int vfx_net_charge(vfx_plan* plan, const double* fe, int nrhs, double* out, void* stream) {
+  if (!plan || !fe || !out || nrhs < 1) return fail(VFX_EINVAL, "vfx_net_charge: null argument or nrhs < 1");
+  vfx::Plan& p = plan->p;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive &&
+      (!p.ctx->D.ready || !p.D.ready || nrhs > p.D.chg_cap))
+    return fail(VFX_EINVAL, "vfx_net_charge: under stream capture the plan must already hold device data for this "
+                            "many right-hand sides (call it once before capturing)");
+  try {
+    std::string err;
+    int rc = vfx::launch_net_charge(&p, fe, nrhs, out, (hipStream_t)stream, err);
+    if (rc) return fail(rc, "vfx_net_charge: " + err);
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_net_charge: out of host memory");
+  }
+  return VFX_OK;
+}
+
 int vfx_mlp_param_count(void) { return vfx::mlp_param_count(); }
 
 int64_t vfx_mlp_grad_work(int64_t batch) { return batch > 0 ? (int64_t)vfx::mlp_grad_work((long)batch) : 0; }

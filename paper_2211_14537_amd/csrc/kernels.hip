@@ -1652,6 +1652,87 @@ int launch_interp(Plan* p, const double* V, long npts, const double* px, const d
 }
 
 // -------------------------------------------------------------------------
+// Net charge A^e = integral of f^e over the tree (Section 6, exterior
+// problem: the volume potential then grows like A^e log|x|, which the
+// boundary solve must offset).  Each leaf contributes h^2 sum_j w_j f_j with
+// w the tensor first-kind Chebyshev (Fejer) weights of the unit square.  Two
+// passes with a fixed partition, so the sum order depends on the tree only:
+// block b of right-hand side r sums the nodes of leaves [b L/G, (b+1) L/G)
+// (each thread a strided share, then a fixed LDS tree) into part[r G + b];
+// one block per right-hand side then sums its G partials the same way.
+constexpr int kChargeBlocks = 256;
+
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+__global__ void __launch_bounds__(256) k_charge_part(int n, int L, int G, double root_size,
+                                                     const int* __restrict__ leaf_box, const int* __restrict__ box_level,
+                                                     const double* __restrict__ w2, const double* __restrict__ fe,
+                                                     long sfe, double* __restrict__ part) {
+  __shared__ double red[256];
+  fe += blockIdx.y * sfe;
+  const int b = blockIdx.x;
+  const long l0 = (long)b * L / G, l1 = (long)(b + 1) * L / G;
+  double acc = 0.0;
+  for (long i = l0 * n + threadIdx.x; i < l1 * n; i += 256) {
+    const int leaf = (int)(i / n), j = (int)(i - (long)leaf * n);
+    const double h = box_side(root_size, box_level[leaf_box[leaf]]);
+    acc += h * h * w2[j] * fe[i];
+  }
+  const double s = block_sum_256(acc, red);
+  if (threadIdx.x == 0) part[(size_t)blockIdx.y * G + b] = s;
+}
+
+__global__ void __launch_bounds__(256) k_charge_sum(int G, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[256];
+  const double v = threadIdx.x < G ? part[(size_t)blockIdx.x * G + threadIdx.x] : 0.0;
+  const double s = block_sum_256(v, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err) {
+  Context* c = p->ctx;
+  const Tables& T = c->T;
+  if (!c->D.ready) {
+    int rc = upload_tables(c, err);
+    if (rc) return rc;
+  }
+  if (!p->D.ready) {
+    int rc = upload_plan(p, err);
+    if (rc) return rc;
+  }
+  DevicePlan& D = p->D;
+  const int L = p->H.L, n = T.n;
+  const int G = std::min(L, kChargeBlocks);
+  if (nrhs > D.chg_cap) {
+    if (D.chg_part) {
+      VFX_HIP(hipDeviceSynchronize());  // no earlier call of this plan in flight
+      VFX_HIP(hipFree(D.chg_part));
+      D.chg_part = nullptr;
+      D.chg_cap = 0;
+    }
+    VFX_HIP(hipMalloc((void**)&D.chg_part, sizeof(double) * kChargeBlocks * (size_t)nrhs));
+    D.chg_cap = nrhs;
+  }
+  if (G > 0)
+    hipLaunchKernelGGL(k_charge_part, dim3(G, nrhs), dim3(256), 0, s, n, L, G, T.root_size, D.leaf_box,
+                       D.box_level, c->D.w2, fe, (long)L * n, D.chg_part);
+  VFX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_charge_sum, dim3(nrhs), dim3(256), 0, s, G, D.chg_part, out);
+  VFX_HIP(hipGetLastError());
+  return VFX_OK;
+}
+
+// -------------------------------------------------------------------------
 template <typename T>
 static int upload(T** dst, const T* src, size_t count, std::string& err) {
   *dst = nullptr;
@@ -1882,7 +1963,7 @@ void free_plan_device(Plan* p) {
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
                   D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg, D.fac_ws,
                   D.ml_first,  D.ml_count,   D.xs,       D.p3_src,   D.l3_slot,  D.t3_cfg,   D.t3_first,
-                  D.t3_count,  D.m2p_y,    D.near_y32};
+                  D.t3_count,  D.m2p_y,    D.near_y32, D.chg_part};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();

@@ -203,6 +203,8 @@ struct DevicePlan {
   double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
   int *p3_src = nullptr, *l3_slot = nullptr, *t3_cfg = nullptr, *t3_first = nullptr, *t3_count = nullptr;
   double* m2p_y = nullptr;   // per-entry M2P values at the target nodes, n_list3 x n
+  double* chg_part = nullptr;  // net-charge block partials, kChargeBlocks x chg_cap
+  int chg_cap = 0;
   int *cut_leaf = nullptr, *ext_ptr = nullptr, *ext_tgt = nullptr, *pinv_ptr = nullptr;
   double* ext_geo = nullptr;
   uint16_t* pinv_idx = nullptr;
@@ -248,6 +250,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
 int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err);
 int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
                   hipStream_t s, std::string& err);
+int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
 
 // mlp.hip (refinement classifier)
 int mlp_param_count();

@@ -175,3 +175,38 @@ def test_laplacian_of_potential_is_density():
     lapv = cheb.eval2d(lap, np.array([0.0]), np.array([0.0]))[0]
     f0 = cheb.eval2d(c, np.array([0.0]), np.array([0.0]))[0]
     assert abs(lapv - f0) < 1e-6 * max(1.0, abs(f0))
+
+
+def test_net_charge_closed_forms():
+    """The oracle's net charge (integral of the leaf data over the tree):
+    f = 1 gives the root's area; f = x^3 y^2 (degree below K in each
+    variable, so every leaf interpolant is f itself) gives the product of
+    the one-dimensional integrals; a Gaussian gives its erf closed form up
+    to the leaf interpolation error; two right-hand sides are summed apart."""
+    t = small_adaptive_tree()
+    K = 6
+    X, Y = t.leaf_nodes(K)
+    x0, x1 = t.cx0 - 0.5 * t.size, t.cx0 + 0.5 * t.size
+    y0, y1 = t.cy0 - 0.5 * t.size, t.cy0 + 0.5 * t.size
+    one = volume.net_charge(t, np.ones_like(X), K)
+    assert abs(one[0] - t.size ** 2) <= 1e-15 * t.size ** 2
+    poly = volume.net_charge(t, X ** 3 * Y ** 2, K)[0]
+    exact = (x1 ** 4 - x0 ** 4) / 4 * (y1 ** 3 - y0 ** 3) / 3
+    assert abs(poly - exact) <= 1e-14 * abs(exact)
+    # x^K is not integrated exactly by the rule on one leaf: the check is sharp
+    bad = volume.net_charge(t, X ** (2 * K), K)[0]
+    assert abs(bad - (x1 ** (2 * K + 1) - x0 ** (2 * K + 1)) / (2 * K + 1) * t.size) > 1e-10
+    # a Gaussian on a finer uniform tree (K = 16, level 3)
+    lv = np.full(64, 3)
+    ix, iy = np.divmod(np.arange(64), 8)
+    u = geometry.Tree(lv, ix, iy, (0.0, 0.0, 2.0))
+    K = 16
+    X, Y = u.leaf_nodes(K)
+    cx, cy, beta = 0.13, -0.21, 0.05
+    g = np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / beta)
+    sb = math.sqrt(beta)
+    ex = math.sqrt(math.pi) * sb / 2 * (math.erf((1 - cx) / sb) - math.erf((-1 - cx) / sb))
+    ey = math.sqrt(math.pi) * sb / 2 * (math.erf((1 - cy) / sb) - math.erf((-1 - cy) / sb))
+    two = volume.net_charge(u, np.stack([g, -2.0 * g]), K)
+    assert abs(two[0] - ex * ey) <= 1e-12 * ex * ey
+    assert two[1] == -2.0 * two[0]  # scaling by 2 is exact
