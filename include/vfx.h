@@ -329,6 +329,9 @@ int vfx_plan_lists(const vfx_plan* plan, int which, int32_t* ptr, int32_t* src, 
 int vfx_plan_boxes(const vfx_plan* plan, int32_t* level, int32_t* ix, int32_t* iy, int32_t* leaf);
 
 const char* vfx_last_error(void);
+/* Fixed name of a status code ("VFX_OK", "VFX_EINVAL", ...; "unknown status"
+ * for any other value).  The returned string is static; never fails. */
+const char* vfx_status_string(int status);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,17 @@ extern "C" {
 
 const char* vfx_last_error(void) { return g_err.c_str(); }
 
+const char* vfx_status_string(int status) {
+  switch (status) {
+    case VFX_OK: return "VFX_OK";
+    case VFX_EINVAL: return "VFX_EINVAL (bad argument)";
+    case VFX_ETREE: return "VFX_ETREE (tree not a balanced quad-tree partition, or extension restriction violated)";
+    case VFX_EHIP: return "VFX_EHIP (HIP runtime error)";
+    case VFX_ENOMEM: return "VFX_ENOMEM (allocation failed)";
+    default: return "unknown status";
+  }
+}
+
 int vfx_create(const vfx_params* prm, vfx_ctx** out) {
   if (!prm || !out) return fail(VFX_EINVAL, "vfx_create: null argument");
   *out = nullptr;

@@ -57,7 +57,7 @@ EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points
             "vfx_plan_autotune", "vfx_plan_set_launch", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
             "vfx_mlp_param_count", "vfx_mlp_forward", "vfx_mlp_grad", "vfx_mlp_adam", "vfx_f32_to_f16",
             "vfx_mlp_infer_f16",
-            "vfx_last_error",
+            "vfx_last_error", "vfx_status_string",
             "vfx_debug_table", "vfx_plan_lists", "vfx_plan_boxes")
 
 
@@ -108,11 +108,13 @@ def lib():
         L.vfx_mlp_infer_f16.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
         L.vfx_plan_timings.argtypes = [vp, dp, ctypes.c_int]
         L.vfx_last_error.restype = ctypes.c_char_p
+        L.vfx_status_string.restype = ctypes.c_char_p
+        L.vfx_status_string.argtypes = [ctypes.c_int]
         L.vfx_debug_table.argtypes = [vp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int64]
         L.vfx_plan_lists.argtypes = [vp, ctypes.c_int, i32p, i32p, i32p]
         L.vfx_plan_boxes.argtypes = [vp, i32p, i32p, i32p, i32p]
         for name in EXPORTED:
-            if name != "vfx_last_error":
+            if name not in ("vfx_last_error", "vfx_status_string"):
                 getattr(L, name).restype = ctypes.c_int
         L.vfx_mlp_grad_work.restype = ctypes.c_int64
         _lib = L
@@ -121,7 +123,7 @@ def lib():
 
 def _check(rc):
     if rc != VFX_OK:
-        raise VfxError(rc, lib().vfx_last_error().decode())
+        raise VfxError(rc, f"{lib().vfx_status_string(rc).decode()}: {lib().vfx_last_error().decode()}")
 
 
 def _ptr(a, t):

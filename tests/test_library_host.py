@@ -160,6 +160,17 @@ def test_extension_owner_matches_oracle(name):
     assert st["pinv_doubles"] == 66 * int(tr["mask"].sum())
 
 
+def test_status_strings():
+    L = vfx.lib()
+    for code, name in ((vfx.VFX_OK, b"VFX_OK"), (vfx.VFX_EINVAL, b"VFX_EINVAL"), (vfx.VFX_ETREE, b"VFX_ETREE"),
+                       (vfx.VFX_EHIP, b"VFX_EHIP"), (vfx.VFX_ENOMEM, b"VFX_ENOMEM")):
+        assert L.vfx_status_string(code).split(b" ")[0] == name
+    assert L.vfx_status_string(-99) == b"unknown status"
+    with pytest.raises(vfx.VfxError) as e:
+        vfx.Plan(vfx.Context(8, 20), [1, 1, 1], [0, 1, 0], [0, 0, 1], [1, 1, 1])
+    assert str(e.value).startswith("[-2] VFX_ETREE")
+
+
 def test_rejects_invalid_input():
     with pytest.raises(vfx.VfxError) as e:
         vfx.Context(1, 20)
