@@ -2020,8 +2020,9 @@ static void near_gemm(int n, int ntiles, const int* cfg, const int* first, const
 
 // P2L (EPI 0, TE 64) and P2M (EPI 1, TE 64) tables: rows padded to a
 // multiple of 64, so MT is 4 or 8; P2L takes them in one row block, P2M
-// (one tile per 64 leaves, few tiles) one row tile per work item on the
-// pipelined kernel, for more items in flight.
+// (one tile per 64 leaves, few tiles) two row tiles per work item on the
+// pipelined kernel, for more items in flight (one row tile per item rereads
+// the leaf data four times, four per item leaves most CUs idle).
 template <int EPI, int TE>
 static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int* first, const int* count,
                            const int* src, const double* A, const double* X, double* Y, hipStream_t s, unsigned R,
@@ -2031,7 +2032,7 @@ static void expansion_gemm(int n, int ntiles, int MT, const int* cfg, const int*
 #define VFX_EXP_CASE(KDV)                                                                                       \
   do {                                                                                                          \
     if (EPI == 1 && KDV % 32 == 0)                                                                              \
-      launch_gemm<KDV, EPI, TE, 1>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
+      launch_gemm<KDV, EPI, TE, 2>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
                                    R, sx, sy);                                                                  \
     else if (MT == 4)                                                                                           \
       launch_gemm<KDV, EPI, TE, 4>(ntiles, MT, cfg, first, count, src, A, X, Y, P2, root, leaf_box, box_level, s, 0, \
