@@ -405,7 +405,8 @@ def main():
                     help="also run one plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the path on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the library runs the path on one GPU (one plan per device); --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
