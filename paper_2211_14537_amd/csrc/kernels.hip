@@ -65,7 +65,7 @@ __global__ void k_fe_init(int n, int L, const int8_t* __restrict__ kind, const d
 // nodes, A_{Xbar,G} f_G elsewhere; A2), the total-order Chebyshev
 // coefficients (A3) and their values on the K x K nodes of every target
 // leaf.  Every global load whose address is known early is issued at the
-// start (two rounds: indices/geometry, then the data they point to), so the
+// start (two waves: indices/geometry, then the data they point to), so the
 // work-group's critical path holds few memory round trips.
 constexpr int kExtTgtMax = 16;  // targets whose geometry is staged in LDS
 
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256) k_extension(
   const int off = pinv_ptr[c], ni = pinv_ptr[c + 1] - off;
   const int e0 = ext_ptr[c], ne = ext_ptr[c + 1] - e0;
   const double* fc = f_cut + (size_t)c * nX;
-  // round 1: indices, flags, small tables, target geometry
+  // first load wave: indices, flags, small tables, target geometry
   int idx0 = tid < ni ? pinv_idx[off + tid] : 0;
   int idx1 = tid + 256 < ni ? pinv_idx[off + tid + 256] : 0;
   const bool given = tid < Kb2 && sbar_given[(size_t)c * Kb2 + tid];
@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_extension(
     s_geo[3 * tid + 1] = ext_geo[3 * (e0 + tid) + 1];
     s_geo[3 * tid + 2] = ext_geo[3 * (e0 + tid) + 2];
   }
-  // round 2: interior samples and the given Sbar-grid values
+  // second load wave: interior samples and the given Sbar-grid values
   if (tid < ni) s_fI[tid] = fc[idx0];
   if (tid + 256 < ni) s_fI[tid + 256] = fc[idx1];
   for (int q = tid + 512; q < ni; q += blockDim.x) s_fI[q] = fc[pinv_idx[off + q]];
