@@ -182,7 +182,7 @@ int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, 
  * its K x K samples.  fe: device, nrhs x n_leaves x K^2 as vfx_execute(_batch)
  * writes it; out: device, nrhs doubles (written).  The sum runs over a fixed
  * partition of the leaves, so the result is bitwise repeatable.  Asynchronous
- * on `stream`; the plan keeps a buffer of 256 partial sums per right-hand
+ * on `stream`; the plan keeps a buffer of 2048 partial sums per right-hand
  * side, allocated by the first call that needs it (under stream capture that
  * call must already have happened).  VFX_EINVAL for null pointers or
  * nrhs < 1. */

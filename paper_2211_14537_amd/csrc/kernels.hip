@@ -1659,8 +1659,11 @@ int launch_interp(Plan* p, const double* V, long npts, const double* px, const d
 // passes with a fixed partition, so the sum order depends on the tree only:
 // block b of right-hand side r sums the nodes of leaves [b L/G, (b+1) L/G)
 // (each thread a strided share, then a fixed LDS tree) into part[r G + b];
-// one block per right-hand side then sums its G partials the same way.
-constexpr int kChargeBlocks = 256;
+// one block per right-hand side then sums its G partials the same way
+// (thread t the partials t, t + 256, ... in order).  G is about L n / 2048
+// (eight samples per thread, enough loads in flight without flooding the
+// dispatcher with tiny blocks), at least 1 and at most min(L, 2048).
+constexpr int kChargeBlocks = 2048;
 
 __device__ __forceinline__ double block_sum_256(double v, double* red) {
   const int tid = threadIdx.x;
@@ -1694,7 +1697,8 @@ __global__ void __launch_bounds__(256) k_charge_part(int n, int L, int G, double
 
 __global__ void __launch_bounds__(256) k_charge_sum(int G, const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double red[256];
-  const double v = threadIdx.x < G ? part[(size_t)blockIdx.x * G + threadIdx.x] : 0.0;
+  double v = 0.0;
+  for (int q = threadIdx.x; q < G; q += 256) v += part[(size_t)blockIdx.x * G + q];
   const double s = block_sum_256(v, red);
   if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
@@ -1712,7 +1716,7 @@ int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStrea
   }
   DevicePlan& D = p->D;
   const int L = p->H.L, n = T.n;
-  const int G = std::min(L, kChargeBlocks);
+  const int G = std::min(L, (int)std::max(1L, std::min((long)kChargeBlocks, (long)L * n / 2048)));
   if (nrhs > D.chg_cap) {
     if (D.chg_part) {
       VFX_HIP(hipDeviceSynchronize());  // no earlier call of this plan in flight
