@@ -1,8 +1,8 @@
 """First-kind Chebyshev grids (test infrastructure; oracle only).
 
 The paper samples f on tensor-product Chebyshev grids of the first kind on
-every leaf (Section 4: "nodes of the first kind, which exclude the
-endpoints").  Plain definitions:
+every leaf (Section 4; first-kind nodes, so no node lies on a leaf edge).
+Plain definitions:
 
 * nodes  t_k = -cos((2k-1) pi / (2K)), k = 1..K  (ascending on (-1,1));
 * T_m(t) = cos(m arccos t);

@@ -31,41 +31,6 @@
 #define MAXQ 48
 #define MAXK 32
 
-static void gauss_legendre(int q, double *x, double *w) {
-  /* Newton iteration on the Legendre polynomial P_q */
-  for (int i = 0; i < (q + 1) / 2; ++i) {
-    long double z = cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (q + 0.5L));
-    long double dp = 1.0L;
-    for (int it = 0; it < 100; ++it) {
-      long double p0 = 1.0L, p1 = z;
-      for (int k = 2; k <= q; ++k) {
-        long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      if (q == 1) { p1 = z; p0 = 1.0L; }
-      dp = q * (z * p1 - p0) / (z * z - 1.0L);
-      long double dz = p1 / dp;
-      z -= dz;
-      if (fabsl(dz) < 1e-19L) break;
-    }
-    {
-      long double p0 = 1.0L, p1 = z;
-      for (int k = 2; k <= q; ++k) {
-        long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      dp = q * (z * p1 - p0) / (z * z - 1.0L);
-    }
-    x[i] = (double)(-z);
-    x[q - 1 - i] = (double)z;
-    double ww = (double)(2.0L / ((1.0L - z * z) * dp * dp));
-    w[i] = ww;
-    w[q - 1 - i] = ww;
-  }
-}
-
 typedef struct {
   int K;
   double cx, cy, h;
@@ -161,16 +126,15 @@ static long double near_pair(double tx, double ty, const box_t *b, int M, int q,
 /*
  * targets: nt points (tx, ty).  boxes: nb boxes with centres, sides and
  * coefficient blocks coef[nb][K*K].  out[t] = V(t) as in (1).
- * qf, qn: far / near Gauss-Legendre orders; M: grading depth; far_ratio:
- * pairs with dist(t,B) >= far_ratio*h_B use the far rule.
+ * (gxf, gwf, qf), (gxn, gwn, qn): the far / near Gauss-Legendre rules on
+ * [-1,1] (nodes and weights, computed by the caller); M: grading depth;
+ * far_ratio: pairs with dist(t,B) >= far_ratio*h_B use the far rule.
  */
 int oracle_volume(int nt, const double *tx, const double *ty, int nb, const double *bcx,
-                  const double *bcy, const double *bh, int K, const double *coef, int qf,
-                  int qn, int M, double far_ratio, double *out) {
-  if (K > MAXK || qf > MAXQ || qn > MAXQ || M > 60) return -1;
-  double gxf[MAXQ], gwf[MAXQ], gxn[MAXQ], gwn[MAXQ];
-  gauss_legendre(qf, gxf, gwf);
-  gauss_legendre(qn, gxn, gwn);
+                  const double *bcy, const double *bh, int K, const double *coef,
+                  const double *gxf, const double *gwf, int qf, const double *gxn,
+                  const double *gwn, int qn, int M, double far_ratio, double *out) {
+  if (K > MAXK || qf < 1 || qn < 1 || qf > MAXQ || qn > MAXQ || M > 60) return -1;
   const long double inv2pi = 1.0L / (2.0L * 3.14159265358979323846264338327950288L);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < nt; ++t) {
@@ -189,12 +153,5 @@ int oracle_volume(int nt, const double *tx, const double *ty, int nb, const doub
     }
     out[t] = (double)(acc * inv2pi);
   }
-  return 0;
-}
-
-/* Gauss-Legendre nodes for tests of the rule itself */
-int oracle_gauss_legendre(int q, double *x, double *w) {
-  if (q < 1 || q > MAXQ) return -1;
-  gauss_legendre(q, x, w);
   return 0;
 }

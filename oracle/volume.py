@@ -5,12 +5,16 @@ nonzero data, where p_B is the degree-(K-1) tensor Chebyshev interpolant of
 the leaf's K x K samples (Section 1, eqs. volpot and greenf; Section 4.1:
 the VFMM computes exactly this for the piecewise-polynomial f^e up to its
 far-field tolerance).  The double sum runs in plain C (volume.c), compiled on
-first use with gcc.
+first use with gcc; the Gauss-Legendre rules it applies come from
+gauss_legendre() below.
 """
 import ctypes
+import functools
 import os
 import subprocess
 import threading
+
+import mpmath as mp
 
 import numpy as np
 
@@ -40,10 +44,9 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             d = ctypes.POINTER(ctypes.c_double)
             lib.oracle_volume.argtypes = [ctypes.c_int, d, d, ctypes.c_int, d, d, d, ctypes.c_int, d,
-                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, d]
+                                          d, d, ctypes.c_int, d, d, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_double, d]
             lib.oracle_volume.restype = ctypes.c_int
-            lib.oracle_gauss_legendre.argtypes = [ctypes.c_int, d, d]
-            lib.oracle_gauss_legendre.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -52,12 +55,38 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def gauss_legendre(q):
+@functools.lru_cache(maxsize=None)
+def _gauss_legendre(q):
+    # Golub-Welsch: the nodes are the eigenvalues of the symmetric Jacobi
+    # matrix of the Legendre recurrence (off-diagonal k / sqrt(4k^2 - 1)).
+    # Each eigenvalue seeds a root search on mpmath's Legendre function in
+    # 34-digit arithmetic; the weight is 2 / ((1 - x^2) P_q'(x)^2) with
+    # P_q'(x) = q P_{q-1}(x) / (1 - x^2) at a root of P_q.  Rounded to
+    # double once, and made exactly symmetric.
+    k = np.arange(1, q)
+    beta = k / np.sqrt(4.0 * k * k - 1.0)
+    seeds = np.linalg.eigvalsh(np.diag(beta, 1) + np.diag(beta, -1))
     x = np.zeros(q)
     w = np.zeros(q)
-    if _load().oracle_gauss_legendre(q, _ptr(x), _ptr(w)) != 0:
-        raise ValueError("bad order")
+    with mp.workdps(34):
+        for i in range(q // 2, q):
+            if q % 2 and i == q // 2:
+                r = mp.mpf(0)
+            else:
+                r = mp.findroot(lambda t: mp.legendre(q, t), mp.mpf(float(seeds[i])))
+            dp = q * mp.legendre(q - 1, r) / (1 - r * r)
+            x[i], w[i] = float(r), float(2 / ((1 - r * r) * dp * dp))
+            x[q - 1 - i], w[q - 1 - i] = -x[i], w[i]
+    x.setflags(write=False)
+    w.setflags(write=False)
     return x, w
+
+
+def gauss_legendre(q):
+    """q-point Gauss-Legendre rule on [-1, 1] (nodes ascending, weights)."""
+    if not 1 <= q <= 48:
+        raise ValueError("bad order")
+    return _gauss_legendre(int(q))
 
 
 def leaf_coefficients(values, K):
@@ -79,8 +108,11 @@ def potential_boxes(tx, ty, cx, cy, h, coef, K, qf=None, qn=12, M=28, far_ratio=
     if qf is None:
         qf = K + 16
     out = np.zeros(tx.size)
+    gxf, gwf = (np.ascontiguousarray(a) for a in gauss_legendre(int(qf)))
+    gxn, gwn = (np.ascontiguousarray(a) for a in gauss_legendre(int(qn)))
     rc = _load().oracle_volume(tx.size, _ptr(tx), _ptr(ty), cx.size, _ptr(cx), _ptr(cy), _ptr(h), K,
-                               _ptr(coef), int(qf), int(qn), int(M), float(far_ratio), _ptr(out))
+                               _ptr(coef), _ptr(gxf), _ptr(gwf), int(qf), _ptr(gxn), _ptr(gwn), int(qn),
+                               int(M), float(far_ratio), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_volume: bad parameters")
     return out

@@ -4,7 +4,12 @@ Each check fixes the result by something other than the quadrature itself:
 * constant density: the closed-form antiderivative of log(x^2 + y^2),
   F(x,y) = xy log(x^2+y^2) - 3xy + x^2 atan(y/x) + y^2 atan(x/y);
 * polynomial density on one box: mpmath tanh-sinh quadrature split at the
-  target (brute force in 20-digit arithmetic);
+  target (brute force in 20-digit arithmetic); for K = 8 and 16 and targets
+  on every branch of the oracle (inside, near an edge, off a corner, at the
+  far-rule threshold), a semi-analytic reference: the y2 integral in closed
+  form, the y1 integral by tanh-sinh in 30-digit arithmetic;
+* the Gauss-Legendre rules: exact on monomials, and equal to numpy's
+  independent implementation;
 * radial source f = Laplacian(u) with u a narrow Gaussian: Newton's theorem
   gives V = u up to the leaf interpolation error of f;
 * scaling: V_s(s x) = s^2 V_1(x) + s^2 log(s) int f / (2 pi);
@@ -47,11 +52,14 @@ def small_adaptive_tree():
 
 
 def test_gauss_legendre_rule():
-    for q in (1, 2, 5, 12, 24):
+    for q in (1, 2, 5, 12, 24, 32, 48):
         x, w = volume.gauss_legendre(q)
         for k in range(2 * q):
             exact = 0.0 if k % 2 else 2.0 / (k + 1)
             assert abs(np.dot(w, x ** k) - exact) < 1e-14
+        xn, wn = np.polynomial.legendre.leggauss(q)
+        # numpy's weights carry up to ~5e-14 relative error at q = 48
+        assert np.abs(x - xn).max() <= 2e-16 and np.abs(w - wn).max() <= 1e-13 * wn.max()
 
 
 def test_constant_density_closed_form():
@@ -99,6 +107,71 @@ def test_polynomial_density_brute_force():
         ref = float(mp.quad(f, [-0.5, tgt[0], 0.5], [-0.5, tgt[1], 0.5]) / (2 * mp.pi))
     v = volume.potential_boxes([tgt[0]], [tgt[1]], [0.0], [0.0], [1.0], c[None], K)[0]
     assert abs(v - ref) < 1e-15
+
+
+def _semi_analytic(c, K, cx, cy, h, tx, ty, dps=30):
+    """(1/2 pi) int_B log|t - y| p(y) dy for the box B of centre (cx, cy)
+    and side h and p = sum c[a, b] T_a(xi) T_b(eta).  With s = y2 - t2 and
+    u = y1 - t1, p is a polynomial sum_k e_k(y1) s^k (T_b(alpha s + beta)
+    expanded in monomials), and
+      M_k(u) = int log(u^2 + s^2) s^k ds
+             = [s^(k+1) log(u^2 + s^2)] / (k+1) - 2 A_(k+2)(u) / (k+1),
+      A_m(u) = int s^m / (u^2 + s^2) ds = int s^(m-2) ds - u^2 A_(m-2)(u),
+      A_0 = (atan(s1/u) - atan(s0/u)) / u,  A_1 = log((u^2+s1^2)/(u^2+s0^2)) / 2,
+    so the y2 integral is closed-form and only the y1 integral is numerical
+    (tanh-sinh, split at t1 when it lies over the box)."""
+    with mp.workdps(dps):
+        cx, cy, h, tx, ty = (mp.mpf(float(v)) for v in (cx, cy, h, tx, ty))
+        x0, x1 = cx - h / 2, cx + h / 2
+        s0, s1 = cy - h / 2 - ty, cy + h / 2 - ty
+        al, be = 2 / h, 2 * (ty - cy) / h
+        Tm = [[mp.mpf(1)], [be, al]]  # monomial coefficients of T_b(al s + be)
+        for b in range(2, K):
+            nxt = [mp.mpf(0)] * (b + 1)
+            for k, v in enumerate(Tm[-1]):
+                nxt[k] += 2 * be * v
+                nxt[k + 1] += 2 * al * v
+            for k, v in enumerate(Tm[-2]):
+                nxt[k] -= v
+            Tm.append(nxt)
+        cm = [[mp.mpf(float(c[a, b])) for b in range(K)] for a in range(K)]
+
+        def inner(y1):
+            u2 = (y1 - tx) ** 2
+            xi = 2 * (y1 - cx) / h
+            Ta = [mp.mpf(1), xi]
+            for _ in range(2, K):
+                Ta.append(2 * xi * Ta[-1] - Ta[-2])
+            g = [mp.fsum(cm[a][b] * Ta[a] for a in range(K)) for b in range(K)]
+            e = [mp.fsum(g[b] * Tm[b][k] for b in range(k, K)) for k in range(K)]
+            u = mp.sqrt(u2)
+            A = [(mp.atan(s1 / u) - mp.atan(s0 / u)) / u, mp.log((u2 + s1 ** 2) / (u2 + s0 ** 2)) / 2]
+            for m in range(2, K + 2):
+                A.append((s1 ** (m - 1) - s0 ** (m - 1)) / (m - 1) - u2 * A[m - 2])
+            L1, L0 = mp.log(u2 + s1 ** 2), mp.log(u2 + s0 ** 2)
+            M = [(s1 ** (k + 1) * L1 - s0 ** (k + 1) * L0) / (k + 1) - 2 * A[k + 2] / (k + 1) for k in range(K)]
+            return mp.fsum(e[k] * M[k] for k in range(K)) / 2
+
+        pts = [x0, tx, x1] if x0 < tx < x1 else [x0, x1]
+        return float(mp.quad(inner, pts) / (2 * mp.pi))
+
+
+@pytest.mark.parametrize("K", [8, 16])
+def test_polynomial_density_every_branch(K):
+    """Degree-(K-1) polynomial density on one box, targets inside it, near
+    an edge (distance 0.3 h and 0.999 h: the graded near rule), off a corner
+    (0.18 h) and at the far-rule threshold (distance exactly h: the tensor
+    rule), against the semi-analytic reference to 1e-14."""
+    rng = np.random.default_rng(K)
+    c = rng.standard_normal((K, K)) / (1.0 + np.add.outer(np.arange(K), np.arange(K)))
+    cx, cy, h = 0.1, -0.2, 0.5
+    targets = {"inside": (cx + 0.13 * h, cy - 0.21 * h), "near": (cx + 0.1 * h, cy + 0.8 * h),
+               "near_edge": (cx - 1.499 * h, cy + 0.3 * h), "corner": (cx + 0.65 * h, cy + 0.6 * h),
+               "far_threshold": (cx + 0.2 * h, cy - 1.5 * h)}
+    for name, (tx, ty) in targets.items():
+        ref = _semi_analytic(c, K, cx, cy, h, tx, ty)
+        v = volume.potential_boxes([tx], [ty], [cx], [cy], [h], c[None], K)[0]
+        assert abs(v - ref) <= 1e-14 * max(1.0, abs(ref)), (name, v, ref)
 
 
 def test_radial_gaussian_newton():
