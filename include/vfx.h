@@ -72,8 +72,17 @@ typedef struct {
 } vfx_params;
 
 /* Create a context on the current HIP device: builds the universal tables
- * (stencil matrix, near-field tables, expansion operators) on the host and
- * uploads them.  Errors: VFX_EINVAL for parameters out of range. */
+ * on the host and uploads them on first use:
+ *   - the stencil matrix A_{X,G} of Section 3.2 (eq. defA; Gaussian basis in
+ *     its flat limit, the total-degree-deg interpolant on the support nodes
+ *     G), which every cut leaf shares;
+ *   - the near-field tables of Section 4 (lists n, n+, n-: integrals of the
+ *     log kernel against the leaf basis for the 33 neighbour configurations
+ *     of a level-restricted tree, in units of the target side);
+ *   - the expansion operators of the far field (multipole / local, order p).
+ * Tables depend only on (K, Kbar, deg, p) and are cached for the process.
+ * Errors: VFX_EINVAL for parameters out of range or a null argument,
+ * VFX_ENOMEM if host memory runs out. */
 int vfx_create(const vfx_params* prm, vfx_ctx** out);
 int vfx_destroy(vfx_ctx* ctx);
 
@@ -118,7 +127,16 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
 
 /*
  * Run the extension and the volume FMM on `stream` (a hipStream_t; NULL for
- * the default stream).  All four arrays are device memory, row-major:
+ * the default stream):
+ *   - on every cut leaf, f_G = A^+_{X^I,G} f_{X^I} and the values on the
+ *     Kbar x Kbar grid of the extension square, A_{Xbar^E,G} f_G where no
+ *     data is given (Section 3.2), the total-order Chebyshev expansion on the
+ *     extension square (Section 4.1, eq. chebexpbarS) evaluated on the K x K
+ *     grid of every leaf in the cut leaf's extension list;
+ *   - V[f^e](x) = int (1/2pi) log|x - y| f^e(y) dy at every leaf node
+ *     (Section 1, eqs. volpot, greenf, volinte), near field by the tables,
+ *     far field by multipole and local expansions (Section 4).
+ * All four arrays are device memory, row-major:
  *   f_leaf  n_leaves x K^2   samples of f on regular leaves (other rows
  *                            are not read)
  *   f_cut   n_cut x |X|      samples of f at the stencil points of each cut
@@ -126,8 +144,13 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
  *   fe_out  n_leaves x K^2   extended data f^e (written)
  *   V_out   n_leaves x K^2   V[f^e] at every leaf node (written)
  * fe_out must be 16-byte aligned (it is read back in 16-byte pieces).
+ * The arrays carry no sizes: the caller guarantees the extents above.
+ * Inputs are not scanned: a NaN or Inf in a value that is read propagates
+ * through IEEE arithmetic into f^e and V (the far field spreads it to every
+ * leaf), and no other error results.
  * Asynchronous: returns after enqueueing.  Errors: VFX_EINVAL for null
- * or misaligned pointers, VFX_EHIP if a launch fails.
+ * or misaligned pointers, or a call under a stream capture that
+ * vfx_graph_begin did not start on this stream; VFX_EHIP if a launch fails.
  */
 int vfx_execute(vfx_plan* plan, const double* f_leaf, const double* f_cut, double* fe_out,
                 double* V_out, void* stream);
@@ -249,15 +272,25 @@ int vfx_plan_set_launch(vfx_plan* plan, int near_wgs, int dense_mtb);
 
 /* HIP graph capture of a sequence of executes, possibly of many plans
  * (many uneven trees in one launch): vfx_graph_begin starts a capture
- * on `stream`; vfx_execute / vfx_execute_batch calls on that stream are
- * recorded (each plan must have executed once before, with at least as many
- * right-hand sides, and have timing off); vfx_graph_end ends the capture and
- * instantiates the graph; vfx_graph_launch replays all of it with one launch
- * on a stream; vfx_graph_destroy frees it.  The graph holds no memset
- * nodes.  Every execute of a capture goes to `stream` itself: executes on
- * other streams forked from it by events are not supported (such a capture
- * has ended in a crash inside hipStreamEndCapture).  VFX_EHIP if the
- * runtime refuses a step. */
+ * on `stream`; vfx_execute / vfx_execute_batch / vfx_net_charge calls on that
+ * stream are recorded (each plan must have executed once before, with at
+ * least as many right-hand sides, and have timing off); vfx_graph_end ends
+ * the capture and instantiates the graph; vfx_graph_launch replays all of it
+ * with one launch on a stream; vfx_graph_destroy frees it.  The graph holds
+ * no memset nodes.
+ *   Streams: while a capture is active, the library accepts calls only on
+ * the stream vfx_graph_begin started it on.  A call on any other capturing
+ * stream (a stream forked from that one by events, or a capture the caller
+ * started without vfx_graph_begin) returns VFX_EINVAL and records nothing:
+ * capturing executes on forked streams has ended in a crash inside
+ * hipStreamEndCapture, so that mode is refused.
+ *   Lifetime: a graph refers to the device buffers of the contexts and plans
+ * it captured.  vfx_destroy, vfx_plan_destroy, vfx_plan_set_precision, a
+ * vfx_execute_batch with more right-hand sides than the plan held, and a
+ * vfx_net_charge with more right-hand sides than any earlier call free or
+ * reallocate them; after any of these on a captured context or plan,
+ * vfx_graph_launch returns VFX_EINVAL (capture again).
+ * VFX_EHIP if the runtime refuses a step. */
 int vfx_graph_begin(void* stream);
 int vfx_graph_end(void* stream, vfx_graph** out);
 int vfx_graph_launch(vfx_graph* graph, void* stream);

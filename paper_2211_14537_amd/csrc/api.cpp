@@ -8,6 +8,9 @@
 #include <new>
 #include <string>
 #include <tuple>
+#include <unordered_map>
+#include <utility>
+#include <vector>
 
 #include "vfx_internal.h"
 
@@ -30,6 +33,61 @@ int fail(int code, const std::string& msg) {
 // seconds at K = 16, so they are kept for the life of the process.
 std::mutex g_cache_mu;
 std::map<std::tuple<int, int, int, int>, std::shared_ptr<const vfx::Tables>> g_cache;
+
+// Live contexts and plans: id -> the generation count of their device
+// buffers.  A captured graph records (id, generation) of everything its
+// executes used; vfx_graph_launch refuses to replay it once one of them
+// has been destroyed or has freed / reallocated those buffers.
+std::mutex g_live_mu;
+uint64_t g_next_id = 1;
+std::unordered_map<uint64_t, const uint64_t*> g_live;
+
+uint64_t register_live(const uint64_t* gen) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  const uint64_t id = g_next_id++;
+  g_live[id] = gen;
+  return id;
+}
+
+void unregister_live(uint64_t id) {
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  g_live.erase(id);
+}
+
+// Captures started by vfx_graph_begin: the stream, its capture id, and the
+// (id, generation) pairs its executes used.
+struct Capture {
+  hipStream_t stream = nullptr;
+  unsigned long long capture_id = 0;
+  std::vector<std::pair<uint64_t, uint64_t>> used;
+};
+std::mutex g_cap_mu;
+std::vector<Capture> g_captures;
+
+// Under stream capture a call is accepted only on the stream vfx_graph_begin
+// started the capture on (not on streams forked from it: capturing executes
+// there has ended in a crash inside hipStreamEndCapture), and records what
+// it uses.  Returns false (with the reason in msg) to refuse.
+bool capture_admit(hipStream_t s, const vfx::Context* c, const vfx::Plan* p, std::string& msg) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long cid = 0;
+  if (hipStreamGetCaptureInfo(s, &cs, &cid) != hipSuccess) {
+    msg = "hipStreamGetCaptureInfo failed";
+    return false;
+  }
+  if (cs != hipStreamCaptureStatusActive) return true;
+  std::lock_guard<std::mutex> lk(g_cap_mu);
+  for (Capture& k : g_captures) {
+    if (k.capture_id != cid) continue;
+    if (k.stream != s) break;
+    k.used.emplace_back(c->id, c->gen);
+    k.used.emplace_back(p->id, p->gen);
+    return true;
+  }
+  msg = "under stream capture, calls must go to the stream vfx_graph_begin started the capture on "
+        "(captures on other streams, or on streams forked from it, are not supported)";
+  return false;
+}
 
 std::shared_ptr<const vfx::Tables> cached_tables(const vfx_params& prm) {
   auto key = std::make_tuple(prm.K, prm.Kbar, prm.deg, prm.p);
@@ -78,6 +136,7 @@ int vfx_create(const vfx_params* prm, vfx_ctx** out) {
     c->c.T.root_cx = prm->root_cx;
     c->c.T.root_cy = prm->root_cy;
     c->c.T.root_size = prm->root_size;
+    c->c.id = register_live(&c->c.gen);
     *out = c.release();
     return VFX_OK;
   } catch (const std::bad_alloc&) {
@@ -89,6 +148,7 @@ int vfx_create(const vfx_params* prm, vfx_ctx** out) {
 
 int vfx_destroy(vfx_ctx* ctx) {
   if (!ctx) return VFX_OK;
+  unregister_live(ctx->c.id);
   vfx::free_tables_device(&ctx->c);
   delete ctx;
   return VFX_OK;
@@ -123,6 +183,7 @@ static int plan_create(vfx_ctx* ctx, const vfx_tree* tree, int flags, vfx_plan**
     std::string err;
     int rc = vfx::build_host_plan(ctx->c.T, tree, p->p.H, err, (flags & VFX_PLAN_DEFER_FACTOR) != 0);
     if (rc) return fail(rc, std::string(who) + ": " + err);
+    p->p.id = register_live(&p->p.gen);
     *out = p.release();
     return VFX_OK;
   } catch (const std::bad_alloc&) {
@@ -156,6 +217,7 @@ int vfx_plan_factor_gpu(vfx_plan* plan, void* stream) {
 
 int vfx_plan_destroy(vfx_plan* plan) {
   if (!plan) return VFX_OK;
+  unregister_live(plan->p.id);
   vfx::free_plan_device(&plan->p);
   delete plan;
   return VFX_OK;
@@ -201,6 +263,8 @@ static int execute_checked(vfx_plan* plan, int nrhs, const double* f_leaf, const
       return fail(VFX_EINVAL, std::string(who) + ": under stream capture the plan must already hold device data "
                                                  "for this many right-hand sides (execute it once before capturing)");
     if (p.timing) return fail(VFX_EINVAL, std::string(who) + ": timing must be off under stream capture");
+    std::string msg;
+    if (!capture_admit((hipStream_t)stream, p.ctx, &p, msg)) return fail(VFX_EINVAL, std::string(who) + ": " + msg);
   }
   try {
     std::string err;
@@ -277,18 +341,44 @@ int vfx_plan_set_launch(vfx_plan* plan, int near_wgs, int dense_mtb) {
 struct vfx_graph {
   hipGraph_t g = nullptr;
   hipGraphExec_t e = nullptr;
+  std::vector<std::pair<uint64_t, uint64_t>> used;  // (id, generation) of the contexts and plans
 };
 
 int vfx_graph_begin(void* stream) {
-  hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed);
-  return e == hipSuccess ? VFX_OK : fail(VFX_EHIP, std::string("vfx_graph_begin: ") + hipGetErrorString(e));
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_graph_begin: ") + hipGetErrorString(e));
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  unsigned long long cid = 0;
+  e = hipStreamGetCaptureInfo(s, &cs, &cid);
+  if (e != hipSuccess) {
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    return fail(VFX_EHIP, std::string("vfx_graph_begin: ") + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g_cap_mu);
+  Capture k;
+  k.stream = s;
+  k.capture_id = cid;
+  g_captures.push_back(std::move(k));
+  return VFX_OK;
 }
 
 int vfx_graph_end(void* stream, vfx_graph** out) {
   if (!out) return fail(VFX_EINVAL, "vfx_graph_end: null argument");
   *out = nullptr;
+  hipStream_t s = (hipStream_t)stream;
   std::unique_ptr<vfx_graph> g(new vfx_graph);
-  hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g->g);
+  {
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    for (size_t i = 0; i < g_captures.size(); ++i)
+      if (g_captures[i].stream == s) {
+        g->used = std::move(g_captures[i].used);
+        g_captures.erase(g_captures.begin() + i);
+        break;
+      }
+  }
+  hipError_t e = hipStreamEndCapture(s, &g->g);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_graph_end: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(&g->e, g->g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
@@ -301,6 +391,15 @@ int vfx_graph_end(void* stream, vfx_graph** out) {
 
 int vfx_graph_launch(vfx_graph* g, void* stream) {
   if (!g) return fail(VFX_EINVAL, "vfx_graph_launch: null graph");
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    for (const auto& u : g->used) {
+      auto it = g_live.find(u.first);
+      if (it == g_live.end() || *it->second != u.second)
+        return fail(VFX_EINVAL, "vfx_graph_launch: a context or plan captured in this graph has since been "
+                                "destroyed or has freed / reallocated its device buffers; capture again");
+    }
+  }
   hipError_t e = hipGraphLaunch(g->e, (hipStream_t)stream);
   return e == hipSuccess ? VFX_OK : fail(VFX_EHIP, std::string("vfx_graph_launch: ") + hipGetErrorString(e));
 }
@@ -348,10 +447,13 @@ int vfx_net_charge(vfx_plan* plan, const double* fe, int nrhs, double* out, void
   if (!plan || !fe || !out || nrhs < 1) return fail(VFX_EINVAL, "vfx_net_charge: null argument or nrhs < 1");
   vfx::Plan& p = plan->p;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive &&
-      (!p.ctx->D.ready || !p.D.ready || nrhs > p.D.chg_cap))
-    return fail(VFX_EINVAL, "vfx_net_charge: under stream capture the plan must already hold device data for this "
-                            "many right-hand sides (call it once before capturing)");
+  if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive) {
+    if (!p.ctx->D.ready || !p.D.ready || nrhs > p.D.chg_cap)
+      return fail(VFX_EINVAL, "vfx_net_charge: under stream capture the plan must already hold device data for "
+                              "this many right-hand sides (call it once before capturing)");
+    std::string msg;
+    if (!capture_admit((hipStream_t)stream, p.ctx, &p, msg)) return fail(VFX_EINVAL, "vfx_net_charge: " + msg);
+  }
   try {
     std::string err;
     int rc = vfx::launch_net_charge(&p, fe, nrhs, out, (hipStream_t)stream, err);

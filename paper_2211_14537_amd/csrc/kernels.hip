@@ -1718,6 +1718,7 @@ int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStrea
   const int L = p->H.L, n = T.n;
   const int G = std::min(L, (int)std::max(1L, std::min((long)kChargeBlocks, (long)L * n / 2048)));
   if (nrhs > D.chg_cap) {
+    p->gen++;  // graphs that captured the old buffer are stale
     if (D.chg_part) {
       VFX_HIP(hipDeviceSynchronize());  // no earlier call of this plan in flight
       VFX_HIP(hipFree(D.chg_part));
@@ -1817,6 +1818,7 @@ int upload_tables(Context* c, std::string& err) {
 
 void free_tables_device(Context* c) {
   DeviceTables& D = c->D;
+  c->gen++;
   void* ptrs[] = {D.t,        D.tbar,     D.w2,       D.AbarT,   D.cbar,     D.near,    D.near_s2,   D.A,
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2p_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
@@ -1836,6 +1838,7 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   const Tables& T = p->ctx->T;
   const size_t P = T.p + 1, R = (size_t)nrhs;
   if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
+  p->gen++;  // graphs that captured the old buffers are stale
   void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.near_y32};
   for (void* q : old)
     if (q) (void)hipFree(q);
@@ -1956,6 +1959,7 @@ int upload_plan(Plan* p, std::string& err) {
 void free_plan_device(Plan* p) {
   DevicePlan& D = p->D;
   if (D.ready) (void)hipDeviceSynchronize();  // no execute of this plan in flight
+  p->gen++;
   void* ptrs[] = {D.box_level, D.box_child0, D.box_leaf, D.box_parent, D.box_cx,   D.box_cy,   D.leaf_box,
                   D.kind,      D.l1_ptr,     D.l1_src,   D.l1_cfg,     D.l2_ptr,   D.l2_src,   D.l2_off,
                   D.l3_ptr,    D.l3_src,     D.l4_ptr,   D.l4_src,     D.l4_cfg,   D.np_src,   D.l1_slot,

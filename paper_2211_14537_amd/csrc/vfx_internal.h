@@ -118,9 +118,13 @@ struct DeviceTables {
           *l2l_out = nullptr;
 };
 
+// Device buffers that a captured HIP graph may refer to carry a generation
+// count: every call that frees or reallocates them adds one, so a graph can
+// tell at launch whether what it recorded still exists (see api.cpp).
 struct Context {
   Tables T;
   DeviceTables D;
+  uint64_t id = 0, gen = 0;
 };
 
 // Host-side plan ------------------------------------------------------------
@@ -233,6 +237,7 @@ struct Plan {
   bool timing = false;
   std::vector<hipEvent_t> ev;   // kEvents * capacity
   int n_timed = 0;
+  uint64_t id = 0, gen = 0;     // identity and generation of the device buffers
 };
 
 // plan.cpp

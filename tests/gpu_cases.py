@@ -74,3 +74,19 @@ def interior_values(case, i):
 
 def oracle_potential(case, fe, tx, ty):
     return volume.potential(case["otree"], fe, case["K"], tx, ty)
+
+
+def volume_checks(case, fe_gpu, V_gpu, sel, tx, ty, fe_o):
+    """Rel Linf errors of V_gpu at the sampled nodes sel (coordinates tx, ty):
+    g1 against the oracle's V of the GPU's own extended data fe_gpu (the
+    volume FMM alone), g3 against the oracle's V of the oracle's extended
+    data fe_o (end to end).  V_o(fe_gpu) = V_o(fe_o) + V_o(fe_gpu - fe_o),
+    and the difference is nonzero only on extension targets, so the second
+    potential is cheap.  Returns (g1, g3, v_o)."""
+    v_o = oracle_potential(case, fe_o, tx, ty)
+    d = np.asarray(fe_gpu, dtype=np.float64) - fe_o
+    v_g = v_o + (oracle_potential(case, d, tx, ty) if np.any(d != 0.0) else 0.0)
+    V = np.asarray(V_gpu).ravel()[sel]
+    g1 = float(np.abs(V - v_g).max() / np.abs(v_g).max())
+    g3 = float(np.abs(V - v_o).max() / np.abs(v_o).max())
+    return g1, g3, v_o

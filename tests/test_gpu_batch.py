@@ -1,16 +1,20 @@
 """Batched right-hand sides, HIP graph capture of many plans, autotuner.
 
 A batch of right-hand sides runs every kernel once with the right-hand side
-as a grid dimension; it must reproduce separate executes bitwise.  Executes
-of several plans captured in one graph, on one stream or on streams forked
-from it, must reproduce the eager results bitwise on every replay (with
-eager work between replays).  The autotuner's
-choices change only the distribution of work, so results are bitwise
-independent of them."""
+as a grid dimension; it must reproduce separate executes bitwise, and two of
+its right-hand sides are checked against the oracle (extension within the
+least-squares bound, V of the extended data within 1e-10).  Executes of
+several plans captured in one graph must reproduce the eager results bitwise
+on every replay (with eager work between replays), and every plan's replayed
+V is checked against the oracle.  A graph refuses to replay once a plan it
+captured has freed or reallocated its buffers, and a capture refuses calls
+on streams it was not started on.  The autotuner's choices change only the
+distribution of work, so results are bitwise independent of them."""
 import numpy as np
 import pytest
 
-from gpu_cases import say, setup
+from gpu_cases import oracle_extension, sample_targets, say, setup, volume_checks
+from oracle import extension
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +61,37 @@ def test_batch_matches_single_executes(gpu_device, name, precision):
         assert np.array_equal(FE[r], singles[r][0])
         assert np.array_equal(V[r], singles[r][1])
     say(f"    {name} precision {precision}: batch of {nrhs} bitwise equal to single executes")
+    # the first and the last right-hand side against the oracle
+    for r in (0, nrhs - 1):
+        g1, g3, wext = _against_oracle(case, fl[r], fc[r], FE[r], V[r], seed=r)
+        say(f"    rhs {r}: V rel Linf vs oracle {g1:.2e} (end to end {g3:.2e}), extension err/bound {wext:.2f}")
+        # FP64: the method's 1e-10 (1e-9 at p = 20, the order the disk
+        # workload states, whose truncation error is ~1e-9)
+        tol = (1e-9 if name == "disk_uniform3" else 1e-10) if precision == 0 else 2e-7
+        assert g1 <= tol
+        assert wext <= 1.0
+
+
+def _against_oracle(case, f_leaf, f_cut, fe, V, seed=0, n_nodes=160):
+    """Extension of one right-hand side against the oracle's float64
+    extension (worst error / bound) and V against the oracle (g1: V of the
+    GPU's extended data, g3: V of the oracle's)."""
+    c = dict(case, f_leaf=np.asarray(f_leaf), f_cut=np.asarray(f_cut))
+    tr = c["tree"]
+    if len(tr["cut_ids"]):
+        ref, info = oracle_extension(c, "fp64")
+    else:
+        ref, info = c["f_leaf"].copy(), {}
+    worst = 0.0
+    cut_ids = list(tr["cut_ids"])
+    for i, rec in info.items():
+        tg = rec["targets"]
+        r = cut_ids.index(i)
+        tol = 2.0 * extension.extension_tolerance(rec, ref[tg], c["f_cut"][r][tr["mask"][r] != 0])
+        worst = max(worst, float(np.abs(fe[tg] - ref[tg]).max()) / tol)
+    sel, tx, ty = sample_targets(c, n_nodes, seed=seed)
+    g1, g3, _ = volume_checks(c, fe, V, sel, tx, ty, ref)
+    return g1, g3, worst
 
 
 def test_graph_of_several_plans_replays_bitwise(gpu_device):
@@ -92,6 +127,90 @@ def test_graph_of_several_plans_replays_bitwise(gpu_device):
         _ = (torch.ones(1000, device="cuda:0") * rep).sum().item()  # eager work between replays
     g.close()
     say("    graph of 3 plans x 2 right-hand sides: 3 replays bitwise equal to eager")
+    # every plan's replayed result (second right-hand side) against the oracle
+    for i, (c, (FL, FC, FE, V)) in enumerate(zip(cases, bufs)):
+        g1, g3, wext = _against_oracle(c, FL[1].cpu().numpy(), FC[1].cpu().numpy(), FE[1].cpu().numpy(),
+                                       V[1].cpu().numpy(), seed=i)
+        say(f"    plan {i}: V rel Linf vs oracle {g1:.2e} (end to end {g3:.2e}), extension err/bound {wext:.2f}")
+        assert g1 <= (1e-9 if i == 1 else 1e-10) and wext <= 1.0  # plan 1: disk workload at p = 20
+
+
+def test_graph_refuses_stale_plans_and_foreign_captures(gpu_device):
+    """A graph records the generation of every plan it captured: after the
+    plan frees its buffers (vfx_plan_set_precision), grows them (a larger
+    batch) or is destroyed, vfx_graph_launch refuses with VFX_EINVAL and
+    launches nothing.  A capture the library did not start (here one begun
+    by torch on another stream) refuses executes and records nothing."""
+    import torch
+    from paper_2211_14537_amd import vfx
+    case = setup("starfish_small", p=24)
+    fl, fc = _inputs(case, 2, 5)
+    FL, FC = _dev(fl), _dev(fc)
+    FE, V = torch.empty_like(FL), torch.empty_like(FL)
+    plan = case["plan"]
+    plan.execute(FL[0], FC[0], FE[0], V[0])
+    torch.cuda.synchronize()
+    V0 = V[0].cpu().numpy().copy()
+    s = torch.cuda.Stream()
+
+    def capture():
+        g = vfx.Graph()
+        with torch.cuda.stream(s):
+            g.begin(s)
+            plan.execute(FL[0], FC[0], FE[0], V[0], stream=s)
+            g.end(s)
+        return g
+
+    # a fresh capture replays; each invalidating call makes it refuse
+    for invalidate in ("set_precision", "grow"):
+        g = capture()
+        V.fill_(float("nan"))
+        g.launch(s)
+        s.synchronize()
+        assert np.array_equal(V[0].cpu().numpy(), V0)
+        if invalidate == "set_precision":
+            plan.set_precision(0)  # frees the device data (re-uploaded by the next execute)
+        else:
+            plan.execute_batch(2, FL, FC, FE, V)  # more right-hand sides: buffers regrow
+        torch.cuda.synchronize()
+        V.fill_(float("nan"))
+        torch.cuda.synchronize()
+        with pytest.raises(vfx.VfxError):
+            g.launch(s)
+        s.synchronize()
+        assert np.isnan(V[0].cpu().numpy()).all()  # nothing ran
+        g.close()
+        plan.execute(FL[0], FC[0], FE[0], V[0])
+        torch.cuda.synchronize()
+        assert np.array_equal(V[0].cpu().numpy(), V0)
+    # a destroyed plan
+    other = setup("disk_uniform3", p=20)
+    fo = _dev(other["f_leaf"])
+    fco = _dev(other["f_cut"])
+    feo, Vo = torch.empty_like(fo), torch.empty_like(fo)
+    other["plan"].execute(fo, fco, feo, Vo)
+    torch.cuda.synchronize()
+    g = vfx.Graph()
+    with torch.cuda.stream(s):
+        g.begin(s)
+        other["plan"].execute(fo, fco, feo, Vo, stream=s)
+        g.end(s)
+    other["plan"].close()
+    with pytest.raises(vfx.VfxError):
+        g.launch(s)
+    g.close()
+    # a capture begun outside the library, on another stream
+    s2 = torch.cuda.Stream()
+    x = torch.zeros(16, device="cuda:0")
+    tg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(tg, stream=s2):
+        with pytest.raises(vfx.VfxError):
+            plan.execute(FL[0], FC[0], FE[0], V[0], stream=s2)
+        x.add_(1.0)
+    tg.replay()
+    torch.cuda.synchronize()
+    assert float(x.sum().item()) == 16.0
+    say("    stale graphs refused after set_precision / batch growth / destroy; foreign capture refused")
 
 
 @pytest.mark.skip(reason="capturing executes on streams forked from the capturing stream ended in a host "

@@ -1,84 +1,128 @@
-"""GPU parity at the full size of the benchmark workload (starfish_adaptive:
-K = 16, p = 24, 4207 leaves, 1.08e6 leaf nodes, 730 cut leaves), in the
-launch configuration bench.py times (FP64 near field, default launch
-parameters), on sampled outputs the oracle computes one by one:
+"""GPU parity at the full size of the benchmark workloads, in the launch
+configuration bench.py times (default launch parameters), on sampled outputs
+the oracle computes one by one:
 
-* V on given leaf data (every leaf regular): 96 seeded nodes plus all nodes
-  of the coarsest and of the finest leaf, rel Linf <= 1e-10 against the
-  oracle's direct quadrature;
-* f^e of 40 seeded cut leaves (their whole extension lists) against the
-  oracle's float64 extension, within the conditioning-aware bound of the
-  other parity tests; regular leaves bit-exact.
+starfish_adaptive (K = 16, p = 24, 4207 leaves, 1.08e6 nodes, 730 cut leaves)
+* the timed plan's own execute: f^e of every cut leaf against the oracle's
+  float64 extension, within the conditioning-aware least-squares bound
+  (regular leaves bit-exact); V against the oracle's V of the GPU's f^e
+  (G1, rel Linf <= 1e-10) and against the oracle's V of the oracle's f^e
+  (G3, end to end: 1e-10 max|V| plus the potential of the allowed extension
+  differences) at 96 seeded nodes plus every node of a cut leaf, of an
+  extension target, of the coarsest and of the finest leaf;
+* V on given leaf data (every leaf regular), rel Linf <= 1e-10.
+
+wedge_adaptive (14254 leaves, 3.65e6 nodes, 1536 cut leaves)
+* the timed plan in FP64: G1 <= 1e-10 and G3 as above;
+* the same plan with the mixed-precision near field at the setting bench.py
+  reports: G1 within the gate stated below.
 """
+import math
+
 import numpy as np
 import pytest
 
-from gpu_cases import interior_values, oracle_extension, oracle_potential, run_gpu, say, setup
+from gpu_cases import interior_values, oracle_extension, oracle_potential, run_gpu, say, setup, volume_checks
 from oracle import extension
 from paper_2211_14537_amd import vfx
 
 pytestmark = pytest.mark.gpu
 
 
-def test_full_size_starfish(gpu_device):
-    say("[full size] starfish_adaptive p=24")
-    case = setup("starfish_adaptive")
-    tr = case["tree"]
-    lv = np.asarray(tr["level"])
-    assert len(lv) == 4207 and len(tr["cut_ids"]) == 730
-    # extension on a seeded sample of cut leaves
-    fe, _ = run_gpu(case)
-    rng = np.random.default_rng(7)
-    cuts = sorted(rng.choice(np.asarray(tr["cut_ids"]), 40, replace=False).tolist())
-    ref, info = oracle_extension(case, "fp64", cut_ids=cuts)
-    worst = 0.0
-    for i in cuts:
-        rec = info[i]
+def _nodes(case, n_random, seed, leaves):
+    X, Y = case["otree"].leaf_nodes(case["K"])
+    rng = np.random.default_rng(seed)
+    n = case["K"] ** 2
+    sel = set(rng.choice(X.size, n_random, replace=False).tolist())
+    for leaf in leaves:
+        sel.update(range(int(leaf) * n, (int(leaf) + 1) * n))
+    sel = np.array(sorted(sel))
+    return sel, X.ravel()[sel], Y.ravel()[sel]
+
+
+def _extension_and_bound(case, fe):
+    """Every cut leaf against the oracle's float64 extension; returns the
+    oracle's extended data, the worst error / bound, and the potential bound
+    of the allowed differences (|int_B log|x-y| d| <= |d| h^2 (|log h| + 2)
+    per target leaf, h <= 1)."""
+    ref, info = oracle_extension(case, "fp64")
+    h = case["otree"].h()
+    worst, bound = 0.0, 0.0
+    for i, rec in info.items():
         tg = rec["targets"]
         tol = 2.0 * extension.extension_tolerance(rec, ref[tg], interior_values(case, i))
         err = float(np.abs(fe[tg] - ref[tg]).max())
         assert err <= tol, (i, err, tol)
         worst = max(worst, err / tol)
+        for j in tg:
+            bound += tol * h[j] ** 2 * (abs(math.log(h[j])) + 2.0) / (2 * math.pi)
+    return ref, worst, bound
+
+
+def _sample_leaves(case, rng):
+    tr = case["tree"]
+    lv = np.asarray(tr["level"])
+    owner = case["plan"].ext_owner()
+    kind = np.asarray(tr["kind"])
+    cut = rng.choice(np.asarray(tr["cut_ids"]))
+    ext = rng.choice(np.nonzero((owner >= 0) & (kind == 0))[0])
+    return [int(np.argmin(lv)), int(np.argmax(lv)), int(cut), int(ext)]
+
+
+def test_full_size_starfish(gpu_device):
+    say("[full size] starfish_adaptive p=24")
+    case = setup("starfish_adaptive")
+    tr = case["tree"]
+    assert len(tr["level"]) == 4207 and len(tr["cut_ids"]) == 730
+    fe, V = run_gpu(case)
     reg = np.asarray(tr["kind"]) == 1
     assert np.array_equal(fe[reg], case["f_leaf"][reg])
-    say(f"    extension: 40 cut leaves, worst error / bound = {worst:.3f}")
-    # V on given data at sampled nodes, same tree, every leaf regular
+    ref, worst, bound = _extension_and_bound(case, fe)
+    say(f"    extension: all 730 cut leaves, worst error / bound = {worst:.3f}")
+    rng = np.random.default_rng(7)
+    sel, tx, ty = _nodes(case, 96, 7, _sample_leaves(case, rng))
+    g1, g3, v_o = volume_checks(case, fe, V, sel, tx, ty, ref)
+    err3 = g3 * np.abs(v_o).max()
+    say(f"    timed plan over {sel.size} nodes: G1 rel Linf {g1:.3e}, G3 rel Linf {g3:.3e} "
+        f"(allowed {1e-10 + bound / np.abs(v_o).max():.3e})")
+    assert g1 <= 1e-10
+    assert err3 <= 1e-10 * np.abs(v_o).max() + bound
+    # V on given data, every leaf regular
     plan = vfx.Plan(case["ctx"], tr["level"], tr["ix"], tr["iy"], np.ones_like(tr["kind"]))
     reg_case = dict(case, plan=plan, f_cut=np.zeros((0, case["ctx"].n_stencil)))
-    fe2, V = run_gpu(reg_case)
+    fe2, V2 = run_gpu(reg_case)
     assert np.array_equal(fe2, case["f_leaf"])
-    n = case["K"] ** 2
-    X, Y = case["otree"].leaf_nodes(case["K"])
-    sel = set(rng.choice(X.size, 96, replace=False).tolist())
-    for leaf in (int(np.argmin(lv)), int(np.argmax(lv))):
-        sel.update(range(leaf * n, (leaf + 1) * n))
-    sel = np.array(sorted(sel))
-    vo = oracle_potential(case, case["f_leaf"], X.ravel()[sel], Y.ravel()[sel])
-    rel = np.abs(V.ravel()[sel] - vo).max() / np.abs(vo).max()
-    say(f"    V: rel Linf = {rel:.3e} over {sel.size} nodes")
+    lv = np.asarray(tr["level"])
+    sel, tx, ty = _nodes(case, 64, 8, (int(np.argmax(lv)),))
+    vo = oracle_potential(case, case["f_leaf"], tx, ty)
+    rel = np.abs(V2.ravel()[sel] - vo).max() / np.abs(vo).max()
+    say(f"    given data: rel Linf = {rel:.3e} over {sel.size} nodes")
     assert rel <= 1e-10
 
 
-def test_full_size_wedge_mixed(gpu_device):
-    """wedge_adaptive (14254 leaves, 3.65e6 nodes) on given data: the FP64
-    path within 1e-10 and the all-mixed near field (bf16 slices, FP32
-    accumulation) within 2e-6 of the oracle at sampled nodes."""
+# The mixed-precision setting bench.py reports beside FP64 on this workload,
+# and its gate on G1 (10x the error stated for it).
+WEDGE_MIXED = dict(min_level=0, gate=4e-9)
+
+
+def test_full_size_wedge(gpu_device):
     say("[full size] wedge_adaptive p=24, FP64 and mixed")
-    case = setup("wedge_adaptive", all_regular=True)
-    assert len(case["tree"]["level"]) == 14254
-    lv = np.asarray(case["tree"]["level"])
-    n = case["K"] ** 2
-    X, Y = case["otree"].leaf_nodes(case["K"])
+    case = setup("wedge_adaptive")
+    tr = case["tree"]
+    assert len(tr["level"]) == 14254
+    fe, V64 = run_gpu(case)
+    ref, worst, bound = _extension_and_bound(case, fe)
+    say(f"    extension: all {len(tr['cut_ids'])} cut leaves, worst error / bound = {worst:.3f}")
     rng = np.random.default_rng(11)
-    sel = set(rng.choice(X.size, 64, replace=False).tolist())
-    sel.update(range(int(np.argmax(lv)) * n, (int(np.argmax(lv)) + 1) * n))
-    sel = np.array(sorted(sel))
-    vo = oracle_potential(case, case["f_leaf"], X.ravel()[sel], Y.ravel()[sel])
-    _, V64 = run_gpu(case)
-    rel64 = np.abs(V64.ravel()[sel] - vo).max() / np.abs(vo).max()
-    case["plan"].set_precision(1, 0)
-    _, Vmx = run_gpu(case)
-    relmx = np.abs(Vmx.ravel()[sel] - vo).max() / np.abs(vo).max()
-    say(f"    rel Linf over {sel.size} nodes: FP64 {rel64:.3e}, mixed {relmx:.3e}")
-    assert rel64 <= 1e-10
-    assert relmx <= 2e-6
+    sel, tx, ty = _nodes(case, 64, 11, _sample_leaves(case, rng))
+    g1, g3, v_o = volume_checks(case, fe, V64, sel, tx, ty, ref)
+    say(f"    FP64 over {sel.size} nodes: G1 {g1:.3e}, G3 {g3:.3e} "
+        f"(allowed {1e-10 + bound / np.abs(v_o).max():.3e})")
+    assert g1 <= 1e-10
+    assert g3 * np.abs(v_o).max() <= 1e-10 * np.abs(v_o).max() + bound
+    case["plan"].set_precision(1, WEDGE_MIXED["min_level"])
+    fe_mx, Vmx = run_gpu(case)
+    assert np.array_equal(fe_mx, fe)  # the extension is FP64 in both modes
+    g1m, g3m, _ = volume_checks(case, fe, Vmx, sel, tx, ty, ref)
+    say(f"    mixed (sources at level >= {WEDGE_MIXED['min_level']}): G1 {g1m:.3e}, G3 {g3m:.3e}")
+    assert g1m <= WEDGE_MIXED["gate"]
