@@ -211,6 +211,21 @@ int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, 
  * nrhs < 1. */
 int vfx_net_charge(vfx_plan* plan, const double* fe, int nrhs, double* out, void* stream);
 
+/* The net charge of vfx_net_charge, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same result bit for bit, but the
+ * block partials live in a fixed device array of the library (1 MiB per GPU,
+ * held until the process ends) instead of a buffer of the plan, and the call
+ * allocates nothing.  The plan's device data must already be resident on the
+ * current device (one vfx_execute or vfx_net_charge before); nrhs may be at
+ * most vfx_net_charge_noalloc_max_rhs() (64).  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (on different streams, or
+ * from different threads) race and give wrong results; calls ordered on one
+ * stream are safe.  VFX_EINVAL for null pointers, nrhs < 1 or above the
+ * limit, a plan not yet on the device or on another device. */
+int vfx_net_charge_noalloc(vfx_plan* plan, const double* fe, int nrhs, double* out, void* stream);
+int vfx_net_charge_noalloc_max_rhs(void);
+
 /* Precision of the near field.  mode 0: FP64
  * everywhere (the default).  mode 1: the list-1 interactions whose source
  * leaf is at level >= min_level are applied with the operands split into

@@ -464,6 +464,24 @@ int vfx_net_charge(vfx_plan* plan, const double* fe, int nrhs, double* out, void
   return VFX_OK;
 }
 
+int vfx_net_charge_noalloc(vfx_plan* plan, const double* fe, int nrhs, double* out, void* stream) {
+  if (!plan || !fe || !out || nrhs < 1)
+    return fail(VFX_EINVAL, "vfx_net_charge_noalloc: null argument or nrhs < 1");
+  vfx::Plan& p = plan->p;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive) {
+    std::string msg;
+    if (!capture_admit((hipStream_t)stream, p.ctx, &p, msg))
+      return fail(VFX_EINVAL, "vfx_net_charge_noalloc: " + msg);
+  }
+  std::string err;
+  int rc = vfx::launch_net_charge_noalloc(&p, fe, nrhs, out, (hipStream_t)stream, err);
+  if (rc) return fail(rc, "vfx_net_charge_noalloc: " + err);
+  return VFX_OK;
+}
+
+int vfx_net_charge_noalloc_max_rhs(void) { return vfx::noalloc_max_rhs(); }
+
 int vfx_mlp_param_count(void) { return vfx::mlp_param_count(); }
 
 int64_t vfx_mlp_grad_work(int64_t batch) { return batch > 0 ? (int64_t)vfx::mlp_grad_work((long)batch) : 0; }

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <string>
 
 #include "vfx_internal.h"
@@ -1733,6 +1734,77 @@ int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStrea
                        D.box_level, c->D.w2, fe, (long)L * n, D.chg_part);
   VFX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_charge_sum, dim3(nrhs), dim3(256), 0, s, G, D.chg_part, out);
+  VFX_HIP(hipGetLastError());
+  return VFX_OK;
+}
+
+// -------------------------------------------------------------------------
+// Net charge without allocation (for callers that cannot allocate: code
+// under HIP graph capture, tight serving loops).  The block partials go to
+// a file-scope device array instead of the plan's buffer: one copy per GPU
+// for the life of the process, kNoallocMaxRhs right-hand sides of
+// kChargeBlocks partials (1 MiB).  Host code never names the array in a
+// launch or a copy: on each device it asks hipGetSymbolAddress for that
+// device's copy once (with the device current) and passes the address it
+// returns.  Every partial the sum reads is written by the same call first,
+// so nothing needs clearing; two calls that overlap on one GPU race on it.
+constexpr int kNoallocMaxRhs = 64;
+static __device__ __align__(256) double scratch[kChargeBlocks * kNoallocMaxRhs];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(int dev, void** out, std::string& err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device ordinal out of range";
+    return VFX_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    VFX_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) {
+      err = "hipGetSymbolAddress returned a null address";
+      return VFX_EHIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return VFX_OK;
+}
+
+int noalloc_max_rhs() { return kNoallocMaxRhs; }
+
+int launch_net_charge_noalloc(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err) {
+  Context* c = p->ctx;
+  if (!c->D.ready || !p->D.ready) {
+    err = "the plan's device data are not resident (run vfx_execute or vfx_net_charge on it once first)";
+    return VFX_EINVAL;
+  }
+  if (nrhs > kNoallocMaxRhs) {
+    err = "nrhs exceeds the allocation-free limit of " + std::to_string(kNoallocMaxRhs);
+    return VFX_EINVAL;
+  }
+  int dev = -1;
+  VFX_HIP(hipGetDevice(&dev));
+  if (dev != c->D.device) {
+    err = "the current device is not the one holding the plan's data";
+    return VFX_EINVAL;
+  }
+  void* ptr = nullptr;
+  int rc = scratch_address(dev, &ptr, err);
+  if (rc) return rc;
+  double* part = static_cast<double*>(ptr);
+  const Tables& T = c->T;
+  const DevicePlan& D = p->D;
+  const int L = p->H.L, n = T.n;
+  const int G = std::min(L, (int)std::max(1L, std::min((long)kChargeBlocks, (long)L * n / 2048)));
+  if (G > 0)
+    hipLaunchKernelGGL(k_charge_part, dim3(G, nrhs), dim3(256), 0, s, n, L, G, T.root_size, D.leaf_box,
+                       D.box_level, c->D.w2, fe, (long)L * n, part);
+  VFX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_charge_sum, dim3(nrhs), dim3(256), 0, s, G, part, out);
   VFX_HIP(hipGetLastError());
   return VFX_OK;
 }

@@ -256,6 +256,8 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err);
 int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
                   hipStream_t s, std::string& err);
 int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
+int launch_net_charge_noalloc(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
+int noalloc_max_rhs();
 
 // mlp.hip (refinement classifier)
 int mlp_param_count();

@@ -52,7 +52,8 @@ _lib = None
 
 EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points", "vfx_leaf_nodes",
             "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
-            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_net_charge", "vfx_execute_batch", "vfx_plan_create_ex",
+            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_net_charge", "vfx_net_charge_noalloc",
+            "vfx_net_charge_noalloc_max_rhs", "vfx_execute_batch", "vfx_plan_create_ex",
             "vfx_plan_factor_gpu",
             "vfx_plan_autotune", "vfx_plan_set_launch", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
             "vfx_mlp_param_count", "vfx_mlp_forward", "vfx_mlp_grad", "vfx_mlp_adam", "vfx_f32_to_f16",
@@ -89,6 +90,8 @@ def lib():
         L.vfx_plan_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_int]
         L.vfx_interp.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
         L.vfx_net_charge.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+        L.vfx_net_charge_noalloc.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+        L.vfx_net_charge_noalloc_max_rhs.argtypes = []
         L.vfx_execute_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
         L.vfx_plan_create_ex.argtypes = [vp, ctypes.POINTER(_Tree), ctypes.c_int, ctypes.POINTER(vp)]
         L.vfx_plan_factor_gpu.argtypes = [vp, vp]
@@ -312,6 +315,22 @@ class Plan:
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().vfx_net_charge(self._h, fe.data_ptr(), nrhs, out.data_ptr(), ctypes.c_void_p(st.cuda_stream)))
 
+    def net_charge_noalloc(self, fe, out, stream=None):
+        """net_charge through the allocation-free entry point (the plan's
+        device data must already be resident; at most
+        net_charge_noalloc_max_rhs() right-hand sides)."""
+        import torch
+        n = self.ctx.K * self.ctx.K
+        if not (fe.is_cuda and fe.dtype == torch.float64 and fe.is_contiguous() and fe.numel() > 0
+                and fe.numel() % (self.n_leaves * n) == 0):
+            raise ValueError(f"fe: expected contiguous float64 CUDA tensor of nrhs x {(self.n_leaves, n)}")
+        nrhs = fe.numel() // (self.n_leaves * n)
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == nrhs):
+            raise ValueError(f"out: expected contiguous float64 CUDA tensor with {nrhs} entries")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().vfx_net_charge_noalloc(self._h, fe.data_ptr(), nrhs, out.data_ptr(),
+                                            ctypes.c_void_p(st.cuda_stream)))
+
     def set_precision(self, mode, min_level=0):
         """Near-field precision: 0 = FP64, 1 = bf16 slices with FP32
         accumulation for sources at level >= min_level (K = 16)."""
@@ -430,3 +449,8 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def net_charge_noalloc_max_rhs():
+    """Right-hand sides vfx_net_charge_noalloc accepts per call."""
+    return int(lib().vfx_net_charge_noalloc_max_rhs())
