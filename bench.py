@@ -35,9 +35,8 @@ HBM_PEAK_GBS = 8000.0
 # event-timed spans include waits for the other stream), the one with the
 # most algorithmic work (the longest time at the roofline): event times of
 # kernels that share the GPU with the other stream vary from run to run.
-SINGLE_KERNEL_PHASES = ("fe_init", "extension", "down", "near_lowrank", "near_dense", "far", "p2l", "m2p")
+SINGLE_KERNEL_PHASES = ("extension", "down", "near_lowrank", "near_dense", "far", "p2l", "m2p")
 PHASE_KERNEL = {
-    "fe_init": ("k_fe_init", "// Initial f^e: f on regular leaves"),
     "extension": ("k_extension", "// Extension of one cut leaf per work-group"),
     "p2m_up": ("k_up", "// Upward pass without the level-by-level chain."),
     "m2l": ("k_m2l_lanes", "// M2L: one lane per list-2 entry"),
@@ -48,14 +47,18 @@ PHASE_KERNEL = {
     "near_dense": ("k_tgemm", "// Table GEMMs with 64-entry tiles"),
     "far": ("k_far", "// Far field and the near-field reduction"),
 }
+# the same phases on the target-stationary path (FP64, K = 16)
+PHASE_KERNEL_TS = dict(PHASE_KERNEL, near_lowrank=("k_tgemm", "// Table GEMMs with 64-entry tiles"),
+                       near_dense=("k_near_ts", None))
 
 
-def algorithmic_work(case):
-    """Algorithmic FP64 flops and HBM bytes of one execute, per phase.
+def algorithmic_work(case, precision="fp64"):
+    """Algorithmic FP64 flops and HBM bytes of one execute, per phase, with
+    the stream each phase runs on.
 
     Flops count the arithmetic the method needs (a complex multiply-add is 8
-    flops), bytes the compulsory HBM traffic (every operand read once, every
-    result written once)."""
+    flops; low-rank operators at their true ranks), bytes the compulsory HBM
+    traffic (every operand read once, every result written once)."""
     import numpy as np
     plan, ctx = case["plan"], case["ctx"]
     st = plan.stats()
@@ -70,42 +73,61 @@ def algorithmic_work(case):
     counts = np.bincount(cfg, minlength=33)
     rk = ctx.debug_table(22, 0, 66)
     lrR, rank = rk[:33].astype(int), rk[33:].astype(int)
-    lr = lrR > 0
-    n_lr, n_dense = int(counts[lr].sum()), int(counts[~lr].sum())
     # pairs (box, leaf below it) of the direct upward/downward passes
     lev = np.asarray(case["tree"]["level"])
     n_pairs_ud = int(np.maximum(lev - 2, 0).sum())
     nI = case["interior"]
+    n_reg = int(np.count_nonzero(np.asarray(case["tree"]["kind"]) == 1))
     work = {
-        # the extension: P_i and f_I read, the Sbar grid data, every list
-        # target written (ext_targets counts the cut leaves themselves)
+        # the extension (P_i and f_I read, the Sbar grid data, every list
+        # target written; ext_targets counts the cut leaves themselves) and,
+        # in the same launch, the f^e initialisation of the other leaves
         "extension": (2.0 * nG * nI + ncut * (2 * nG * 144 + 4 * 144 * 12) + ext_targets * (2 * 12 * 12 * K + 2 * 12 * n),
-                      8.0 * (nG * nI + nI + ncut * 144 + ext_targets * n)),
-        "fe_init": (0.0, 16.0 * L * n),
-        "p2m_up": (8.0 * P * n * L / 2 + 8.0 * P * P / 2 * n_pairs_ud, 8.0 * L * n + 16.0 * B * P),
+                      8.0 * (nG * nI + nI + ncut * 144) + 8.0 * L * n + 8.0 * n_reg * n, "caller"),
+        "p2m_up": (8.0 * P * n * L / 2 + 8.0 * P * P / 2 * n_pairs_ud, 8.0 * L * n + 16.0 * B * P, "caller"),
         # M2L sums the list-4 products of P2L with the list-2 translations
-        "m2l": (8.0 * P * P * N2, 16.0 * 2 * B * P + 16.0 * N4 * P),
-        "p2l": (4.0 * P * n * N4, 8.0 * L * n + 16.0 * N4 * P),
-        "down": (8.0 * P * P / 2 * n_pairs_ud, 16.0 * (B + L) * P),
-        # low-rank near field: W (r x n) then Q (n x r) per pair, true ranks;
-        # bytes: every leaf's samples once, one n-vector written per pair,
-        # the factors once
-        "near_lowrank": (float((counts * 4.0 * n * rank)[lr].sum()),
-                         8.0 * (L * n + n * n_lr) + 8.0 * 2 * n * 64 * int(lr.sum())),
-        "near_dense": (2.0 * n * n * n_dense, 8.0 * (L * n + n * n_dense) + 8.0 * n * n * int((~lr).sum())),
-        # list-1 and list-3 sums and L2P; M2P as a table product (2P real
-        # coefficients per list-3 box)
-        "far": (8.0 * P * n * L + n * (st["n_list1"] + N3), 8.0 * n * (st["n_list1"] + N3) + 8.0 * L * n + 16.0 * L * P),
-        "m2p": (2.0 * n * 2 * P * N3, 16.0 * N3 * P + 8.0 * n * N3 + 8.0 * 2 * P * n * 20),
+        "m2l": (8.0 * P * P * N2, 16.0 * 2 * B * P + 16.0 * N4 * P, "caller"),
+        "p2l": (4.0 * P * n * N4, 8.0 * L * n + 16.0 * N4 * P, "side"),
+        "down": (8.0 * P * P / 2 * n_pairs_ud, 16.0 * (B + L) * P, "caller"),
+        "m2p": (2.0 * n * 2 * P * N3, 16.0 * N3 * P + 8.0 * n * N3 + 8.0 * 2 * P * n * 20, "side"),
     }
-    return work
+    info = ctx.debug_table(24, 0, 82)
+    ts = precision == "fp64" and K == 16 and info[80] == 1.0
+    if ts:
+        cls = info[:33].astype(int)
+        base = info[66:73].astype(int)
+        r_cls = np.array([rank[base[cls[c]]] if cls[c] > 0 else 0 for c in range(33)])
+        n_self = int(counts[4])
+        zr = float((counts * r_cls).sum())  # sum over low-rank pairs of the class rank
+        # phase 1, the factor products Z = (W_b P_g^T) f of every non-self
+        # pair: each source leaf read once, Z written, the factors once
+        work["near_lowrank"] = (2.0 * n * zr, 8.0 * L * n + 8.0 * zr + 8.0 * 32 * n * 64, "side")
+        # phase 2 per target group: Q_b Z per pair and the self operator;
+        # Z and the self rows read, each leaf's sum written once
+        work["near_dense"] = (2.0 * n * zr + 2.0 * n * n * n_self,
+                              8.0 * zr + 8.0 * n * n_self + 8.0 * L * n + 8.0 * (n * n + 6 * n * 64), "side")
+        # the far-field kernel: M2P values of list 3, the near sums, L2P; V written
+        work["far"] = (8.0 * P * n * L + n * N3, 8.0 * n * N3 + 16.0 * L * n + 16.0 * L * P, "caller")
+    else:
+        lr = lrR > 0
+        n_lr, n_dense = int(counts[lr].sum()), int(counts[~lr].sum())
+        work["near_lowrank"] = (float((counts * 4.0 * n * rank)[lr].sum()),
+                                8.0 * (L * n + n * n_lr) + 8.0 * 2 * n * 64 * int(lr.sum()), "side")
+        work["near_dense"] = (2.0 * n * n * n_dense, 8.0 * (L * n + n * n_dense) + 8.0 * n * n * int((~lr).sum()),
+                              "side")
+        work["far"] = (8.0 * P * n * L + n * (st["n_list1"] + N3),
+                       8.0 * n * (st["n_list1"] + N3) + 8.0 * L * n + 16.0 * L * P, "caller")
+    return work, ts
 
 
 def kernel_digest(marker):
-    """Digest of the source block of a kernel in kernels.hip (from its
-    opening comment to the next separator line)."""
+    """Digest of a kernel's source: the block of kernels.hip from its opening
+    comment to the next separator line, or (marker None) all of near.hip."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2211_14537_amd", "csrc", "kernels.hip")).read()
+    csrc = os.path.join(ROOT, "paper_2211_14537_amd", "csrc")
+    if marker is None:
+        return hashlib.sha256(open(os.path.join(csrc, "near.hip")).read().encode()).hexdigest()[:16]
+    src = open(os.path.join(csrc, "kernels.hip")).read()
     i = src.find(marker)
     if i < 0:
         return None
@@ -446,6 +468,8 @@ def main():
     ap.add_argument("--min-level", type=int, default=0,
                     help="with --precision mixed: sources at this level or finer run mixed")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision sweep beside FP64")
+    ap.add_argument("--near-mode", type=int, default=0, choices=(0, 1),
+                    help="FP64 near field: 0 pair-based, 1 target-stationary")
     ap.add_argument("--check-nodes", type=int, default=0,
                     help="without the CPU baseline: oracle accuracy check at this many seeded nodes")
     ap.add_argument("--batch", type=int, default=0,
@@ -474,6 +498,8 @@ def main():
         return bench_trees(args, dev)
     case = build_case(args.config, args.p)
     plan = case["plan"]
+    if args.near_mode:
+        plan.set_near_mode(args.near_mode)
     if args.precision == "mixed":
         plan.set_precision(1, args.min_level)
     st = plan.stats()
@@ -511,28 +537,40 @@ def main():
     N = st["n_leaves"] * case["K"] ** 2
     value = N / sec
 
-    work = algorithmic_work(case)
-    # in mixed precision the near-field phases hold the bf16 kernels (and the
-    # slice split), which this FP64 roofline does not describe
-    single = [k for k in SINGLE_KERNEL_PHASES
-              if args.precision == "fp64" or k not in ("near_lowrank", "near_dense")]
-    dom = max(single, key=lambda k: max(work[k][0] / (FP64_PEAK_TFLOPS * 1e12), work[k][1] / (HBM_PEAK_GBS * 1e9)))
-    flops, nbytes = work[dom]
-    ksec = phases[dom] * 1e-3
-    t_mfma = flops / (FP64_PEAK_TFLOPS * 1e12)
-    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
-    if t_mfma >= t_hbm:
+    work, ts = algorithmic_work(case, args.precision if args.near_mode == 1 else "pairs")
+    kernels = PHASE_KERNEL_TS if ts else PHASE_KERNEL
+    # per-phase rooflines: time at the roofline = the larger of flops at the
+    # FP64 peak and bytes at the HBM peak; fraction = that / measured phase
+    # time (HIP events on the phase's stream; spans of several kernels
+    # include waits).  The step's fraction: the sum of the phase rooflines
+    # over the measured step.
+    rows = []
+    for k, (fl_, by_, stream_) in work.items():
+        if args.precision != "fp64" and k in ("near_lowrank", "near_dense"):
+            continue  # bf16 kernels: not an FP64 roofline
+        t_roof = max(fl_ / (FP64_PEAK_TFLOPS * 1e12), by_ / (HBM_PEAK_GBS * 1e9))
+        ms = phases.get(k)
+        rows.append({"phase": k, "kernel": kernels[k][0], "stream": stream_, "flops": fl_, "bytes": by_,
+                     "bound": "mfma" if fl_ / (FP64_PEAK_TFLOPS * 1e12) >= by_ / (HBM_PEAK_GBS * 1e9) else "hbm",
+                     "ms": ms, "roofline_ms": 1e3 * t_roof, "frac": (1e3 * t_roof / ms) if ms else None,
+                     "single_kernel": k in SINGLE_KERNEL_PHASES})
+    step_roof = sum(r["roofline_ms"] for r in rows)
+    single = [r for r in rows if r["single_kernel"]]
+    dom = max(single, key=lambda r: r["roofline_ms"])
+    flops, nbytes, ksec = dom["flops"], dom["bytes"], dom["ms"] * 1e-3
+    if dom["bound"] == "mfma":
         roof = {"bound": "mfma", "achieved": flops / ksec / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s"}
     else:
         roof = {"bound": "hbm", "achieved": nbytes / ksec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    kname, marker = PHASE_KERNEL[dom]
+    kname, marker = kernels[dom["phase"]]
     roof["traffic"] = load_traffic(kname, case["cfg"]["name"], kernel_digest(marker), nbytes)
     roof["kernel"] = kname
-    roof["kernel_ms"] = phases[dom]
+    roof["phase"] = dom["phase"]
+    roof["kernel_ms"] = dom["ms"]
     roof["algorithmic_flops"] = flops
     roof["algorithmic_bytes"] = nbytes
-    roof["roofline_ms"] = 1e3 * max(t_mfma, t_hbm)
+    roof["roofline_ms"] = dom["roofline_ms"]
 
     plan_stage = gpu_plan_stage(case, fl, fc, dev)
     out = {
@@ -550,6 +588,9 @@ def main():
         "autotune": choice,
         "plan_s": st["plan_seconds"], "tables_s": case["t_ctx"], "plan_stage": plan_stage,
         "roofline": roof,
+        "roofline_phases": rows,
+        "roofline_step": {"roofline_ms": step_roof, "ms_per_step": 1e3 * sec, "frac": step_roof / (1e3 * sec),
+                          "note": "sum over phases of max(flops / 78.6 TFLOP/s, bytes / 8 TB/s), FP64 phases"},
     }
     sel = v_g = None
     if not args.no_cpu_baseline or args.check_nodes > 0:

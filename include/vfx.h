@@ -143,7 +143,8 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
  *                            leaf (exterior entries are not read)
  *   fe_out  n_leaves x K^2   extended data f^e (written)
  *   V_out   n_leaves x K^2   V[f^e] at every leaf node (written)
- * fe_out must be 16-byte aligned (it is read back in 16-byte pieces).
+ * f_leaf and fe_out must be 16-byte aligned (they are accessed in 16-byte
+ * pieces).
  * The arrays carry no sizes: the caller guarantees the extents above.
  * Inputs are not scanned: a NaN or Inf in a value that is read propagates
  * through IEEE arithmetic into f^e and V (the far field spreads it to every
@@ -239,6 +240,23 @@ int vfx_net_charge_noalloc_max_rhs(void);
  * device and must not overlap an execute of the same plan. */
 int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level);
 
+/* Near-field strategy of the FP64 path at K = 16.  mode 0 (the default):
+ * pair-based - every list-1 pair's table product is formed on its own
+ * (configuration-major tiles of 32-64 pairs, operators shared through LDS)
+ * and the far-field kernel sums each target's pair products.  mode 1:
+ * target-stationary - the products of each group of 16 consecutive target
+ * leaves are summed in registers and each leaf's near-field sum is written
+ * once: the 32 neighbour configurations are folded onto six symmetry
+ * classes of the square (T_c = P_g T_b P_g^T, Section 4 tables in
+ * low-rank form Q_b W_b), a table GEMM forms every pair's W_b P_g^T f, and a
+ * per-group kernel applies Q_b and the self table.  Both compute the same
+ * sum (they differ by rounding); mode 1 reads and writes far less memory
+ * but does more matrix work (tiles of one pair per target).  Other K and
+ * mixed pairs keep mode 0.  The plan's device data are rebuilt on the next
+ * vfx_execute (graphs that captured it are invalidated); the call must not
+ * overlap an execute of the same plan.  VFX_EINVAL for other modes. */
+int vfx_plan_set_near_mode(vfx_plan* plan, int mode);
+
 /* Plan with the per-cut-leaf least-squares operators computed on the GPU
  * (the plan stage on the GPU).  flags = VFX_PLAN_DEFER_FACTOR: the host builds
  * only the lists and the interior index sets, and vfx_plan_factor_gpu then
@@ -319,16 +337,21 @@ int vfx_graph_destroy(vfx_graph* graph);
  * enabling again restarts the count).  The query synchronises on the last
  * recorded event and returns, averaged over the recorded executes, the
  * milliseconds of eleven phases:
- *   ms[0] extension (the cut-leaf kernel)
+ *   ms[0] extension (the cut-leaf kernel, with the f^e initialisation of
+ *         the other leaves)
  *   ms[1] P2M and the upward pass
  *   ms[2] M2L (with the wait for P2L)
  *   ms[3] downward pass (leaf local expansions)
- *   ms[4] near field, low-rank operators (side stream)
- *   ms[5] near field, dense operators (side stream)
+ *   ms[4] near field, first kernel (side stream): the low-rank pairs, or on
+ *         the target-stationary path (FP64, K = 16) the factor products
+ *   ms[5] near field, second kernel (side stream): the dense pairs, or the
+ *         per-target-group kernel of the target-stationary path
  *   ms[6] far field (list-1 and list-3 sums, L2P)   ms[7] total
  *   ms[8] P2L, list-4 products (side stream)
- *   ms[9] M2P, list-3 products (after the upward pass)
- *   ms[10] f^e initialisation (f on regular leaves, zero elsewhere)
+ *   ms[9] M2P, list-3 products (side stream, after the near field and the
+ *         upward pass)
+ *   ms[10] f^e initialisation: 0 (it runs inside the extension launch,
+ *         which ms[0] times)
  * and ms[11] (if n_out >= 12) the number of executes averaged.  Phases on
  * the two streams overlap, so they do not add up to the total.  n_out must
  * be >= 11. */
@@ -365,6 +388,16 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
  *            rows x n, [k][i], rows as for table 19: row 0 log|z|, rows
  *            2k and 2k+1 Re z^-k and -Im z^-k (k >= 1), z = node i of the
  *            leaf minus the box centre in units of the box side
+ *        24 (`index` ignored): 82 values describing the symmetry classes of
+ *            the target-stationary near field (K = 16): the class (0..6) and
+ *            the D4 code g of each of the 33 configurations, the base
+ *            configuration and padded rank of each of the 7 classes, 1 if
+ *            the path is available (else 0), and max |T_c[g(i)][g(j)] -
+ *            T_b[i][j]| / max |T_b| over the configurations.  D4 code bits:
+ *            1 swaps the axes, then 2 negates x and 4 negates y; on node
+ *            (a, b) of the K x K grid: (A, B) = swapped ? (b, a) : (a, b),
+ *            a' = (g & 2) ? K-1-A : A, b' = (g & 4) ? K-1-B : B
+ *            (all -1 when K != 16)
  * VFX_EINVAL if `which`, `index` or `count` does not match. */
 int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count);
 /* Interaction list `which` (1..4) of a plan as CSR arrays (host):

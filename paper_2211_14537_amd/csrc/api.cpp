@@ -251,8 +251,8 @@ static int execute_checked(vfx_plan* plan, int nrhs, const double* f_leaf, const
                            double* V_out, void* stream, const char* who) {
   if (!plan || !f_leaf || !fe_out || !V_out || nrhs < 1)
     return fail(VFX_EINVAL, std::string(who) + ": null argument or nrhs < 1");
-  if (reinterpret_cast<uintptr_t>(fe_out) % 16)
-    return fail(VFX_EINVAL, std::string(who) + ": fe_out must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(fe_out) % 16 || reinterpret_cast<uintptr_t>(f_leaf) % 16)
+    return fail(VFX_EINVAL, std::string(who) + ": f_leaf and fe_out must be 16-byte aligned");
   if (plan->p.H.ncut > 0 && !f_cut)
     return fail(VFX_EINVAL, std::string(who) + ": f_cut is null but the tree has cut leaves");
   vfx::Plan& p = plan->p;
@@ -429,6 +429,21 @@ int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level) {
   return VFX_OK;
 }
 
+int vfx_plan_set_near_mode(vfx_plan* plan, int mode) {
+  if (!plan || (mode != 0 && mode != 1)) return fail(VFX_EINVAL, "vfx_plan_set_near_mode: mode must be 0 or 1");
+  vfx::Plan& p = plan->p;
+  try {
+    std::string err;
+    p.H.near_mode = mode;
+    int rc = vfx::build_near_tiles(p.ctx->T, p.H, p.H.precision, p.H.mixed_min_level, err);
+    if (rc) return fail(rc, "vfx_plan_set_near_mode: " + err);
+  } catch (const std::bad_alloc&) {
+    return fail(VFX_ENOMEM, "vfx_plan_set_near_mode: out of host memory");
+  }
+  vfx::free_plan_device(&p);  // re-uploaded by the next execute
+  return VFX_OK;
+}
+
 int vfx_interp(vfx_plan* plan, const double* V, int64_t npts, const double* px, const double* py, double* out,
                void* stream) {
   if (!plan || npts < 0 || (npts > 0 && (!V || !px || !py || !out)))
@@ -536,7 +551,7 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out) {
   hipError_t e = hipEventSynchronize(p.ev[(size_t)(p.n_timed - 1) * NE + 9]);
   if (e != hipSuccess) return fail(VFX_EHIP, std::string("vfx_plan_timings: ") + hipGetErrorString(e));
   // phase k runs from event a[k] to event b[k]
-  static const int a_[NP] = {12, 1, 11, 3, 5, 6, 8, 0, 10, 2, 0};
+  static const int a_[NP] = {12, 1, 2, 3, 5, 6, 8, 0, 10, 13, 0};
   static const int b_[NP] = {1, 2, 3, 4, 6, 7, 9, 9, 5, 11, 12};
   double acc[NP] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int r = 0; r < p.n_timed; ++r) {
@@ -612,6 +627,23 @@ int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64
       }
       src = rk.data();
       size = (int64_t)rk.size();
+      break;
+    }
+    case 24: {
+      static thread_local std::vector<double> v;
+      v.clear();
+      if (T.near_cls.size() == (size_t)vfx::kNearConfigs) {
+        for (int c = 0; c < vfx::kNearConfigs; ++c) v.push_back(T.near_cls[c]);
+        for (int c = 0; c < vfx::kNearConfigs; ++c) v.push_back(T.near_g[c]);
+        for (int k = 0; k < vfx::kNearClasses; ++k) v.push_back(T.cls_base[k]);
+        for (int k = 0; k < vfx::kNearClasses; ++k) v.push_back(T.cls_R[k]);
+      } else {
+        v.assign(2 * vfx::kNearConfigs + 2 * vfx::kNearClasses, -1.0);
+      }
+      v.push_back(T.ts_ok ? 1.0 : 0.0);
+      v.push_back(T.ts_sym_err);
+      src = v.data();
+      size = (int64_t)v.size();
       break;
     }
     case 23:

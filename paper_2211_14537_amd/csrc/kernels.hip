@@ -2,8 +2,8 @@
 //
 // Execution order on one stream (every output element has one writer, so no
 // atomics are needed and results are bitwise reproducible):
-//   fe_init      f^e = f on regular leaves, 0 elsewhere
-//   extension    per cut leaf: f_G = P_i f_{X^I}; values on the Kbar grid of
+//   extension    f^e = f on regular leaves, 0 on leaves outside every
+//                extension list, and per cut leaf: f_G = P_i f_{X^I}; values on the Kbar grid of
 //                Sbar (given data where interior); total-order Chebyshev
 //                expansion; evaluation on every leaf of its extension list
 //                (Sections 3.2 and 4.1)
@@ -47,20 +47,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ double box_side(double root, int level) { return ldexp(root, -level); }
 
 // -------------------------------------------------------------------------
-// Initial f^e: f on regular leaves, zero elsewhere (the extension kernel
-// then writes its target leaves).
-__global__ void k_fe_init(int n, int L, const int8_t* __restrict__ kind, const double* __restrict__ f_leaf,
-                          double* __restrict__ fe) {
-  const long total = (long)L * n;
-  f_leaf += blockIdx.y * total;  // right-hand side blockIdx.y
-  fe += blockIdx.y * total;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int leaf = (int)(e / n);
-    fe[e] = (kind[leaf] == 1) ? f_leaf[e] : 0.0;
-  }
-}
-
-// -------------------------------------------------------------------------
 // Extension of one cut leaf per work-group (256 threads): f_G = P_i f_I
 // (A1), values on the Kbar x Kbar grid of Sbar (given data at interior
 // nodes, A_{Xbar,G} f_G elsewhere; A2), the total-order Chebyshev
@@ -75,7 +61,25 @@ __global__ void __launch_bounds__(256) k_extension(
     const double* __restrict__ pinv_val, const uint8_t* __restrict__ sbar_given, const int* __restrict__ ext_ptr,
     const int* __restrict__ ext_tgt, const double* __restrict__ ext_geo, const double* __restrict__ t,
     const double* __restrict__ AbarT, const double* __restrict__ cbar, const double* __restrict__ f_cut,
-    double* __restrict__ fe, int nrhs, long sfc, long sfe) {
+    double* __restrict__ fe, int nrhs, long sfc, long sfe, int ext_blocks, int L,
+    const int8_t* __restrict__ fe_src, const double* __restrict__ f_leaf) {
+  if ((int)blockIdx.x >= ext_blocks) {
+    // the work-groups past the cut leaves initialise every leaf no extension
+    // list writes: f on regular leaves (fe_src 1), zero elsewhere (fe_src
+    // 0); list targets (fe_src 2) are left to their cut leaf's work-group,
+    // so every element has one writer.  16-byte pieces, grid-stride.
+    const int n = K * K;
+    const long half = (long)L * n / 2, pieces = half * nrhs;
+    const long nb = (long)(gridDim.x - ext_blocks) * blockDim.x;
+    for (long e = (long)(blockIdx.x - ext_blocks) * blockDim.x + threadIdx.x; e < pieces; e += nb) {
+      const long r = e / half, i = 2 * (e - r * half);
+      const int src = fe_src[i / n];
+      if (src == 2) continue;
+      const double2 v = src ? *(const double2*)(f_leaf + r * sfe + i) : make_double2(0.0, 0.0);
+      *(double2*)(fe + r * sfe + i) = v;
+    }
+    return;
+  }
   // consecutive work-groups take the right-hand sides of one cut leaf, so
   // its operator P_i is read from HBM once and reused from L2
   const int rhs = blockIdx.x % nrhs;
@@ -1473,7 +1477,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <int PM, bool EXACT, int NPL, bool MX>
+template <int PM, bool EXACT, int NPL, bool MX, bool NTS>
 __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, const int* __restrict__ leaf_box,
                                             const int* __restrict__ box_level, const double* __restrict__ t,
                                             const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
@@ -1500,7 +1504,7 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
   // fewer than 64), list-3 entry `lane` (at most 20), local coefficient `lane`
   const int e0 = l1_ptr[leaf], n1 = l1_ptr[leaf + 1] - e0;
   const int f0 = l3_ptr[leaf], n3 = l3_ptr[leaf + 1] - f0;
-  const int my_slot = lane < n1 ? l1_slot[e0 + lane] : 0;
+  const int my_slot = (!NTS && lane < n1) ? l1_slot[e0 + lane] : 0;
   const double my_a0 = lane < n1 ? mpole[(size_t)l1_srcbox[e0 + lane] * P].x : 0.0;
   const int my_slot3 = lane < n3 ? l3_slot[f0 + lane] : 0;
   const double my_b0 = lane < n3 ? mpole[(size_t)l3_src[f0 + lane] * P].x : 0.0;
@@ -1518,19 +1522,26 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
     double yn[NPL], y3[NPL], lg = 0.0, lg3 = 0.0;
 #pragma unroll
     for (int j = 0; j < NPL; ++j) yn[j] = y3[j] = 0.0;
+    if (NTS) {
+      // the target-stationary kernel left h^2 times the list-1 table sum in V
+#pragma unroll
+      for (int j = 0; j < NPL; ++j) yn[j] = V[(size_t)leaf * n + node[j]];
+      for (int e = 0; e < n1; ++e) lg += readlane_d(my_a0, e);
+    } else {
 #pragma unroll 4
-    for (int e = 0; e < n1; ++e) {
-      const int sl = __builtin_amdgcn_readlane(my_slot, e);
-      if (!MX || sl >= 0) {
-        const double* y = Y + (size_t)sl * n;
+      for (int e = 0; e < n1; ++e) {
+        const int sl = __builtin_amdgcn_readlane(my_slot, e);
+        if (!MX || sl >= 0) {
+          const double* y = Y + (size_t)sl * n;
 #pragma unroll
-        for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
-      } else {  // a pair applied in mixed precision: FP32 result
-        const float* y = Y32 + (size_t)(-1 - sl) * n;
+          for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
+        } else {  // a pair applied in mixed precision: FP32 result
+          const float* y = Y32 + (size_t)(-1 - sl) * n;
 #pragma unroll
-        for (int j = 0; j < NPL; ++j) yn[j] += (double)y[node[j]];
+          for (int j = 0; j < NPL; ++j) yn[j] += (double)y[node[j]];
+        }
+        lg += readlane_d(my_a0, e);
       }
-      lg += readlane_d(my_a0, e);
     }
 #pragma unroll 4
     for (int q = 0; q < n3; ++q) {
@@ -1542,7 +1553,7 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
     const double lh = log(h);
     const double lt = lh * lg + (lh - kLn2) * lg3;
 #pragma unroll
-    for (int j = 0; j < NPL; ++j) acc[j] = h * h * yn[j] + y3[j] + lt;
+    for (int j = 0; j < NPL; ++j) acc[j] = (NTS ? yn[j] : h * h * yn[j]) + y3[j] + lt;
   }
   // L2P
   if (lev >= 2) {
@@ -1846,6 +1857,12 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.lr_W, T.lr_W);
   UP(D.lr_Q, T.lr_Q);
   UP(D.lr_Wb, T.lr_Wb);
+  if (T.ts_ok) {
+    UP(D.cls_R, T.cls_R);
+    UP(D.lr_Wp, T.lr_Wp);
+    UP(D.cls_QT, T.cls_QT);
+    UP(D.self_T, T.self_T);
+  }
   UP(D.lr_Qb, T.lr_Qb);
   UP(D.self_Ab, T.self_Ab);
   UP(D.p2l_gemm, T.p2l_gemm);
@@ -1895,7 +1912,8 @@ void free_tables_device(Context* c) {
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2p_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
-                  D.lr_R,     D.lr_W,     D.lr_Q,     D.lr_Wb,    D.lr_Qb,    D.self_Ab};
+                  D.lr_R,     D.lr_W,     D.lr_Q,     D.lr_Wb,    D.lr_Qb,    D.self_Ab,
+                  D.cls_R,    D.lr_Wp,    D.cls_QT,   D.self_T};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   D = DeviceTables();
@@ -1911,18 +1929,20 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   const size_t P = T.p + 1, R = (size_t)nrhs;
   if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
   p->gen++;  // graphs that captured the old buffers are stale
-  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.near_y32};
+  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.near_y32, D.near_z};
   for (void* q : old)
     if (q) (void)hipFree(q);
   D.mpole = D.local = D.up_part = D.locf = nullptr;
-  D.near_y = D.p2l_y = D.m2p_y = nullptr;
+  D.near_y = D.p2l_y = D.m2p_y = D.near_z = nullptr;
   D.near_y32 = nullptr;
   D.xs = nullptr;
   D.cap = 0;
   VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P * R));
   VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P * R));
   VFX_HIP(hipMemset(D.local, 0, sizeof(double2) * (size_t)H.B * P * R));
-  if (!H.np_src.empty()) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n * R));
+  if (!H.np_src.empty() && !H.ts) VFX_HIP(hipMalloc((void**)&D.near_y, sizeof(double) * H.np_src.size() * T.n * R));
+  if (!H.np_src.empty() && H.ts)
+    VFX_HIP(hipMalloc((void**)&D.near_z, sizeof(double) * H.np_src.size() * kNearLrMax * R));
   if (!H.p4_src.empty()) VFX_HIP(hipMalloc((void**)&D.p2l_y, sizeof(double) * H.p4_src.size() * T.p2l_rows * R));
   if (!H.p3_src.empty()) VFX_HIP(hipMalloc((void**)&D.m2p_y, sizeof(double) * H.p3_src.size() * T.n * R));
   if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P * R));
@@ -1947,6 +1967,12 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.box_cy, H.box_cy);
   UP(D.leaf_box, H.leaf_box);
   UP(D.kind, H.kind);
+  {
+    // where each leaf's f^e comes from: 2 an extension list, 1 f (regular), 0 zero
+    std::vector<int8_t> src(H.L, 0);
+    for (int i = 0; i < H.L; ++i) src[i] = H.owner[i] >= 0 ? 2 : (H.kind[i] == 1 ? 1 : 0);
+    UP(D.fe_src, src);
+  }
   UP(D.l1_ptr, H.l1_ptr);
   UP(D.l1_src, H.l1_src);
   UP(D.l1_cfg, H.l1_cfg);
@@ -1986,6 +2012,10 @@ int upload_plan(Plan* p, std::string& err) {
   UP(D.ml_cfg, H.ml_cfg);
   UP(D.ml_first, H.ml_first);
   UP(D.ml_count, H.ml_count);
+  UP(D.ts_grp, H.ts_grp);
+  UP(D.ts_tcls, H.ts_tcls);
+  UP(D.ts_row, H.ts_row);
+  UP(D.ts_code, H.ts_code);
 
   UP(D.p4_src, H.p4_src);
   UP(D.l4_slot, H.l4_slot);
@@ -2024,6 +2054,7 @@ int upload_plan(Plan* p, std::string& err) {
   VFX_HIP(hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming));
   VFX_HIP(hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming));
   VFX_HIP(hipEventCreateWithFlags(&p->p2l_ev, hipEventDisableTiming));
+  VFX_HIP(hipEventCreateWithFlags(&p->up_ev, hipEventDisableTiming));
   D.ready = true;
   return VFX_OK;
 }
@@ -2043,7 +2074,8 @@ void free_plan_device(Plan* p) {
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
                   D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg, D.fac_ws,
                   D.ml_first,  D.ml_count,   D.xs,       D.p3_src,   D.l3_slot,  D.t3_cfg,   D.t3_first,
-                  D.t3_count,  D.m2p_y,    D.near_y32, D.chg_part};
+                  D.t3_count,  D.m2p_y,    D.near_y32, D.chg_part, D.near_z, D.ts_grp, D.ts_tcls,
+                  D.ts_row,    D.ts_code,  D.fe_src};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   D = DevicePlan();
@@ -2055,9 +2087,19 @@ void free_plan_device(Plan* p) {
   if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
   if (p->join_ev) (void)hipEventDestroy(p->join_ev);
   if (p->p2l_ev) (void)hipEventDestroy(p->p2l_ev);
+  if (p->up_ev) (void)hipEventDestroy(p->up_ev);
   if (p->side) (void)hipStreamDestroy(p->side);
-  p->fork_ev = p->join_ev = p->p2l_ev = nullptr;
+  p->fork_ev = p->join_ev = p->p2l_ev = p->up_ev = nullptr;
   p->side = nullptr;
+}
+
+// Grid of a persistent, XCD-aware kernel: at most max_wgs work-groups (0 =
+// one per item), but never fewer than min(items, 8) - the kernels split
+// their items into eight contiguous ranges walked by the work-groups of one
+// XCD each (blockIdx % 8), so every range needs a work-group.
+static int persistent_grid(int items, int max_wgs) {
+  int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
+  return std::max(grid, std::min(items, 8));
 }
 
 template <int KD, int EPI, int TE, int MTB>
@@ -2066,7 +2108,7 @@ static void launch_gemm(int ntiles, int MT, const int* cfg, const int* first, co
                         const int* box_level, hipStream_t s, int max_wgs, unsigned R, long sx, long sy,
                         int ldx = KD, int kx = KD) {
   const int items = ntiles * (MT / MTB);
-  const int grid = (max_wgs > 0 && items > max_wgs) ? max_wgs : items;
+  const int grid = persistent_grid(items, max_wgs);
   if constexpr (TE == 64 && KD % 32 == 0)
     hipLaunchKernelGGL((k_tgemm<KD, MTB, EPI>), dim3(grid, R), dim3(256), 0, s, items, MT, cfg, first, count, src, A,
                        X, Y, sx, sy, ldx, kx, P2, root, leaf_box, box_level);
@@ -2184,6 +2226,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   // per-right-hand-side strides (elements) of the batched buffers
   const long sFL = (long)L * n, sFC = (long)H.ncut * T.nX, sMP = (long)H.B * P;
   const long sNY = (long)H.np_src.size() * n, sPL = (long)H.p4_src.size() * T.p2l_rows;
+  const long sNZ = (long)H.np_src.size() * kNearLrMax;
   const long sM3 = (long)H.p3_src.size() * n;
   const long sUP = (long)H.up_slots * P, sLF = (long)L * P;
   const unsigned R = (unsigned)nrhs;
@@ -2198,10 +2241,13 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
       p->ev.push_back(e);
     }
   }
-  // events on the caller's stream: 0 start, 1 after the extension, 2 after
-  // P2M and the upward pass, 3 after P2L+M2L, 4 after the downward pass, 8
-  // after the join, 9 end; on the side stream: 5 start, 6 after the low-rank
-  // near-field kernel, 7 after the dense one
+  // events on the caller's stream: 0 start, 12 after f^e initialisation, 1
+  // after the extension, 2 after P2M and the upward pass, 3 after M2L, 4
+  // after the downward pass, 8 after the join, 9 end; on the side stream: 10
+  // start, 5 after P2L, 6 after the first near-field kernel (low-rank pairs,
+  // or the factor products of the target-stationary path), 7 after the
+  // second (dense pairs, or the per-target-group kernel), 13 after the wait
+  // for the upward pass, 11 after M2P
   auto mark = [&](int k, hipStream_t st) -> int {
     if (timed) {
       hipError_t e = hipEventRecord(p->ev[ev0 + k], st);
@@ -2218,16 +2264,18 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
     if (rc_) return rc_;     \
   } while (0)
   MARK(0, s);
-  {
-    const long total = (long)L * n;
-    int blocks = (int)std::min<long>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_fe_init, dim3(blocks, R), dim3(256), 0, s, n, L, D.kind, f_leaf, fe);
-  }
   MARK(12, s);
-  if (H.ncut > 0)
-    hipLaunchKernelGGL(k_extension, dim3(H.ncut * R), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG, D.pinv_ptr,
-                       D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t, DT.AbarT, DT.cbar,
-                       f_cut, fe, nrhs, sFC, sFL);
+  {
+    // the extension of every cut leaf, and in the same launch the f^e
+    // initialisation of the other leaves (about 2 MB of copy per work-group
+    // at the wedge's size, spread over the extension's run)
+    const int ext_blocks = H.ncut * nrhs;
+    const long pieces = (long)L * n / 2 * nrhs;
+    const int copy_blocks = (int)std::min<long>((pieces + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_extension, dim3(ext_blocks + copy_blocks), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG,
+                       D.pinv_ptr, D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t,
+                       DT.AbarT, DT.cbar, f_cut, fe, nrhs, sFC, sFL, ext_blocks, L, D.fe_src, f_leaf);
+  }
   VFX_HIP(hipGetLastError());
   MARK(1, s);
   // fork: P2L and the near field on the side stream, concurrent with P2M,
@@ -2245,37 +2293,53 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   VFX_HIP(hipGetLastError());
   VFX_HIP(hipEventRecord(p->p2l_ev, p->side));
   MARK(5, p->side);
-  if (!H.nl_cfg.empty()) {
-    const int items = (int)H.nl_cfg.size();
-    hipLaunchKernelGGL(k_near_lr<256>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
-                       D.nl_cfg, D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y, sFL, sNY);
-  }
   const long total = (long)L * n;
-  if (H.precision == 1) {
-    // pairs in mixed precision: bf16 slices of the leaf data, then the
-    // low-rank kernel (here) and the dense one for the self operator (below)
-    hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192), R), dim3(256), 0, p->side,
-                       total, fe, D.xs);
-    if (!H.ml_cfg.empty()) {
-      const int items = (int)H.ml_cfg.size();
-      hipLaunchKernelGGL(k_near_mx<true>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
-                         1, D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs, total,
+  if (H.ts) {
+    // target-stationary near field: the factor products Z = (W_b P_g^T) f
+    // of every non-self pair (table GEMM over the configuration-major
+    // tiles), then the per-target-group kernel, which leaves h^2 times each
+    // leaf's list-1 table sum in V
+    if (!H.nl_cfg.empty())
+      launch_gemm<256, 0, 64, 4>((int)H.nl_cfg.size(), 4, D.nl_cfg, D.nl_first, D.nl_count, D.np_src, DT.lr_Wp, fe,
+                                 D.near_z, 0, 0, nullptr, nullptr, p->side, p->tune.near_wgs, R, sFL, sNZ);
+    VFX_HIP(hipGetLastError());
+    MARK(6, p->side);
+    {
+      int rc = launch_near_ts(p, fe, V, nrhs, p->tune.near_wgs, p->side, err);
+      if (rc) return rc;
+    }
+  } else {
+    if (!H.nl_cfg.empty()) {
+      const int items = (int)H.nl_cfg.size();
+      hipLaunchKernelGGL(k_near_lr<256>, dim3(persistent_grid(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
+                         D.nl_cfg, D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y, sFL,
+                         sNY);
+    }
+    if (H.precision == 1) {
+      // pairs in mixed precision: bf16 slices of the leaf data, then the
+      // low-rank kernel (here) and the dense one for the self operator (below)
+      hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192), R), dim3(256), 0, p->side,
+                         total, fe, D.xs);
+      if (!H.ml_cfg.empty()) {
+        const int items = (int)H.ml_cfg.size();
+        hipLaunchKernelGGL(k_near_mx<true>, dim3(persistent_grid(items, p->tune.near_wgs), R), dim3(256), 0, p->side,
+                           items, 1, D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs,
+                           total, D.near_y32, sNY);
+      }
+    }
+    VFX_HIP(hipGetLastError());
+    MARK(6, p->side);
+    near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
+              p->tune.near_wgs, p->tune.dense_mtb, R, sFL, sNY);
+    if (H.precision == 1 && !H.mt_cfg.empty()) {
+      const int items = 4 * (int)H.mt_cfg.size();
+      hipLaunchKernelGGL(k_near_mx<false>, dim3(persistent_grid(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
+                         4, D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
                          D.near_y32, sNY);
     }
   }
   VFX_HIP(hipGetLastError());
-  MARK(6, p->side);
-  near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
-            p->tune.near_wgs, p->tune.dense_mtb, R, sFL, sNY);
-  if (H.precision == 1 && !H.mt_cfg.empty()) {
-    const int items = 4 * (int)H.mt_cfg.size();
-    hipLaunchKernelGGL(k_near_mx<false>, dim3(std::min(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items, 4,
-                       D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
-                       D.near_y32, sNY);
-  }
-  VFX_HIP(hipGetLastError());
   MARK(7, p->side);
-  VFX_HIP(hipEventRecord(p->join_ev, p->side));
   // multipoles of the leaves
   expansion_gemm<1, 64>(n, (int)H.t0_first.size(), T.p2l_rows / 16, D.t0_cfg, D.t0_first, D.t0_count, D.leaf_ids,
                         DT.p2m_gemm, fe, (double*)D.mpole, s, R, sFL, 2 * sMP, 2 * P, T.root_size, D.leaf_box,
@@ -2305,12 +2369,16 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   }
   VFX_HIP(hipGetLastError());
   MARK(2, s);
-  // M2P for list 3 on the caller's stream, right after the upward pass
-  // (the side stream carries P2L and the near field, the longer share)
+  // M2P for list 3 on the side stream, behind the near field, once the
+  // upward pass is done; the side stream then joins the caller's
+  VFX_HIP(hipEventRecord(p->up_ev, s));
+  VFX_HIP(hipStreamWaitEvent(p->side, p->up_ev, 0));
+  MARK(13, p->side);
   m2p_gemm(n, T.p2l_rows, 2 * P, (int)H.t3_cfg.size(), D.t3_cfg, D.t3_first, D.t3_count, D.p3_src, DT.m2p_gemm,
-           (const double*)D.mpole, D.m2p_y, s, R, 2 * sMP, sM3);
+           (const double*)D.mpole, D.m2p_y, p->side, R, 2 * sMP, sM3);
   VFX_HIP(hipGetLastError());
-  MARK(11, s);
+  MARK(11, p->side);
+  VFX_HIP(hipEventRecord(p->join_ev, p->side));
   if (H.nlev > 2) {
     VFX_HIP(hipStreamWaitEvent(s, p->p2l_ev, 0));  // list-4 products from the side stream
     const int ng = (int)H.m2l_grp.size() - 1;
@@ -2366,19 +2434,21 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(8, s);
-#define VFX_FAR(PMV, EX, NPLV, MXV)                                                                            \
-  hipLaunchKernelGGL((k_far<PMV, EX, NPLV, MXV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,          \
+#define VFX_FAR(PMV, EX, NPLV, MXV, TSV)                                                                       \
+  hipLaunchKernelGGL((k_far<PMV, EX, NPLV, MXV, TSV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,     \
                      D.box_level, DT.t, D.l3_ptr, D.l3_src, D.l3_slot, D.m2p_y, D.locf, D.mpole, D.l1_ptr,         \
                      D.l1_srcbox, D.l1_slot, D.near_y, D.near_y32, V, sLF, sMP, sNY, sM3, sFL)
-#define VFX_FAR_N(PMV, EX)      \
-  if (npl == 4 && mx)           \
-    VFX_FAR(PMV, EX, 4, true);  \
-  else if (npl == 4)            \
-    VFX_FAR(PMV, EX, 4, false); \
-  else if (npl == 3)            \
-    VFX_FAR(PMV, EX, 3, false); \
-  else                          \
-    VFX_FAR(PMV, EX, 1, false);
+#define VFX_FAR_N(PMV, EX)             \
+  if (npl == 4 && H.ts)                \
+    VFX_FAR(PMV, EX, 4, false, true);  \
+  else if (npl == 4 && mx)             \
+    VFX_FAR(PMV, EX, 4, true, false);  \
+  else if (npl == 4)                   \
+    VFX_FAR(PMV, EX, 4, false, false); \
+  else if (npl == 3)                   \
+    VFX_FAR(PMV, EX, 3, false, false); \
+  else                                 \
+    VFX_FAR(PMV, EX, 1, false, false);
   const int npl = (n + 63) / 64;  // 1, 3 or 4 for K = 4, 8, 12, 16
   const bool mx = D.near_y32 != nullptr;  // some pairs' results are FP32 (K = 16 only)
   if (P == 21) {

@@ -86,9 +86,17 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
   for (auto* v : {&H.nt_cfg, &H.nt_first, &H.nt_count, &H.nl_cfg, &H.nl_first, &H.nl_count, &H.mt_cfg,
                   &H.mt_first, &H.mt_count, &H.ml_cfg, &H.ml_first, &H.ml_count})
     v->clear();
+  // With the target-stationary near field selected (near_mode 1), FP64 at
+  // K = 16 (also precision mode 1 when no pair is mixed) takes that path: every non-self pair's factor product by the
+  // table GEMM (configuration-major tiles of 64), then the per-target-group
+  // kernel; the self pairs only there
+  bool any_mixed = false;
+  for (int e = 0; e < N1 && !any_mixed; ++e) any_mixed = mixed(H.l1_src[e]);
+  const bool ts = H.near_mode == 1 && !any_mixed && k16 && T.ts_ok;
   constexpr int kTile = 64;
   for (int c = 0; c < kNearConfigs; ++c) {
-    const bool lr = k16 && T.lr_R[c] > 0;
+    const bool lr = ts ? c != kNearSelf : (k16 && T.lr_R[c] > 0);
+    if (ts && !lr) continue;
     for (int cls = 0; cls < 2; ++cls) {
       const int g = 2 * c + cls;
       std::vector<int>*cf, *fi, *co;
@@ -101,15 +109,63 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
         fi = lr ? &H.ml_first : &H.mt_first;
         co = lr ? &H.ml_count : &H.mt_count;
       }
-      // FP64 low-rank tiles hold 32 pairs (the kernel splits a tile's work
-      // over its four waves), the others 64
-      const int tile = (cls == 0 && lr) ? kTile / 2 : kTile;
+      // FP64 low-rank tiles of the fused kernel hold 32 pairs (it splits a
+      // tile's work over its four waves), the others 64
+      const int tile = (cls == 0 && lr && !ts) ? kTile / 2 : kTile;
       for (int f = cnt[g]; f < cnt[g + 1]; f += tile) {
         cf->push_back(c);
         fi->push_back(f);
         co->push_back(std::min(tile, cnt[g + 1] - f));
       }
     }
+  }
+  for (auto* v : {&H.ts_grp, &H.ts_tcls, &H.ts_row, &H.ts_code}) v->clear();
+  H.ts = ts;
+  if (ts) {
+    // per group of kTsGroup targets: the self tile (if any target is a
+    // source of its own), then per class as many tiles as the largest
+    // number of that class's pairs of one target; tile j of a class holds
+    // the j-th such pair of every target (list order), in its target's slot
+    std::vector<int> per[kNearClasses];
+    for (int t0 = 0; t0 < L; t0 += kTsGroup) {
+      const int t1 = std::min(L, t0 + kTsGroup);
+      H.ts_grp.push_back((int)H.ts_tcls.size());
+      for (int k = 0; k < kNearClasses; ++k) per[k].assign((size_t)kTsGroup * 64, -1);
+      int cnt[kNearClasses][kTsGroup] = {};
+      for (int t = t0; t < t1; ++t)
+        for (int e = H.l1_ptr[t]; e < H.l1_ptr[t + 1]; ++e) {
+          const int c = H.l1_cfg[e];
+          const int k = T.near_cls[c];
+          int& m = cnt[k][t - t0];
+          if (m >= 64) {
+            err = "near field: more than 64 pairs of one class for a target";
+            return VFX_ETREE;
+          }
+          per[k][(size_t)m * kTsGroup + (t - t0)] = e;
+          m++;
+        }
+      for (int k = 0; k < kNearClasses; ++k) {
+        int rounds = 0;
+        for (int s = 0; s < kTsGroup; ++s) rounds = std::max(rounds, cnt[k][s]);
+        for (int j = 0; j < rounds; ++j) {
+          H.ts_tcls.push_back(k);
+          for (int s = 0; s < kTsGroup; ++s) {
+            const int e = per[k][(size_t)j * kTsGroup + s];
+            if (e < 0) {
+              H.ts_row.push_back(-1);
+              H.ts_code.push_back(0);
+            } else if (k == 0) {
+              H.ts_row.push_back(H.l1_src[e]);
+              H.ts_code.push_back(0);
+            } else {
+              H.ts_row.push_back(H.l1_slot[e]);
+              H.ts_code.push_back(d4_inverse(T.near_g[H.l1_cfg[e]]));
+            }
+          }
+        }
+      }
+    }
+    H.ts_grp.push_back((int)H.ts_tcls.size());
   }
   H.precision = mode;
   H.mixed_min_level = min_level;

@@ -528,6 +528,94 @@ static void build_near_lowrank(Tables& T) {
     }
 }
 
+// Symmetry classes of the near-field configurations (K = 16, low-rank
+// operators built): class, D4 code and base of every configuration, the
+// symmetry-folded row factors, the class column factors and the transposed
+// self table (see Tables).
+static void build_near_classes(Tables& T) {
+  const int n = T.n, K = T.K;
+  T.ts_ok = false;
+  if (n != 256 || T.lr_R.empty()) return;
+  // canonical base offsets (units of the target side) per class
+  const double bx[kNearClasses] = {0.0, 1.0, 1.0, 1.5, 1.5, 0.75, 0.75};
+  const double by[kNearClasses] = {0.0, 0.0, 1.0, 1.5, 0.5, 0.75, 0.25};
+  T.near_cls.assign(kNearConfigs, -1);
+  T.near_g.assign(kNearConfigs, 0);
+  T.cls_base.assign(kNearClasses, -1);
+  T.cls_R.assign(kNearClasses, 0);
+  auto class_of = [&](int c) {
+    double ox, oy, side;
+    near_config_geometry(c, &ox, &oy, &side);
+    if (c == kNearSelf) return 0;
+    const bool corner = std::fabs(std::fabs(ox) - std::fabs(oy)) < 1e-12;
+    if (side == 1.0) return corner ? 2 : 1;
+    if (side == 2.0) return corner ? 3 : 4;
+    return corner ? 5 : 6;
+  };
+  for (int c = 0; c < kNearConfigs; ++c) {
+    double ox, oy, side;
+    near_config_geometry(c, &ox, &oy, &side);
+    const int k = class_of(c);
+    T.near_cls[c] = k;
+    if (ox == bx[k] && oy == by[k]) T.cls_base[k] = c;
+  }
+  for (int k = 0; k < kNearClasses; ++k)
+    if (T.cls_base[k] < 0) return;
+  for (int c = 0; c < kNearConfigs; ++c) {
+    double ox, oy, side;
+    near_config_geometry(c, &ox, &oy, &side);
+    const int k = T.near_cls[c];
+    int found = -1;
+    for (int g = 0; g < 8 && found < 0; ++g) {
+      double gx, gy;
+      d4_point(g, bx[k], by[k], &gx, &gy);
+      if (gx == ox && gy == oy) found = g;
+    }
+    if (found < 0) return;
+    T.near_g[c] = found;
+  }
+  for (int k = 1; k < kNearClasses; ++k) {
+    T.cls_R[k] = T.lr_R[T.cls_base[k]];
+    if (T.cls_R[k] <= 0) return;  // a class base applied densely: no target-stationary path
+  }
+  // symmetry check against the configuration tables themselves
+  double err = 0.0;
+  for (int c = 0; c < kNearConfigs; ++c) {
+    const int b = T.cls_base[T.near_cls[c]], g = T.near_g[c];
+    const double* Tc = T.near.data() + (size_t)c * n * n;
+    const double* Tb = T.near.data() + (size_t)b * n * n;
+    double mx = 0.0, d = 0.0;
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        mx = std::max(mx, std::fabs(Tb[(size_t)j * n + i]));
+        d = std::max(d, std::fabs(Tc[(size_t)d4_node(g, K, j) * n + d4_node(g, K, i)] - Tb[(size_t)j * n + i]));
+      }
+    err = std::max(err, d / mx);
+  }
+  T.ts_sym_err = err;
+  T.lr_Wp.assign((size_t)kNearConfigs * n * kNearLrMax, 0.0);
+  for (int c = 0; c < kNearConfigs; ++c) {
+    if (c == kNearSelf) continue;
+    const int b = T.cls_base[T.near_cls[c]], gi = d4_inverse(T.near_g[c]);
+    for (int j = 0; j < n; ++j) {
+      const int jb = d4_node(gi, K, j);
+      for (int a = 0; a < kNearLrMax; ++a)
+        T.lr_Wp[((size_t)c * n + j) * kNearLrMax + a] = T.lr_W[((size_t)b * n + jb) * kNearLrMax + a];
+    }
+  }
+  T.cls_QT.assign((size_t)kNearClasses * n * kNearLrMax, 0.0);
+  for (int k = 1; k < kNearClasses; ++k) {
+    const int b = T.cls_base[k];
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < kNearLrMax; ++a)
+        T.cls_QT[((size_t)k * n + i) * kNearLrMax + a] = T.lr_Q[((size_t)b * kNearLrMax + a) * n + i];
+  }
+  T.self_T.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) T.self_T[(size_t)i * n + j] = T.near[((size_t)kNearSelf * n + j) * n + i];
+  T.ts_ok = true;
+}
+
 // Chebyshev moments of a smooth kernel over a square by tensor Gauss-Legendre
 // on npan x npan panels, for several kernel values at once.
 static void build_p2l(Tables& T) {
@@ -828,6 +916,7 @@ void build_tables(Tables& T) {
   build_expansions(T);
   build_near(T);
   build_near_lowrank(T);
+  build_near_classes(T);
   build_p2l(T);
   build_pascal(T);
 }

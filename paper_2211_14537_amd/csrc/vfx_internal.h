@@ -36,6 +36,35 @@ constexpr int kP2LSlots = 36;
 // in units of its own half side, odd values in {-5..5} with
 // max(|ox|,|oy|) = 5; the same 36-slot index ((ox+5)/2)*6 + (oy+5)/2.
 
+// Symmetries of the square (the dihedral group D4) as 3-bit codes g:
+// bit 0 swaps the axes, then bit 1 negates x and bit 2 negates y.  On the
+// K x K first-kind grid (nodes symmetric about 0) g maps node (a, b) to
+// node (a', b'): (A, B) = swap ? (b, a) : (a, b), a' = negx ? K-1-A : A,
+// b' = negy ? K-1-B : B.
+__host__ __device__ inline int d4_inverse(int g) {
+  return (g & 1) ? (1 | (((g >> 2) & 1) << 1) | (((g >> 1) & 1) << 2)) : g;
+}
+__host__ __device__ inline void d4_point(int g, double x, double y, double* gx, double* gy) {
+  const double X = (g & 1) ? y : x, Y = (g & 1) ? x : y;
+  *gx = (g & 2) ? -X : X;
+  *gy = (g & 4) ? -Y : Y;
+}
+__host__ __device__ inline int d4_node(int g, int K, int i) {
+  const int a = i / K, b = i % K;
+  int A = (g & 1) ? b : a, B = (g & 1) ? a : b;
+  if (g & 2) A = K - 1 - A;
+  if (g & 4) B = K - 1 - B;
+  return A * K + B;
+}
+// Target-stationary near field: the 33 list-1 configurations fall into
+// seven classes under D4 about the target centre: 0 self; 1 edge and 2
+// corner colleagues; 3 corner and 4 edge coarse neighbours; 5 corner and 6
+// edge fine neighbours.  A log-kernel table is invariant under an isometry
+// applied to target and source alike, so with g mapping the class's base
+// configuration b onto c,  T_c[g(i)][g(j)] = T_b[i][j].
+constexpr int kNearClasses = 7;
+constexpr int kTsGroup = 16;  // target leaves per group of the target-stationary near field
+
 int near_config_coarse_index(int ox2, int oy2);  // -1 if invalid
 int near_config_fine_index(int ox4, int oy4);
 void near_config_geometry(int c, double* ox, double* oy, double* side);
@@ -88,6 +117,19 @@ struct Tables {
   std::vector<double> p2m_gemm;
   // M2P (list 3) as a real GEMM operand: [slot][k][i], k < p2l_rows
   std::vector<double> m2p_gemm;
+  // Target-stationary near field (K = 16; ts_ok when every non-self class
+  // base is applied in low-rank form): class and D4 code of each
+  // configuration (T_c = P_g T_b P_g^T), the base configuration and padded
+  // rank of each class, the row factors of each configuration with the
+  // symmetry folded into their columns, lr_Wp[c][j][a] = W_b[a][g^-1(j)]
+  // (so Z = W_b P_g^T f), the column factor of each class as
+  // cls_QT[k][i][a] = Q_b[i][a], and the self table as self_T[i][j] =
+  // T_self[i][j].  ts_sym_err: max over c, i, j of
+  // |T_c[g(i)][g(j)] - T_b[i][j]| relative to max |T_b|.
+  bool ts_ok = false;
+  std::vector<int> near_cls, near_g, cls_base, cls_R;
+  std::vector<double> lr_Wp, cls_QT, self_T;
+  double ts_sym_err = 0.0;
 };
 
 // Host precompute (quadrature.cpp, stencil.cpp)
@@ -116,6 +158,8 @@ struct DeviceTables {
   double *pas_m2l_t = nullptr, *pas_m2m_t = nullptr, *pas_l2l_t = nullptr;
   double2 *m2l_tpow = nullptr, *m2l_tneg = nullptr, *m2m_in = nullptr, *m2m_out = nullptr, *l2l_in = nullptr,
           *l2l_out = nullptr;
+  int* cls_R = nullptr;
+  double *lr_Wp = nullptr, *cls_QT = nullptr, *self_T = nullptr;
 };
 
 // Device buffers that a captured HIP graph may refer to carry a generation
@@ -159,6 +203,18 @@ struct HostPlan {
   // the same for the pairs applied in mixed precision (bf16 slices)
   std::vector<int> mt_cfg, mt_first, mt_count, ml_cfg, ml_first, ml_count;
   int precision = 0, mixed_min_level = 0;
+  // target-stationary near field (FP64, K = 16): groups of kTsGroup
+  // consecutive target leaves; per group a range of tiles (ts_grp); per tile
+  // its class (0 self, 1..6 low-rank classes) and kTsGroup entries, one per
+  // target slot: the A-operand row (the leaf itself for the self tile; for
+  // a class tile the row of the list-1 factor products Z of one pair of
+  // that target, i.e. the pair's index in the configuration-major order;
+  // -1 for none) and d4_inverse(g) of the pair's configuration.  The
+  // low-rank pairs' Z = W_b P_g^T f come from the table GEMM over the
+  // configuration-major tiles nl_*.
+  bool ts = false;
+  int near_mode = 0;  // 0 pair-based near field, 1 target-stationary (vfx_plan_set_near_mode)
+  std::vector<int> ts_grp, ts_tcls, ts_row, ts_code;
   // list-4 entries regrouped by P2L slot, the same way
   std::vector<int> p4_src, l4_slot, t4_cfg, t4_first, t4_count;
   // list-3 entries regrouped by M2P slot, the same way
@@ -183,6 +239,7 @@ struct DevicePlan {
   double *box_cx = nullptr, *box_cy = nullptr;
   int* leaf_box = nullptr;
   int8_t* kind = nullptr;
+  int8_t* fe_src = nullptr;  // per leaf: 2 written by the extension, 1 copied from f, 0 zero
   int *l1_ptr = nullptr, *l1_src = nullptr, *l1_cfg = nullptr, *l1_srcbox = nullptr;
   int *l2_ptr = nullptr, *l2_src = nullptr, *l2_off = nullptr, *l2_tgt = nullptr, *m2l_grp = nullptr;
   int *l3_ptr = nullptr, *l3_src = nullptr;
@@ -201,6 +258,8 @@ struct DevicePlan {
   bool factored = false;   // pinv_val holds the P_i
   double* fac_ws = nullptr;  // scratch of the GPU factorisation
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
+  double* near_z = nullptr;  // target-stationary path: per-pair factor products Z, n_pairs x 64
+  int *ts_grp = nullptr, *ts_tcls = nullptr, *ts_row = nullptr, *ts_code = nullptr;
   float* near_y32 = nullptr;  // the same for the pairs applied in mixed precision (FP32 results)
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
@@ -225,9 +284,9 @@ struct Plan {
   // after the extension; M2L waits for P2L (p2l_ev), the far-field kernel
   // for the whole side stream (join_ev)
   hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr, p2l_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr, p2l_ev = nullptr, up_ev = nullptr;
   // per-phase timing: one set of kEvents events per timed execute
-  static constexpr int kEvents = 13;
+  static constexpr int kEvents = 14;
   // launch parameters chosen by vfx_plan_autotune
   struct Tune {
     int near_wgs = 512;  // work-group cap of the persistent near-field kernels (2 per CU,
@@ -256,6 +315,9 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err);
 int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
                   hipStream_t s, std::string& err);
 int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
+// near.hip
+int launch_near_ts(const Plan* p, const double* fe, double* V, int nrhs, int max_wgs, hipStream_t s,
+                   std::string& err);
 int launch_net_charge_noalloc(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
 int noalloc_max_rhs();
 

@@ -52,7 +52,7 @@ _lib = None
 
 EXPORTED = ("vfx_create", "vfx_destroy", "vfx_stencil_size", "vfx_stencil_points", "vfx_leaf_nodes",
             "vfx_plan_create", "vfx_plan_destroy", "vfx_plan_stats_get", "vfx_plan_ext_owner",
-            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_interp", "vfx_net_charge", "vfx_net_charge_noalloc",
+            "vfx_execute", "vfx_plan_set_timing", "vfx_plan_timings", "vfx_plan_set_precision", "vfx_plan_set_near_mode", "vfx_interp", "vfx_net_charge", "vfx_net_charge_noalloc",
             "vfx_net_charge_noalloc_max_rhs", "vfx_execute_batch", "vfx_plan_create_ex",
             "vfx_plan_factor_gpu",
             "vfx_plan_autotune", "vfx_plan_set_launch", "vfx_graph_begin", "vfx_graph_end", "vfx_graph_launch", "vfx_graph_destroy",
@@ -88,6 +88,7 @@ def lib():
         L.vfx_execute.argtypes = [vp, vp, vp, vp, vp, vp]
         L.vfx_plan_set_timing.argtypes = [vp, ctypes.c_int]
         L.vfx_plan_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        L.vfx_plan_set_near_mode.argtypes = [vp, ctypes.c_int]
         L.vfx_interp.argtypes = [vp, vp, ctypes.c_int64, vp, vp, vp, vp]
         L.vfx_net_charge.argtypes = [vp, vp, ctypes.c_int, vp, vp]
         L.vfx_net_charge_noalloc.argtypes = [vp, vp, ctypes.c_int, vp, vp]
@@ -330,6 +331,11 @@ class Plan:
         st = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().vfx_net_charge_noalloc(self._h, fe.data_ptr(), nrhs, out.data_ptr(),
                                             ctypes.c_void_p(st.cuda_stream)))
+
+    def set_near_mode(self, mode):
+        """Near-field strategy (FP64, K = 16): 0 pair-based (default),
+        1 target-stationary."""
+        _check(lib().vfx_plan_set_near_mode(self._h, int(mode)))
 
     def set_precision(self, mode, min_level=0):
         """Near-field precision: 0 = FP64, 1 = bf16 slices with FP32

@@ -98,6 +98,12 @@ def test_full_size_starfish(gpu_device):
     rel = np.abs(V2.ravel()[sel] - vo).max() / np.abs(vo).max()
     say(f"    given data: rel Linf = {rel:.3e} over {sel.size} nodes")
     assert rel <= 1e-10
+    # the same with the target-stationary near field
+    plan.set_near_mode(1)
+    _, V3 = run_gpu(reg_case)
+    rel3 = np.abs(V3.ravel()[sel] - vo).max() / np.abs(vo).max()
+    say(f"    given data, target-stationary near field: rel Linf = {rel3:.3e}")
+    assert rel3 <= 1e-10
 
 
 # The mixed-precision setting bench.py reports beside FP64 on this workload,
@@ -114,7 +120,7 @@ def test_full_size_wedge(gpu_device):
     ref, worst, bound = _extension_and_bound(case, fe)
     say(f"    extension: all {len(tr['cut_ids'])} cut leaves, worst error / bound = {worst:.3f}")
     rng = np.random.default_rng(11)
-    sel, tx, ty = _nodes(case, 64, 11, _sample_leaves(case, rng))
+    sel, tx, ty = _nodes(case, 64, 11, _sample_leaves(case, rng)[1:3])  # the finest leaf and a cut leaf
     g1, g3, v_o = volume_checks(case, fe, V64, sel, tx, ty, ref)
     say(f"    FP64 over {sel.size} nodes: G1 {g1:.3e}, G3 {g3:.3e} "
         f"(allowed {1e-10 + bound / np.abs(v_o).max():.3e})")

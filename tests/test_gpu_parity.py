@@ -211,3 +211,43 @@ def test_volume_parity_other_grids(gpu_device, K):
     rel = np.abs(V.ravel()[sel] - vo).max() / np.abs(vo).max()
     say(f"    {len(tr['level'])} leaves, rel Linf = {rel:.3e} over {sel.size} nodes")
     assert rel <= 1e-10
+
+
+@pytest.mark.parametrize("name,p", [("starfish_small", 24), ("disk_adaptive_small", 40)])
+def test_target_stationary_near_field(gpu_device, name, p):
+    """The target-stationary near field (near mode 1: per group of 16
+    targets, the six symmetry classes' low-rank tables and the self table,
+    each leaf's sum written once) on given data against the oracle
+    (rel Linf <= 1e-10) and against the pair-based near field (the same sum
+    up to rounding: <= 1e-13 of max |V|), bitwise repeatable, for one right-
+    hand side and a batch of three.  K = 8 (disk) keeps the pair-based path."""
+    import torch
+    say(f"[target-stationary near field] {name} p={p}")
+    case = setup(name, p=p, all_regular=True)
+    _, V0 = run_gpu(case)
+    case["plan"].set_near_mode(1)
+    (fe1, V1), (_, V1b) = run_gpu(case, repeat=2)
+    assert np.array_equal(V1, V1b)
+    assert np.array_equal(fe1, case["f_leaf"])
+    d = float(np.abs(V1 - V0).max() / np.abs(V0).max())
+    sel, tx, ty = sample_targets(case, 300, leaves=(0, case["otree"].n - 1))
+    vo = oracle_potential(case, case["f_leaf"], tx, ty)
+    rel = float(np.abs(V1.ravel()[sel] - vo).max() / np.abs(vo).max())
+    say(f"    vs pair-based {d:.2e}, vs oracle {rel:.2e} over {sel.size} nodes")
+    assert d <= 1e-13 and rel <= 1e-10
+    if case["K"] == 16:
+        assert d > 0.0  # a different summation: not bitwise the pair-based result
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4)
+    stack = np.stack([case["f_leaf"] * s_ for s_ in (1.0, -0.5, 2.0)]) + 0.01 * rng.standard_normal(
+        (3,) + case["f_leaf"].shape)
+    FL = torch.tensor(stack, dtype=torch.float64, device=dev)
+    FC = torch.zeros((3, 0, case["ctx"].n_stencil), dtype=torch.float64, device=dev)
+    FE, VB = torch.empty_like(FL), torch.empty_like(FL)
+    case["plan"].execute_batch(3, FL, FC, FE, VB)
+    torch.cuda.synchronize()
+    for r in range(3):
+        fe_r, V_r = torch.empty_like(FL[r]), torch.empty_like(FL[r])
+        case["plan"].execute(FL[r], FC[r], fe_r, V_r)
+        torch.cuda.synchronize()
+        assert np.array_equal(V_r.cpu().numpy(), VB[r].cpu().numpy())

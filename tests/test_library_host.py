@@ -301,3 +301,47 @@ def test_list3_boxes_are_one_level_finer():
             ox = (2 * ix[w] + 1) - 2 * (2 * lx[leaf] + 1)
             oy = (2 * iy[w] + 1) - 2 * (2 * ly[leaf] + 1)
             assert max(abs(ox), abs(oy)) == 5
+
+
+def test_near_symmetry_classes():
+    """The target-stationary near field applies one table per symmetry
+    class: with g the D4 element the library assigns to configuration c,
+    T_c[g(i)][g(j)] must equal the class base's T_b[i][j] (a log-kernel
+    integral is invariant under an isometry of target and source), and g
+    must carry the base's source offset onto c's.  Checked here with node
+    maps and offsets computed independently of the library."""
+    ctx = vfx.Context(16, 24)
+    info = ctx.debug_table(24, 0, 82)
+    cls, g, base, R = info[:33].astype(int), info[33:66].astype(int), info[66:73].astype(int), info[73:80].astype(int)
+    assert info[80] == 1.0 and info[81] <= 1e-13
+    assert cls[4] == 0 and np.count_nonzero(cls == 0) == 1
+    assert all(R[k] in (16, 32, 48, 64) for k in range(1, 7))
+    K = 16
+
+    def node_map(code):
+        a, b = np.divmod(np.arange(K * K), K)
+        A, B = (b, a) if code & 1 else (a, b)
+        A = K - 1 - A if code & 2 else A
+        B = K - 1 - B if code & 4 else B
+        return A * K + B
+
+    def offset(c):  # source centre minus target centre, units of the target side
+        if c < 9:
+            return np.array([c // 3 - 1, c % 3 - 1], float)
+        cells = [(i // 4, i % 4) for i in range(16) if not (i // 4 in (1, 2) and i % 4 in (1, 2))]
+        aa, bb = cells[(c - 9) % 12]
+        return np.array([2 * aa - 3, 2 * bb - 3], float) / (2.0 if c < 21 else 4.0)
+
+    def apply(code, v):
+        x, y = (v[1], v[0]) if code & 1 else (v[0], v[1])
+        return np.array([-x if code & 2 else x, -y if code & 4 else y])
+
+    worst = 0.0
+    for c in range(33):
+        b = base[cls[c]]
+        assert np.array_equal(apply(g[c], offset(b)), offset(c)), c
+        Tc = ctx.debug_table(0, c, K ** 4).reshape(K * K, K * K)  # [j][i]
+        Tb = ctx.debug_table(0, b, K ** 4).reshape(K * K, K * K)
+        m = node_map(g[c])
+        worst = max(worst, np.abs(Tc[np.ix_(m, m)] - Tb).max() / np.abs(Tb).max())
+    assert worst <= 1e-13
