@@ -445,8 +445,9 @@ def mixed_sweep(case, plan, fl, fc, fe, V, stream, args, V64, sel=None, v_g=None
            "tolerance": 1e-10,
            "sweep": [dict(r, value=N / (1e-3 * r["ms_per_step"])) for r in rows]}
     if best is not None:
-        out.update({"setting": f"near field of sources at level >= {best['min_level']} in bf16 slices, "
-                               "FP32 accumulation; everything else FP64",
+        out.update({"setting": f"near field of sources at level >= {best['min_level']} on the bf16 matrix "
+                               "cores in four fixed-point slices (exact FP32 block sums, FP64 results); "
+                               "everything else FP64",
                     "min_level": best["min_level"], "value": N / (1e-3 * best["ms_per_step"]),
                     "ms_per_step": best["ms_per_step"], "rel_linf": best["rel_linf"]})
     else:

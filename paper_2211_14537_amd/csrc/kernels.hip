@@ -982,255 +982,6 @@ __global__ void __launch_bounds__(256, 3) k_near_lr(int nitems, const int* __res
 }
 
 // -------------------------------------------------------------------------
-// Mixed-precision near field (K = 16).  Operands are split into three bf16
-// slices, x ~ x0 + x1 + x2 (about 24 significant bits); a product keeps the
-// six slice pairs down to order 2^-24, x0 y0 + x0 y1 + x1 y0 + x0 y2 +
-// x1 y1 + x2 y0, on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16) with
-// FP32 accumulation.  Results are stored as they were accumulated, in FP32
-// (half the bytes of the FP64 pairs' results); the far-field kernel widens
-// them and sums them with the FP64 terms in FP64.  MFMA operands are loaded straight
-// from memory: a lane's eight consecutive contraction values are 16
-// contiguous bytes (tables stored contraction-fastest).
-// v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16]
-// (j = 0..7) and the outputs D[4(l/16)+r][l%16], r = 0..3 (checked on gfx950).
-typedef short vfx_s8 __attribute__((ext_vector_type(8)));
-typedef float vfx_f4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ uint16_t bf16_rne(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_float(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// leaf data -> three bf16 slices, xs[s][leaf][node]
-__global__ void k_split3(long total, const double* __restrict__ x, uint16_t* __restrict__ xs) {
-  x += blockIdx.y * total;  // right-hand side blockIdx.y
-  xs += blockIdx.y * 3 * total;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x) {
-    double r = x[i];
-#pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      const uint16_t h = bf16_rne((float)r);
-      xs[(size_t)s * total + i] = h;
-      r -= (double)bf16_float(h);
-    }
-  }
-}
-
-__device__ __forceinline__ vfx_f4 mfma_bf16(vfx_s8 a, vfx_s8 b, vfx_f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-// acc += A B over the six slice pairs
-__device__ __forceinline__ vfx_f4 mfma_x3(const vfx_s8 a[3], const vfx_s8 b[3], vfx_f4 acc) {
-  acc = mfma_bf16(a[2], b[0], acc);
-  acc = mfma_bf16(a[1], b[1], acc);
-  acc = mfma_bf16(a[0], b[2], acc);
-  acc = mfma_bf16(a[1], b[0], acc);
-  acc = mfma_bf16(a[0], b[1], acc);
-  acc = mfma_bf16(a[0], b[0], acc);
-  return acc;
-}
-
-// Operand staging for the mixed kernels: a block of 64 B-operand rows x 32
-// contraction values x 3 slices, rows padded to 40 bf16 (80 bytes, so the 16
-// rows a quarter-wave reads start in distinct bank groups).  The 256 threads
-// move it in 768 16-byte pieces; consecutive threads take consecutive pieces
-// of a row.
-constexpr int kMxRS = 40;
-constexpr int kMxBuf = 3 * 64 * kMxRS;  // bf16 per staging buffer
-
-struct MxStage {
-  vfx_s8 v[3];
-};
-
-// load the block (rows row0.. of a [s][row][ld] slice array, columns c0..c0+31)
-__device__ __forceinline__ void mx_gload(MxStage& st, const uint16_t* __restrict__ base, size_t slice, int ld,
-                                         int row0, int c0, int nrows) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int q = t + 256 * j, s = q >> 8, rem = q & 255, row = rem >> 2, part = rem & 3;
-    st.v[j] = row < nrows ? *(const vfx_s8*)(base + (size_t)s * slice + (size_t)(row0 + row) * ld + c0 + 8 * part)
-                          : vfx_s8{0, 0, 0, 0, 0, 0, 0, 0};
-  }
-}
-__device__ __forceinline__ void mx_lstore(const MxStage& st, uint16_t* sb) {
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const int q = t + 256 * j, s = q >> 8, rem = q & 255, row = rem >> 2, part = rem & 3;
-    *(vfx_s8*)(sb + s * 64 * kMxRS + row * kMxRS + 8 * part) = st.v[j];
-  }
-}
-// B fragments of row tile r from a staged block
-__device__ __forceinline__ void mx_bfrag(const uint16_t* sb, int r, vfx_s8 b[3]) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int s = 0; s < 3; ++s) b[s] = *(const vfx_s8*)(sb + s * 64 * kMxRS + (16 * r + li) * kMxRS + 8 * lk);
-}
-
-// Phase 1: acc[r] = (this lane's pair row of X) . (B rows 16r..16r+15),
-// r < MT1 (compile-time), over n = 256 contraction values in 8 blocks of 32;
-// B from `wbase` ([s][row][256], slice stride wslice, rows row0..), staged
-// through a ring of two register blocks into the double buffer sbuf; the A
-// fragments (this wave's own rows) come straight from the pair's bf16
-// slices into a ring of three register blocks.  Every global load is issued
-// two compute phases before its data is needed.
-template <int MT1>
-__device__ __forceinline__ void mx_phase1(const uint16_t* __restrict__ xrow, long xs_slice,
-                                          const uint16_t* __restrict__ wbase, size_t wslice, int row0,
-                                          uint16_t* sbuf, vfx_f4 acc[4]) {
-  constexpr int n = 256, NKB = n / 32;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = vfx_f4{0, 0, 0, 0};
-  MxStage st[2];
-  vfx_s8 a[3][3];
-  auto ga = [&](auto kbc, auto slc) __attribute__((always_inline)) {
-    constexpr int kb = decltype(kbc)::value, sl = decltype(slc)::value;
-#pragma unroll
-    for (int s = 0; s < 3; ++s) a[sl][s] = *(const vfx_s8*)(xrow + (size_t)s * xs_slice + 32 * kb);
-  };
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  ga(I0{}, I0{});
-  mx_gload(st[0], wbase, wslice, n, row0, 0, 16 * MT1);
-  ga(I1{}, I1{});
-  mx_gload(st[1], wbase, wslice, n, row0, 32, 16 * MT1);
-  __syncthreads();  // the previous user of sbuf is done
-  mx_lstore(st[0], sbuf);
-  __syncthreads();
-  static_for<0, NKB>([&](auto kbc) __attribute__((always_inline)) {
-    constexpr int kb = decltype(kbc)::value;
-    if constexpr (kb + 2 < NKB) {
-      ga(std::integral_constant<int, kb + 2>{}, std::integral_constant<int, (kb + 2) % 3>{});
-      mx_gload(st[kb % 2], wbase, wslice, n, row0, 32 * (kb + 2), 16 * MT1);
-    }
-    const uint16_t* sb = sbuf + (kb % 2) * kMxBuf;
-#pragma unroll
-    for (int r = 0; r < MT1; ++r) {
-      vfx_s8 b[3];
-      mx_bfrag(sb, r, b);
-      acc[r] = mfma_x3(a[kb % 3], b, acc[r]);
-    }
-    if constexpr (kb + 1 < NKB) mx_lstore(st[(kb + 1) % 2], sbuf + ((kb + 1) % 2) * kMxBuf);
-    __syncthreads();
-  });
-}
-
-// One work item: a tile of <= 64 pairs of one configuration (wave w owns
-// pairs 16w..16w+15).  LR: Z = X W^T (R_c ranks), then Y = Z Q^T with Z
-// re-split into bf16 slices; dense (self operator): Y = X A^T for one block
-// of 64 target rows (four row blocks per tile).  Persistent, XCD-aware item
-// order as in k_gemm.
-template <bool LR>
-__global__ void __launch_bounds__(256) k_near_mx(int nitems, int nrb, const int* __restrict__ t_cfg,
-                                                 const int* __restrict__ t_first, const int* __restrict__ t_count,
-                                                 const int* __restrict__ src, const int* __restrict__ lr_R,
-                                                 const uint16_t* __restrict__ Wb, const uint16_t* __restrict__ Qb,
-                                                 const uint16_t* __restrict__ xs, long xs_slice,
-                                                 float* __restrict__ Y, long sy) {
-  xs += blockIdx.y * 3 * xs_slice;  // right-hand side blockIdx.y
-  Y += blockIdx.y * sy;
-  constexpr int n = 256, LM = kNearLrMax, LDZ = LM + 4;
-  __shared__ __attribute__((aligned(16))) uint16_t sbuf[2 * kMxBuf];
-  __shared__ float sZ[LR ? 64 * LDZ : 1];
-  const int nb = gridDim.x, bb = blockIdx.x;
-  const int x = bb & 7;
-  const int q = nitems >> 3, rr = nitems & 7;
-  const int xfirst = x * q + min(x, rr), xcount = q + (x < rr ? 1 : 0);
-  const int xwgs = (nb - x + 7) >> 3;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  for (int j = bb >> 3; j < xcount; j += xwgs) {
-    const int item = xfirst + j;
-    const int tile = item / nrb, rb = item - tile * nrb;
-    const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
-    const int ent = 16 * w + li;  // this lane's A-operand pair
-    const int leaf = src[p0 + (ent < np ? ent : 0)];
-    const uint16_t* xrow = xs + (size_t)leaf * n + 8 * lk;
-    const int MT1 = LR ? lr_R[c] / 16 : 4;
-    const size_t wslice = LR ? (size_t)LM * n : (size_t)n * n;
-    const uint16_t* wbase = LR ? Wb + (size_t)c * 3 * wslice : Wb;
-    const int row0 = LR ? 0 : 64 * rb;
-    vfx_f4 acc[4];
-    switch (MT1) {
-      case 1: mx_phase1<1>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
-      case 2: mx_phase1<2>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
-      case 3: mx_phase1<3>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
-      default: mx_phase1<4>(xrow, xs_slice, wbase, wslice, row0, sbuf, acc); break;
-    }
-    if (!LR) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int pe = 16 * w + 4 * lk + e;
-          if (pe < np) Y[(size_t)(p0 + pe) * n + 64 * rb + 16 * r + li] = acc[r][e];
-        }
-      continue;
-    }
-    // Z (FP32) of this wave's pairs to LDS, ranks >= R zero
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) sZ[(16 * w + 4 * lk + e) * LDZ + 16 * r + li] = r < MT1 ? acc[r][e] : 0.0f;
-    // phase 2: Y = Z Q^T; stages (rank block kb, row chunk ch of 64 rows),
-    // Q blocks staged through sbuf
-    const uint16_t* qbase = Qb + (size_t)c * 3 * LM * n;
-    const int nkb = (16 * MT1 + 31) / 32, nst = 4 * nkb;
-    vfx_f4 acc2[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc2[r] = vfx_f4{0, 0, 0, 0};
-    MxStage st;
-    mx_gload(st, qbase, (size_t)LM * n, LM, 0, 0, 64);
-    __syncthreads();  // phase-1 reads of sbuf and the Z writes are done
-    mx_lstore(st, sbuf);
-    __syncthreads();
-    vfx_s8 a[3];
-    for (int sg = 0; sg < nst; ++sg) {
-      const int kb = sg >> 2, ch = sg & 3, qb = sg & 1;
-      if (sg + 1 < nst) mx_gload(st, qbase, (size_t)LM * n, LM, 64 * ((sg + 1) & 3), 32 * ((sg + 1) >> 2), 64);
-      if (ch == 0) {
-        const float* zr = sZ + (16 * w + li) * LDZ + 32 * kb + 8 * lk;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          float v = zr[t];
-#pragma unroll
-          for (int s = 0; s < 3; ++s) {
-            const uint16_t h = bf16_rne(v);
-            a[s][t] = (short)h;
-            v -= bf16_float(h);
-          }
-        }
-      }
-      const uint16_t* sb = sbuf + qb * kMxBuf;
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        vfx_s8 b[3];
-        mx_bfrag(sb, r4, b);
-        switch (ch) {  // row tile 4 ch + r4 (the accumulators stay in registers)
-          case 0: acc2[r4] = mfma_x3(a, b, acc2[r4]); break;
-          case 1: acc2[4 + r4] = mfma_x3(a, b, acc2[4 + r4]); break;
-          case 2: acc2[8 + r4] = mfma_x3(a, b, acc2[8 + r4]); break;
-          default: acc2[12 + r4] = mfma_x3(a, b, acc2[12 + r4]); break;
-        }
-      }
-      if (sg + 1 < nst) mx_lstore(st, sbuf + (qb ^ 1) * kMxBuf);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int pe = 16 * w + 4 * lk + e;
-        if (pe < np) Y[(size_t)(p0 + pe) * n + 16 * r + li] = acc2[r][e];
-      }
-  }
-}
-
-// -------------------------------------------------------------------------
 // Upward pass without the level-by-level chain.  The multipole of a non-leaf
 // box B (level >= 2) about its own centre is the sum, over the leaves L below
 // it, of the leaf multipoles shifted to B.  The shifted coefficients b_l
@@ -1468,8 +1219,6 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
 // expansion, the list slots) comes in with one vector load, lane k holding
 // item k, and is broadcast with readlane, so no step waits on a chain of
 // scalar loads.  One wave per leaf keeps the whole grid resident at once.
-// With MX, a negative list-1 slot -1 - s names a pair applied in mixed
-// precision, whose products are read from the FP32 buffer and widened.
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)u, l);
@@ -1477,7 +1226,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-template <int PM, bool EXACT, int NPL, bool MX, bool NTS>
+template <int PM, bool EXACT, int NPL, bool NTS>
 __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, const int* __restrict__ leaf_box,
                                             const int* __restrict__ box_level, const double* __restrict__ t,
                                             const int* __restrict__ l3_ptr, const int* __restrict__ l3_src,
@@ -1485,13 +1234,12 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
                                             const double2* __restrict__ locf, const double2* __restrict__ mpole,
                                             const int* __restrict__ l1_ptr, const int* __restrict__ l1_srcbox,
                                             const int* __restrict__ l1_slot, const double* __restrict__ Y,
-                                            const float* __restrict__ Y32, double* __restrict__ V, long slf,
+                                            double* __restrict__ V, long slf,
                                             long smp, long sny, long sy3, long sv) {
   const int P = EXACT ? PM : Prt;  // <= 64
   locf += blockIdx.y * slf;        // right-hand side blockIdx.y
   mpole += blockIdx.y * smp;
   Y += blockIdx.y * sny;
-  if (MX) Y32 += blockIdx.y * sny;
   Y3 += blockIdx.y * sy3;
   V += blockIdx.y * sv;
   const int n = K * K;
@@ -1530,16 +1278,9 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
     } else {
 #pragma unroll 4
       for (int e = 0; e < n1; ++e) {
-        const int sl = __builtin_amdgcn_readlane(my_slot, e);
-        if (!MX || sl >= 0) {
-          const double* y = Y + (size_t)sl * n;
+        const double* y = Y + (size_t)__builtin_amdgcn_readlane(my_slot, e) * n;
 #pragma unroll
-          for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
-        } else {  // a pair applied in mixed precision: FP32 result
-          const float* y = Y32 + (size_t)(-1 - sl) * n;
-#pragma unroll
-          for (int j = 0; j < NPL; ++j) yn[j] += (double)y[node[j]];
-        }
+        for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
         lg += readlane_d(my_a0, e);
       }
     }
@@ -1856,15 +1597,18 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.lr_R, T.lr_R);
   UP(D.lr_W, T.lr_W);
   UP(D.lr_Q, T.lr_Q);
-  UP(D.lr_Wb, T.lr_Wb);
+  UP(D.fx_W, T.fx_W);
+  UP(D.fx_Wexp, T.fx_Wexp);
   if (T.ts_ok) {
     UP(D.cls_R, T.cls_R);
     UP(D.lr_Wp, T.lr_Wp);
     UP(D.cls_QT, T.cls_QT);
     UP(D.self_T, T.self_T);
   }
-  UP(D.lr_Qb, T.lr_Qb);
-  UP(D.self_Ab, T.self_Ab);
+  UP(D.fx_Q, T.fx_Q);
+  UP(D.fx_Qexp, T.fx_Qexp);
+  UP(D.fx_A, T.fx_A);
+  UP(D.fx_Aexp, T.fx_Aexp);
   UP(D.p2l_gemm, T.p2l_gemm);
   UP(D.m2p_gemm, T.m2p_gemm);
   UP(D.p2m_gemm, T.p2m_gemm);
@@ -1912,7 +1656,8 @@ void free_tables_device(Context* c) {
                   D.p2m,      D.l2p,      D.m2m,      D.l2l,     D.m2l,      D.p2l,     D.p2l_area,
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2p_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
-                  D.lr_R,     D.lr_W,     D.lr_Q,     D.lr_Wb,    D.lr_Qb,    D.self_Ab,
+                  D.lr_R,     D.lr_W,     D.lr_Q,     D.fx_W,     D.fx_Q,     D.fx_A,     D.fx_Wexp,
+                  D.fx_Qexp,  D.fx_Aexp,
                   D.cls_R,    D.lr_Wp,    D.cls_QT,   D.self_T};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1929,13 +1674,13 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   const size_t P = T.p + 1, R = (size_t)nrhs;
   if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
   p->gen++;  // graphs that captured the old buffers are stale
-  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.near_y32, D.near_z};
+  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.xs_exp, D.near_z};
   for (void* q : old)
     if (q) (void)hipFree(q);
   D.mpole = D.local = D.up_part = D.locf = nullptr;
   D.near_y = D.p2l_y = D.m2p_y = D.near_z = nullptr;
-  D.near_y32 = nullptr;
   D.xs = nullptr;
+  D.xs_exp = nullptr;
   D.cap = 0;
   VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P * R));
   VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P * R));
@@ -1947,9 +1692,10 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   if (!H.p3_src.empty()) VFX_HIP(hipMalloc((void**)&D.m2p_y, sizeof(double) * H.p3_src.size() * T.n * R));
   if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P * R));
   VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P * R));
-  if (H.precision == 1) VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 3 * (size_t)H.L * T.n * R));
-  if (H.precision == 1 && !H.np_src.empty())
-    VFX_HIP(hipMalloc((void**)&D.near_y32, sizeof(float) * H.np_src.size() * T.n * R));
+  if (H.precision == 1 && !H.ts) {
+    VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 4 * (size_t)H.L * T.n * R));
+    VFX_HIP(hipMalloc((void**)&D.xs_exp, sizeof(int) * (size_t)H.L * R));
+  }
   D.cap = nrhs;
   return VFX_OK;
 }
@@ -2074,7 +1820,7 @@ void free_plan_device(Plan* p) {
                   D.nl_cfg,    D.nl_first,   D.nl_count, D.l1_srcbox,  D.ext_geo,
                   D.anc_leaf,  D.dn_grp,     D.locf,     D.mt_cfg,   D.mt_first, D.mt_count, D.ml_cfg, D.fac_ws,
                   D.ml_first,  D.ml_count,   D.xs,       D.p3_src,   D.l3_slot,  D.t3_cfg,   D.t3_first,
-                  D.t3_count,  D.m2p_y,    D.near_y32, D.chg_part, D.near_z, D.ts_grp, D.ts_tcls,
+                  D.t3_count,  D.m2p_y,    D.xs_exp,   D.chg_part, D.near_z, D.ts_grp, D.ts_tcls,
                   D.ts_row,    D.ts_code,  D.fe_src};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -2316,27 +2062,15 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
                          sNY);
     }
     if (H.precision == 1) {
-      // pairs in mixed precision: bf16 slices of the leaf data, then the
-      // low-rank kernel (here) and the dense one for the self operator (below)
-      hipLaunchKernelGGL(k_split3, dim3((int)std::min<long>((total + 255) / 256, 8192), R), dim3(256), 0, p->side,
-                         total, fe, D.xs);
-      if (!H.ml_cfg.empty()) {
-        const int items = (int)H.ml_cfg.size();
-        hipLaunchKernelGGL(k_near_mx<true>, dim3(persistent_grid(items, p->tune.near_wgs), R), dim3(256), 0, p->side,
-                           items, 1, D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.lr_Wb, DT.lr_Qb, D.xs,
-                           total, D.near_y32, sNY);
-      }
+      // pairs in mixed precision: fixed-point bf16 slices of the leaf data,
+      // then their low-rank and self products (FP64 results, same buffer)
+      int rc = launch_near_fx(p, fe, nrhs, p->tune.near_wgs, p->side, err);
+      if (rc) return rc;
     }
     VFX_HIP(hipGetLastError());
     MARK(6, p->side);
     near_gemm(n, (int)H.nt_cfg.size(), D.nt_cfg, D.nt_first, D.nt_count, D.np_src, DT.near, fe, D.near_y, p->side,
               p->tune.near_wgs, p->tune.dense_mtb, R, sFL, sNY);
-    if (H.precision == 1 && !H.mt_cfg.empty()) {
-      const int items = 4 * (int)H.mt_cfg.size();
-      hipLaunchKernelGGL(k_near_mx<false>, dim3(persistent_grid(items, p->tune.near_wgs), R), dim3(256), 0, p->side, items,
-                         4, D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.self_Ab, DT.lr_Qb, D.xs, total,
-                         D.near_y32, sNY);
-    }
   }
   VFX_HIP(hipGetLastError());
   MARK(7, p->side);
@@ -2434,23 +2168,20 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   MARK(4, s);
   VFX_HIP(hipStreamWaitEvent(s, p->join_ev, 0));  // join
   MARK(8, s);
-#define VFX_FAR(PMV, EX, NPLV, MXV, TSV)                                                                       \
-  hipLaunchKernelGGL((k_far<PMV, EX, NPLV, MXV, TSV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,     \
+#define VFX_FAR(PMV, EX, NPLV, TSV)                                                                            \
+  hipLaunchKernelGGL((k_far<PMV, EX, NPLV, TSV>), dim3(L, R), dim3(64), 0, s, T.K, P, T.root_size, D.leaf_box,      \
                      D.box_level, DT.t, D.l3_ptr, D.l3_src, D.l3_slot, D.m2p_y, D.locf, D.mpole, D.l1_ptr,         \
-                     D.l1_srcbox, D.l1_slot, D.near_y, D.near_y32, V, sLF, sMP, sNY, sM3, sFL)
-#define VFX_FAR_N(PMV, EX)             \
-  if (npl == 4 && H.ts)                \
-    VFX_FAR(PMV, EX, 4, false, true);  \
-  else if (npl == 4 && mx)             \
-    VFX_FAR(PMV, EX, 4, true, false);  \
-  else if (npl == 4)                   \
-    VFX_FAR(PMV, EX, 4, false, false); \
-  else if (npl == 3)                   \
-    VFX_FAR(PMV, EX, 3, false, false); \
-  else                                 \
-    VFX_FAR(PMV, EX, 1, false, false);
+                     D.l1_srcbox, D.l1_slot, D.near_y, V, sLF, sMP, sNY, sM3, sFL)
+#define VFX_FAR_N(PMV, EX)      \
+  if (npl == 4 && H.ts)         \
+    VFX_FAR(PMV, EX, 4, true);  \
+  else if (npl == 4)            \
+    VFX_FAR(PMV, EX, 4, false); \
+  else if (npl == 3)            \
+    VFX_FAR(PMV, EX, 3, false); \
+  else                          \
+    VFX_FAR(PMV, EX, 1, false);
   const int npl = (n + 63) / 64;  // 1, 3 or 4 for K = 4, 8, 12, 16
-  const bool mx = D.near_y32 != nullptr;  // some pairs' results are FP32 (K = 16 only)
   if (P == 21) {
     VFX_FAR_N(21, true)
   } else if (P == 25) {

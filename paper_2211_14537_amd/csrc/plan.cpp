@@ -53,7 +53,9 @@ inline bool touch(int la, int ax, int ay, int lb, int bx, int by) {
 
 // List-1 pairs grouped for the near-field kernels: configuration-major, and
 // inside a configuration by precision class (mode 1: sources at level >=
-// min_level are applied in mixed precision), then by target.  Tiles of <= 64
+// min_level are applied in mixed precision: the self operator densely, the
+// other configurations in their low-rank form, so a configuration without
+// one stays in FP64), then by target.  Tiles of <= 64
 // pairs go to the low-rank or the dense kernel of their class.  l1_slot maps
 // every per-target list-1 entry to its pair.
 int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std::string& err) {
@@ -64,12 +66,13 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
     err = "mixed precision is available for K = 16 only";
     return VFX_EINVAL;
   }
-  auto mixed = [&](int src_leaf) {
-    return mode == 1 && H.box_level[H.leaf_box[src_leaf]] >= min_level;
+  auto mixed = [&](int e) {
+    const int c = H.l1_cfg[e];
+    return mode == 1 && H.box_level[H.leaf_box[H.l1_src[e]]] >= min_level && (c == kNearSelf || T.lr_R[c] > 0);
   };
   // counting sort on (configuration, class)
   std::vector<int> cnt(2 * kNearConfigs + 1, 0);
-  for (int e = 0; e < N1; ++e) cnt[2 * H.l1_cfg[e] + (mixed(H.l1_src[e]) ? 1 : 0) + 1]++;
+  for (int e = 0; e < N1; ++e) cnt[2 * H.l1_cfg[e] + (mixed(e) ? 1 : 0) + 1]++;
   for (int g = 0; g < 2 * kNearConfigs; ++g) cnt[g + 1] += cnt[g];
   H.np_src.assign(N1, 0);
   H.np_tgt.assign(N1, 0);
@@ -77,11 +80,10 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
   std::vector<int> pos(cnt.begin(), cnt.end() - 1);
   for (int leaf = 0; leaf < L; ++leaf)  // targets ascending inside each group
     for (int e = H.l1_ptr[leaf]; e < H.l1_ptr[leaf + 1]; ++e) {
-      const int s = pos[2 * H.l1_cfg[e] + (mixed(H.l1_src[e]) ? 1 : 0)]++;
+      const int s = pos[2 * H.l1_cfg[e] + (mixed(e) ? 1 : 0)]++;
       H.np_src[s] = H.l1_src[e];
       H.np_tgt[s] = leaf;
-      // a mixed pair's result lives in the FP32 partials: slot -1 - s
-      H.l1_slot[e] = mixed(H.l1_src[e]) ? -1 - s : s;
+      H.l1_slot[e] = s;
     }
   for (auto* v : {&H.nt_cfg, &H.nt_first, &H.nt_count, &H.nl_cfg, &H.nl_first, &H.nl_count, &H.mt_cfg,
                   &H.mt_first, &H.mt_count, &H.ml_cfg, &H.ml_first, &H.ml_count})
@@ -91,7 +93,7 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
   // table GEMM (configuration-major tiles of 64), then the per-target-group
   // kernel; the self pairs only there
   bool any_mixed = false;
-  for (int e = 0; e < N1 && !any_mixed; ++e) any_mixed = mixed(H.l1_src[e]);
+  for (int e = 0; e < N1 && !any_mixed; ++e) any_mixed = mixed(e);
   const bool ts = H.near_mode == 1 && !any_mixed && k16 && T.ts_ok;
   constexpr int kTile = 64;
   for (int c = 0; c < kNearConfigs; ++c) {

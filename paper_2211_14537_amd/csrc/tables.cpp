@@ -382,27 +382,33 @@ static void build_near(Tables& T) {
   }
 }
 
-// bf16 with round-to-nearest-even of a float (finite inputs)
-static uint16_t bf16_rne(float f) {
+// Fixed-point bf16 slices of a vector v (one row of a mixed-precision MFMA
+// operand, along the contraction): with e the exponent of max |v|
+// (max |v| 2^-e in [1/2, 1)), v_k = 2^e sum_{s<4} q_s[k] 2^(-8(s+1)) up to
+// 2^(e-33), each q_s[k] an integer of magnitude <= 256 (exact in bf16).
+// Products of two such slices and their sums over 32 terms stay integers
+// below 2^24, so the bf16 matrix cores sum them exactly in FP32.
+static uint16_t bf16_of_int(double q) {
+  const float f = (float)q;  // |q| <= 256: exact, and exact in bf16
   uint32_t u;
   std::memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-static double bf16_value(uint16_t h) {
-  const uint32_t u = (uint32_t)h << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
-// x ~ s0 + s1 + s2 (each bf16; the residual after three slices is about
-// 2^-24 |x|)
-static void bf16_split3(double x, uint16_t s[3]) {
-  double r = x;
-  for (int k = 0; k < 3; ++k) {
-    s[k] = bf16_rne((float)r);
-    r -= bf16_value(s[k]);
+static int fx_split(const double* v, int count, long stride, uint16_t* out, long slice_stride, long out_stride) {
+  double m = 0.0;
+  for (int k = 0; k < count; ++k) m = std::max(m, std::fabs(v[k * stride]));
+  int e = 0;
+  if (m > 0.0) std::frexp(m, &e);
+  for (int k = 0; k < count; ++k) {
+    double r = std::ldexp(v[k * stride], -e);
+    for (int sl = 0; sl < 4; ++sl) {
+      r *= 256.0;
+      const double q = std::nearbyint(r);
+      out[sl * slice_stride + k * out_stride] = bf16_of_int(q);
+      r -= q;
+    }
   }
+  return e;
 }
 
 // Truncated rank-revealing factorisation of the n x n near-field operator
@@ -502,30 +508,29 @@ static void build_near_lowrank(Tables& T) {
         T.lr_Q[((size_t)c * kNearLrMax + a) * n + j] = Q[(size_t)j * r + a];
       }
   }
-  // bf16 slices for the mixed-precision kernels (K = 16)
+  // fixed-point bf16 slices for the mixed-precision kernels (K = 16):
+  // W rows (rank a, along j), Q rows (target node i, along a), self table
+  // rows (target node i, along j), each with its exponent
   if (n != 256) return;
   const size_t SW = (size_t)kNearLrMax * n;  // one slice of one configuration
-  T.lr_Wb.assign((size_t)kNearConfigs * 3 * SW, 0);
-  T.lr_Qb.assign((size_t)kNearConfigs * 3 * SW, 0);
-  T.self_Ab.assign((size_t)3 * n * n, 0);
-  for (int c = 0; c < kNearConfigs; ++c)
-    for (int a = 0; a < kNearLrMax; ++a)
-      for (int j = 0; j < n; ++j) {
-        uint16_t w3[3], q3[3];
-        bf16_split3(T.lr_W[((size_t)c * n + j) * kNearLrMax + a], w3);
-        bf16_split3(T.lr_Q[((size_t)c * kNearLrMax + a) * n + j], q3);
-        for (int s = 0; s < 3; ++s) {
-          T.lr_Wb[((size_t)c * 3 + s) * SW + (size_t)a * n + j] = w3[s];
-          T.lr_Qb[((size_t)c * 3 + s) * SW + (size_t)j * kNearLrMax + a] = q3[s];
-        }
-      }
-  const int cs = kNearSelf;
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      uint16_t a3[3];
-      bf16_split3(T.near[((size_t)cs * n + j) * n + i], a3);
-      for (int s = 0; s < 3; ++s) T.self_Ab[((size_t)s * n + i) * n + j] = a3[s];
-    }
+  T.fx_W.assign((size_t)kNearConfigs * 4 * SW, 0);
+  T.fx_Q.assign((size_t)kNearConfigs * 4 * SW, 0);
+  T.fx_A.assign((size_t)4 * n * n, 0);
+  T.fx_Wexp.assign((size_t)kNearConfigs * kNearLrMax, 0);
+  T.fx_Qexp.assign((size_t)kNearConfigs * n, 0);
+  T.fx_Aexp.assign(n, 0);
+  for (int c = 0; c < kNearConfigs; ++c) {
+    for (int a = 0; a < kNearLrMax; ++a)  // fx_W[c][s][a][j] = W[a][j]
+      T.fx_Wexp[(size_t)c * kNearLrMax + a] =
+          fx_split(&T.lr_W[(size_t)c * n * kNearLrMax + a], n, kNearLrMax,
+                   &T.fx_W[(size_t)c * 4 * SW + (size_t)a * n], (long)SW, 1);
+    for (int i = 0; i < n; ++i)  // fx_Q[c][s][i][a] = Q[i][a]
+      T.fx_Qexp[(size_t)c * n + i] =
+          fx_split(&T.lr_Q[(size_t)c * kNearLrMax * n + i], kNearLrMax, n,
+                   &T.fx_Q[(size_t)c * 4 * SW + (size_t)i * kNearLrMax], (long)SW, 1);
+  }
+  for (int i = 0; i < n; ++i)  // fx_A[s][i][j] = T_self[i][j] = near[self][j][i]
+    T.fx_Aexp[i] = fx_split(&T.near[(size_t)kNearSelf * n * n + i], n, n, &T.fx_A[(size_t)i * n], (long)n * n, 1);
 }
 
 // Symmetry classes of the near-field configurations (K = 16, low-rank

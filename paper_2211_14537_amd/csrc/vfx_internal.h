@@ -84,11 +84,14 @@ struct Tables {
   std::vector<int> lr_R, lr_rank;      // 33: padded rank (0 = dense), rank
   std::vector<double> lr_W;            // 33 x n x kNearLrMax, [c][j][a]
   std::vector<double> lr_Q;            // 33 x kNearLrMax x n, [c][a][i]
-  // bf16 slices (x ~ s0 + s1 + s2) of the K = 16 near-field operators as
-  // MFMA B operands, contraction index fastest:
-  //   lr_Wb [c][s][a][j] = W[a][j],  lr_Qb [c][s][i][a] = Q[i][a],
-  //   self_Ab [s][i][j] = self table, row i (target node), column j
-  std::vector<uint16_t> lr_Wb, lr_Qb, self_Ab;
+  // fixed-point bf16 slices of the K = 16 near-field operators as MFMA B
+  // operands, contraction index fastest, 4 slices, one exponent per row:
+  //   fx_W [c][s][a][j] = W[a][j] (exponent per rank a),
+  //   fx_Q [c][s][i][a] = Q[i][a] (exponent per target node i),
+  //   fx_A [s][i][j] = self table, row i (target node), column j
+  // (v = 2^e sum_s q_s 2^(-8(s+1)), q_s integers of magnitude <= 256)
+  std::vector<uint16_t> fx_W, fx_Q, fx_A;
+  std::vector<int> fx_Wexp, fx_Qexp, fx_Aexp;
   std::vector<double> p2m;             // (p+1) x n complex, [k][j] (re,im)
   std::vector<double> l2p;             // n x (p+1) complex, [i][l]
   std::vector<double> m2m;             // 4 x (p+1) x (p+1) complex, [q][k][l]
@@ -150,7 +153,8 @@ struct DeviceTables {
   double *near = nullptr, *near_s2 = nullptr;
   int* lr_R = nullptr;
   double *lr_W = nullptr, *lr_Q = nullptr;
-  uint16_t *lr_Wb = nullptr, *lr_Qb = nullptr, *self_Ab = nullptr;
+  uint16_t *fx_W = nullptr, *fx_Q = nullptr, *fx_A = nullptr;
+  int *fx_Wexp = nullptr, *fx_Qexp = nullptr, *fx_Aexp = nullptr;
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
@@ -253,14 +257,14 @@ struct DevicePlan {
   int *nl_cfg = nullptr, *nl_first = nullptr, *nl_count = nullptr;
   int *mt_cfg = nullptr, *mt_first = nullptr, *mt_count = nullptr, *ml_cfg = nullptr, *ml_first = nullptr,
       *ml_count = nullptr;
-  uint16_t* xs = nullptr;  // bf16 slices of the leaf data, 3 x L x n
+  uint16_t* xs = nullptr;  // fixed-point bf16 slices of the leaf data, 4 x L x n
+  int* xs_exp = nullptr;   // their exponent per leaf, L
   int cap = 0;             // right-hand sides the per-RHS buffers hold
   bool factored = false;   // pinv_val holds the P_i
   double* fac_ws = nullptr;  // scratch of the GPU factorisation
   double* near_y = nullptr;  // per-pair partial potentials, n_pairs x n
   double* near_z = nullptr;  // target-stationary path: per-pair factor products Z, n_pairs x 64
   int *ts_grp = nullptr, *ts_tcls = nullptr, *ts_row = nullptr, *ts_code = nullptr;
-  float* near_y32 = nullptr;  // the same for the pairs applied in mixed precision (FP32 results)
   int *p4_src = nullptr, *l4_slot = nullptr, *t4_cfg = nullptr, *t4_first = nullptr, *t4_count = nullptr;
   int *leaf_ids = nullptr, *t0_cfg = nullptr, *t0_first = nullptr, *t0_count = nullptr;
   double* p2l_y = nullptr;   // per-entry P2L partial locals, n_list4 x p2l_rows
@@ -315,6 +319,8 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err);
 int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
                   hipStream_t s, std::string& err);
 int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
+// mixed.hip
+int launch_near_fx(const Plan* p, const double* fe, int nrhs, int max_wgs, hipStream_t s, std::string& err);
 // near.hip
 int launch_near_ts(const Plan* p, const double* fe, double* V, int nrhs, int max_wgs, hipStream_t s,
                    std::string& err);

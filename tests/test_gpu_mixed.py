@@ -1,8 +1,9 @@
 """Mixed-precision near field against the oracle and the FP64 path.
 
 The list-1 interactions of sources at level >= min_level run on the bf16
-matrix cores (three bf16 slices per operand, FP32 accumulation); everything
-else stays FP64.  The tests state the error of V against the oracle's direct
+matrix cores (four fixed-point bf16 slices per operand row, exact FP32 sums
+per block of 128 contraction indices, FP64 results); everything else stays
+FP64.  The tests state the error of V against the oracle's direct
 quadrature per setting, bound it, and check that raising min_level (fewer
 mixed interactions, each with a smaller h^2 weight excluded) does not make
 it worse than the all-mixed setting."""
@@ -42,11 +43,11 @@ def test_mixed_volume_against_oracle(gpu_device):
 
 
 def test_mixed_mode_with_no_mixed_pair_is_bitwise_fp64(gpu_device):
-    """Mode 1 with a level threshold below every leaf mixes no list-1 pair:
-    the pairs keep the FP64 tiles and kernels, and the far-field variant of
-    mixed plans (which tells FP64 from FP32 pair results by the sign of the
-    slot) must then sum them exactly as the FP64 plan does, bit for bit;
-    with one more level of threshold the two paths differ."""
+    """Mode 1 with a level threshold above every leaf mixes no list-1 pair:
+    the pairs keep the FP64 tiles and kernels and the result is the FP64
+    plan's, bit for bit; with the threshold at the finest level the two
+    paths differ, by about the slices' truncation (2^-32 of the row maxima
+    of the operands)."""
     case = setup("starfish_small", p=24, all_regular=True)
     lv = int(np.max(case["tree"]["level"]))
     _, V64 = run_gpu(case)
