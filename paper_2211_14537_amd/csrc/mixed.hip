@@ -35,8 +35,7 @@ typedef float fx_f4 __attribute__((ext_vector_type(4)));
 typedef double fx_d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kFxN = 256;               // K^2
-constexpr int kFxRS = 40;               // bf16 per staged B row (32 + 8: rows of a quarter-wave in distinct banks)
-constexpr int kFxBuf = 4 * 64 * kFxRS;  // one staging buffer: 4 slices x 64 rows x 32 contraction values
+constexpr int kFxBuf = 4 * 64 * 32;    // one staging buffer: 4 slices x 64 rows x 32 contraction values
 constexpr int kFxLDZ = kNearLrMax + 4;  // LDS row stride of the FP64 factor products Z
 
 __device__ __forceinline__ uint16_t fx_bf16_of_int(double q) {
@@ -101,42 +100,45 @@ __device__ __forceinline__ double fx_value(const fx_f4 t[4], int r) {
 }
 
 // B staging: 64 rows x 32 contraction values x 4 slices, 1024 pieces of 16
-// bytes, four per thread; consecutive threads take consecutive pieces of a row
+// bytes, four per thread; consecutive threads take consecutive pieces of a
+// row.  In LDS a row is 64 bytes and its piece p sits at slot p ^ fx_sw(row):
+// the 16 lanes of a fragment read (rows 16 r + li, piece lk) and the 16
+// lanes of a store (four rows, four pieces each) then fall in distinct banks,
+// as do the eight-lane halves of either.
 struct FxStage {
   fx_s8 v[4];
 };
+__device__ __forceinline__ int fx_sw(int row) { return ((row >> 1) ^ (row >> 3)) & 3; }
 
 __device__ __forceinline__ void fx_gload(FxStage& st, const uint16_t* __restrict__ base, size_t slice, int ld,
                                          int row0, int c0, int nrows) {
   const int t = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int q = t + 256 * j, s = q >> 8, rem = q & 255, row = rem >> 2, part = rem & 3;
-    st.v[j] = row < nrows ? *(const fx_s8*)(base + (size_t)s * slice + (size_t)(row0 + row) * ld + c0 + 8 * part)
+    const int row = t >> 2, part = t & 3;  // slice j
+    st.v[j] = row < nrows ? *(const fx_s8*)(base + (size_t)j * slice + (size_t)(row0 + row) * ld + c0 + 8 * part)
                           : fx_s8{0, 0, 0, 0, 0, 0, 0, 0};
   }
 }
 __device__ __forceinline__ void fx_lstore(const FxStage& st, uint16_t* sb) {
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, row = t >> 2, part = t & 3;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int q = t + 256 * j, s = q >> 8, rem = q & 255, row = rem >> 2, part = rem & 3;
-    *(fx_s8*)(sb + s * 64 * kFxRS + row * kFxRS + 8 * part) = st.v[j];
-  }
+  for (int j = 0; j < 4; ++j) *(fx_s8*)(sb + j * 2048 + row * 32 + 8 * (part ^ fx_sw(row))) = st.v[j];
 }
 // B fragments (four slices) of row tile r from a staged block
 __device__ __forceinline__ void fx_bfrag(const uint16_t* sb, int r, fx_s8 b[4]) {
-  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4, row = 16 * r + li;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) b[s] = *(const fx_s8*)(sb + s * 64 * kFxRS + (16 * r + li) * kFxRS + 8 * lk);
+  for (int s = 0; s < 4; ++s) b[s] = *(const fx_s8*)(sb + s * 2048 + row * 32 + 8 * (lk ^ fx_sw(row)));
 }
 
 // Phase 1: acc[r] (r < MT1) = the integer-scaled products of this lane's pair
 // row of the leaf slices with B rows row0 + 16 r .. (B: [s][row][256], slice
-// stride wslice) over the 256 nodes in 8 blocks of 32.  Two blocks in flight:
-// while block kb is multiplied, the A fragments of block kb + 1 sit in
-// registers and its B rows in the other LDS buffer, and the loads of block
-// kb + 2 are issued.
+// stride wslice) over the 256 nodes in 8 blocks of 32.  The A fragments of
+// block kb + 4 are loaded once block kb is multiplied (a ring of four register
+// blocks: they come from the leaf data in HBM); the B rows of block kb + 2
+// are loaded into registers (from the L2-resident tables) once block kb + 1
+// is stored to the other LDS buffer.
 template <int MT1>
 __device__ __forceinline__ void fx_phase1(const uint16_t* __restrict__ xrow, long xs_slice,
                                           const uint16_t* __restrict__ wbase, size_t wslice, int row0,
@@ -147,51 +149,44 @@ __device__ __forceinline__ void fx_phase1(const uint16_t* __restrict__ xrow, lon
   for (int r = 0; r < 4; ++r) acc[r] = fx_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < MT1; ++r) fx_zero(t[r]);
-  fx_s8 a0[4], a1[4];
+  fx_s8 a[4][4];
   FxStage st;
-  auto ga = [&](fx_s8* a, int kb) __attribute__((always_inline)) {
+  auto ga = [&](fx_s8* av, int kb) __attribute__((always_inline)) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) a[s] = *(const fx_s8*)(xrow + (size_t)s * xs_slice + 32 * kb);
+    for (int s = 0; s < 4; ++s) av[s] = *(const fx_s8*)(xrow + (size_t)s * xs_slice + 32 * kb);
   };
-  auto mul = [&](const fx_s8* a, const uint16_t* sb) __attribute__((always_inline)) {
 #pragma unroll
-    for (int r = 0; r < MT1; ++r) {
-      fx_s8 b[4];
-      fx_bfrag(sb, r, b);
-      fx_block(a, b, t[r]);
-    }
-  };
-  ga(a0, 0);
+  for (int k = 0; k < 4; ++k) ga(a[k], k);
   fx_gload(st, wbase, wslice, kFxN, row0, 0, 16 * MT1);
   __syncthreads();  // the previous user of sbuf is done
   fx_lstore(st, sbuf);
-  ga(a1, 1);
   fx_gload(st, wbase, wslice, kFxN, row0, 32, 16 * MT1);
   __syncthreads();
 #pragma unroll 1
-  for (int kb = 0; kb < NKB; kb += 2) {
-    mul(a0, sbuf);                  // block kb (buffer 0)
-    fx_lstore(st, sbuf + kFxBuf);  // block kb + 1 -> buffer 1
-    if (kb + 2 < NKB) {
-      ga(a0, kb + 2);
-      fx_gload(st, wbase, wslice, kFxN, row0, 32 * (kb + 2), 16 * MT1);
-    }
-    __syncthreads();
-    mul(a1, sbuf + kFxBuf);  // block kb + 1 (buffer 1)
-    if (kb & 2) {            // four blocks done: widen
+  for (int k0 = 0; k0 < NKB; k0 += 4) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kb = k0 + s4;
+      const uint16_t* sb = sbuf + (s4 & 1) * kFxBuf;
 #pragma unroll
       for (int r = 0; r < MT1; ++r) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[r][e] += fx_value(t[r], e);
-        fx_zero(t[r]);
+        fx_s8 b[4];
+        fx_bfrag(sb, r, b);
+        fx_block(a[s4], b, t[r]);
       }
+      if (kb + 4 < NKB) ga(a[s4], kb + 4);
+      if (kb + 1 < NKB) fx_lstore(st, sbuf + ((s4 + 1) & 1) * kFxBuf);
+      if (kb + 2 < NKB) fx_gload(st, wbase, wslice, kFxN, row0, 32 * (kb + 2), 16 * MT1);
+      if (s4 == 3) {  // four blocks done: widen
+#pragma unroll
+        for (int r = 0; r < MT1; ++r) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[r][e] += fx_value(t[r], e);
+          fx_zero(t[r]);
+        }
+      }
+      __syncthreads();
     }
-    if (kb + 2 < NKB) {
-      fx_lstore(st, sbuf);  // block kb + 2 -> buffer 0
-      ga(a1, kb + 3);
-      fx_gload(st, wbase, wslice, kFxN, row0, 32 * (kb + 3), 16 * MT1);
-    }
-    __syncthreads();
   }
 }
 
@@ -261,25 +256,50 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
       }
       continue;
     }
-    // Z (FP64) of this wave's pairs to LDS, ranks >= R zero
+    // Z (FP64) of this wave's pairs to LDS (ranks >= R zero) and the
+    // exponent of every pair's row of Z: the maximum over the row is taken
+    // over r and over the 16 lanes li that hold it
+    int ez_out[4];
+    {
+      double m[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int a = 16 * r + li;
-      const int ea = r < MT1 ? wexp[a] : 0;
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * r + li;
+        const int ea = r < MT1 ? wexp[a] : 0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        sZ[(16 * w + 4 * lk + e) * kFxLDZ + a] = r < MT1 ? ldexp(acc[r][e], ex_out[e] + ea - 16) : 0.0;
+        for (int e = 0; e < 4; ++e) {
+          const double z = r < MT1 ? ldexp(acc[r][e], ex_out[e] + ea - 16) : 0.0;
+          sZ[(16 * w + 4 * lk + e) * kFxLDZ + a] = z;
+          m[e] = fmax(m[e], fabs(z));
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) m[e] = fmax(m[e], __shfl_xor(m[e], o, 16));
+        int ee = 0;
+        if (m[e] > 0.0) frexp(m[e], &ee);
+        ez_out[e] = ee;
+        if (li == 0) s_ez[16 * w + 4 * lk + e] = ee;
+      }
     }
-    __syncthreads();
-    // the exponent of every pair's row of Z
-    if (tid < 64) {
-      double m = 0.0;
-      for (int a = 0; a < LM; ++a) m = fmax(m, fabs(sZ[tid * kFxLDZ + a]));
-      int e = 0;
-      if (m > 0.0) frexp(m, &e);
-      s_ez[tid] = e;
-    }
-    __syncthreads();
+    // phase 2: Y = Z Q^T over the target rows in four chunks of 64; stage g
+    // holds Q rows 64 (g / nkb) .. + 63, ranks 32 (g % nkb) .. + 31 (4 slices),
+    // loaded two stages ahead into registers and stored one stage ahead into
+    // the other LDS buffer
+    const uint16_t* qbase = Qb + (size_t)c * 4 * LM * n;
+    const int* qexp = Qexp + (size_t)c * n;
+    const int nkb = (16 * MT1 + 31) / 32, nst = 4 * nkb;
+    auto qload = [&](FxStage& stg, int g) __attribute__((always_inline)) {
+      const int ch = g / nkb;
+      fx_gload(stg, qbase, (size_t)LM * n, LM, 64 * ch, 32 * (g - ch * nkb), 64);
+    };
+    FxStage st[2];
+    qload(st[0], 0);
+    qload(st[1], 1);
+    fx_lstore(st[0], sbuf);  // the last phase-1 barrier freed sbuf
+    qload(st[0], 2);
+    __syncthreads();         // Z, its exponents and stage 0 are in LDS
     // A fragments of Z for both 32-rank blocks: this lane's pair 16w + li,
     // ranks 32 kb + 8 lk + t, four slices
     const int myez = s_ez[16 * w + li];
@@ -299,53 +319,42 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         }
       }
     }
-    int ez_out[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) ez_out[e] = s_ez[16 * w + 4 * lk + e];
-    // phase 2: Y = Z Q^T over the target rows in four chunks of 64; Q blocks
-    // (64 rows x 32 ranks x 4 slices) staged through sbuf, double-buffered
-    const uint16_t* qbase = Qb + (size_t)c * 4 * LM * n;
-    const int* qexp = Qexp + (size_t)c * n;
-    const int nkb = (16 * MT1 + 31) / 32, nst = 4 * nkb;
-    FxStage st;
-    fx_gload(st, qbase, (size_t)LM * n, LM, 0, 0, 64);
-    __syncthreads();  // phase-1 reads of sbuf are done
-    fx_lstore(st, sbuf);
-    __syncthreads();
     fx_f4 t2[4][4];  // a chunk's contraction (<= 64 ranks) is at most two blocks: exact in FP32
-    for (int sg = 0; sg < nst; ++sg) {
-      const int ch = sg / nkb, kb = sg - ch * nkb, qb = sg & 1;
-      if (sg + 1 < nst) {
-        const int ch1 = (sg + 1) / nkb, kb1 = sg + 1 - ch1 * nkb;
-        fx_gload(st, qbase, (size_t)LM * n, LM, 64 * ch1, 32 * kb1, 64);
-      }
-      if (kb == 0)
+#pragma unroll 1
+    for (int g0 = 0; g0 < nst; g0 += 2) {
 #pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) fx_zero(t2[r4]);
-      const uint16_t* sb = sbuf + qb * kFxBuf;
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {
-        fx_s8 b[4];
-        fx_bfrag(sb, r4, b);
+      for (int h = 0; h < 2; ++h) {
+        const int g = g0 + h;
+        const int ch = g / nkb, kb = g - ch * nkb;
         if (kb == 0)
-          fx_block(za[0], b, t2[r4]);
-        else
-          fx_block(za[1], b, t2[r4]);
-      }
-      if (kb == nkb - 1) {
+#pragma unroll
+          for (int r4 = 0; r4 < 4; ++r4) fx_zero(t2[r4]);
+        const uint16_t* sb = sbuf + h * kFxBuf;
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
-          const int i = 64 * ch + 16 * r4 + li;
-          const int ei = qexp[i];
+          fx_s8 b[4];
+          fx_bfrag(sb, r4, b);
+          if (h == 1 && nkb == 2)
+            fx_block(za[1], b, t2[r4]);
+          else
+            fx_block(za[0], b, t2[r4]);
+        }
+        if (g + 1 < nst) fx_lstore(st[(h + 1) & 1], sbuf + ((h + 1) & 1) * kFxBuf);
+        if (g + 3 < nst) qload(st[(h + 1) & 1], g + 3);
+        if (kb == nkb - 1) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int pe = 16 * w + 4 * lk + e;
-            if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(fx_value(t2[r4], e), ez_out[e] + ei - 16);
+          for (int r4 = 0; r4 < 4; ++r4) {
+            const int i = 64 * ch + 16 * r4 + li;
+            const int ei = qexp[i];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int pe = 16 * w + 4 * lk + e;
+              if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(fx_value(t2[r4], e), ez_out[e] + ei - 16);
+            }
           }
         }
+        __syncthreads();
       }
-      if (sg + 1 < nst) fx_lstore(st, sbuf + (qb ^ 1) * kFxBuf);
-      __syncthreads();
     }
   }
 }

@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libvfx.so")
+# VFX_LIBRARY selects another build of the same library (the host-sanitized
+# one the CPU tests load); the default is the in-tree build
+LIB_PATH = os.environ.get("VFX_LIBRARY") or os.path.join(_HERE, "lib", "libvfx.so")
 
 VFX_OK = 0
 VFX_EINVAL = -1
