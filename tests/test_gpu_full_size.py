@@ -107,8 +107,9 @@ def test_full_size_starfish(gpu_device):
 
 
 # The mixed-precision setting bench.py reports beside FP64 on this workload,
-# and its gate on G1 (10x the error stated for it).
-WEDGE_MIXED = dict(min_level=0, gate=4e-9)
+# and its gate on G1: 10x the 8.4e-13 measured over these nodes (the FP64
+# path: 4.5e-13).
+WEDGE_MIXED = dict(min_level=0, gate=8.5e-12)
 
 
 def test_full_size_wedge(gpu_device):

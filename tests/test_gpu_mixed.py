@@ -36,7 +36,10 @@ def test_mixed_volume_against_oracle(gpu_device):
     _, Vb = run_gpu(case)
     assert np.array_equal(Vb, V64)  # back to FP64: bitwise the FP64 result
     assert e64 <= 1e-11
-    assert errs[0] <= 2e-6
+    # measured 4.5e-10 all mixed: the slices keep about 2^-32 of each
+    # operand row's maximum, and on this shallow uniform tree the near field
+    # carries a large share of V
+    assert errs[0] <= 2e-9
     assert int(np.max(case["tree"]["level"])) == 4
     for lmin in (3, 4):
         assert e64 < errs[lmin] <= errs[0] * 1.01 + 1e-15
@@ -58,7 +61,7 @@ def test_mixed_mode_with_no_mixed_pair_is_bitwise_fp64(gpu_device):
     _, Vf = run_gpu(case)
     d = float(np.abs(Vf - V64).max() / np.abs(V64).max())
     say(f"    mixed only at level {lv}: rel Linf vs FP64 path {d:.3e}")
-    assert 0 < d <= 2e-6
+    assert 0 < d <= 3e-9  # measured 7.3e-10
 
 
 def test_mixed_end_to_end(gpu_device):
@@ -73,7 +76,7 @@ def test_mixed_end_to_end(gpu_device):
     assert np.array_equal(fe, fe64)  # the extension is FP64 in both modes
     d = float(np.abs(V - V64).max() / np.abs(V64).max())
     say(f"    mixed vs FP64 path, end to end: rel Linf {d:.3e}")
-    assert d <= 2e-6
+    assert d <= 8e-9  # measured 1.7e-9
 
 
 def test_mixed_rejects_other_grid_sizes(gpu_device):
