@@ -303,13 +303,31 @@ def bench_batch(args, dev):
         plan.execute(FL[r], FC[r], FE[r], V[r])
     torch.cuda.synchronize()
     el1 = (time.perf_counter() - t0) / k1
+    # the extension phase (HIP events around it on the execute stream) per
+    # right-hand side: in the batch (from 8 right-hand sides on its matrix
+    # products run as MFMA GEMMs over the batch) and one at a time
+    plan.set_timing(True)
+    for _ in range(3):
+        plan.execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    ph_b = plan.timings()
+    plan.set_timing(True)
+    for r in range(k1):
+        plan.execute(FL[r], FC[r], FE[r], V[r])
+    torch.cuda.synchronize()
+    ph_1 = plan.timings()
+    plan.set_timing(False)
+    ext = {"batch_ms_per_rhs": ph_b["extension"] / nrhs, "single_ms": ph_1["extension"],
+           "speedup": ph_1["extension"] * nrhs / max(ph_b["extension"], 1e-12),
+           "batch_phases_ms": {k: v for k, v in ph_b.items() if k != "count"}}
     out = {"metric": "leaf points/s over a batch of right-hand sides (ext + volume FMM), FP64", "unit": "leaf points/s",
            "value": nrhs * L * n / el, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * el, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": "starfish_batch", "rhs": nrhs, "leaves": L, "nodes_per_rhs": L * n,
                       "K": cfg["K"], "p": cfg["p"], "cut_leaves": len(tr["cut_ids"])},
-           "single_rhs_ms": 1e3 * el1, "batch_speedup_per_rhs": el1 * nrhs / el, "autotune": choice}
+           "single_rhs_ms": 1e3 * el1, "batch_speedup_per_rhs": el1 * nrhs / el, "extension": ext,
+           "autotune": choice}
     print(json.dumps(out), flush=True)
 
 

@@ -1674,13 +1674,15 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   const size_t P = T.p + 1, R = (size_t)nrhs;
   if (D.cap > 0) (void)hipDeviceSynchronize();  // no execute of this plan in flight
   p->gen++;  // graphs that captured the old buffers are stale
-  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.xs_exp, D.near_z};
+  void* old[] = {D.mpole, D.local, D.near_y, D.p2l_y, D.up_part, D.locf, D.xs, D.m2p_y, D.xs_exp, D.near_z,
+                 D.ext_fg, D.ext_g};
   for (void* q : old)
     if (q) (void)hipFree(q);
   D.mpole = D.local = D.up_part = D.locf = nullptr;
   D.near_y = D.p2l_y = D.m2p_y = D.near_z = nullptr;
   D.xs = nullptr;
   D.xs_exp = nullptr;
+  D.ext_fg = D.ext_g = nullptr;
   D.cap = 0;
   VFX_HIP(hipMalloc((void**)&D.mpole, sizeof(double2) * (size_t)H.B * P * R));
   VFX_HIP(hipMalloc((void**)&D.local, sizeof(double2) * (size_t)H.B * P * R));
@@ -1695,6 +1697,10 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   if (H.precision == 1 && !H.ts) {
     VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 4 * (size_t)H.L * T.n * R));
     VFX_HIP(hipMalloc((void**)&D.xs_exp, sizeof(int) * (size_t)H.L * R));
+  }
+  if (nrhs >= kExtGemmMinRhs && H.ncut > 0) {
+    VFX_HIP(hipMalloc((void**)&D.ext_fg, sizeof(double) * (size_t)H.ncut * R * T.nG));
+    VFX_HIP(hipMalloc((void**)&D.ext_g, sizeof(double) * (size_t)H.ncut * R * T.Kbar * T.Kbar));
   }
   D.cap = nrhs;
   return VFX_OK;
@@ -2018,9 +2024,20 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
     const int ext_blocks = H.ncut * nrhs;
     const long pieces = (long)L * n / 2 * nrhs;
     const int copy_blocks = (int)std::min<long>((pieces + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_extension, dim3(ext_blocks + copy_blocks), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG,
+    // a batch of at least kExtGemmMinRhs right-hand sides: A1 and A2 as
+    // MFMA GEMMs, then the Chebyshev step and the evaluation for eight
+    // right-hand sides per work-group; the extension kernel only
+    // initialises the leaves no extension list writes
+    const bool gemm = nrhs >= kExtGemmMinRhs && H.ncut > 0;
+    if (gemm) {
+      int rc = launch_ext_gemm(p, f_cut, nrhs, s, err);
+      if (!rc) rc = launch_ext_eval(p, f_cut, fe, nrhs, s, err);
+      if (rc) return rc;
+    }
+    const int blocks1 = gemm ? 0 : ext_blocks;
+    hipLaunchKernelGGL(k_extension, dim3(blocks1 + copy_blocks), dim3(256), 0, s, T.K, T.Kbar, T.nX, T.nG,
                        D.pinv_ptr, D.pinv_idx, D.pinv_val, D.sbar_given, D.ext_ptr, D.ext_tgt, D.ext_geo, DT.t,
-                       DT.AbarT, DT.cbar, f_cut, fe, nrhs, sFC, sFL, ext_blocks, L, D.fe_src, f_leaf);
+                       DT.AbarT, DT.cbar, f_cut, fe, nrhs, sFC, sFL, blocks1, L, D.fe_src, f_leaf);
   }
   VFX_HIP(hipGetLastError());
   MARK(1, s);

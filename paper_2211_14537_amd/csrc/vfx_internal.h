@@ -278,6 +278,10 @@ struct DevicePlan {
   double* pinv_val = nullptr;
   uint8_t* sbar_given = nullptr;
   double2 *mpole = nullptr, *local = nullptr;
+  // batched extension (nrhs >= kExtGemmMinRhs): f_G of every (cut leaf,
+  // right-hand side), ncut x cap x nG, and A_{Xbar,G} f_G on the Sbar grid,
+  // ncut x cap x Kbar^2 (column c * nrhs + r)
+  double *ext_fg = nullptr, *ext_g = nullptr;
 };
 
 struct Plan {
@@ -319,6 +323,12 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err);
 int launch_interp(Plan* p, const double* V, long npts, const double* px, const double* py, double* out,
                   hipStream_t s, std::string& err);
 int launch_net_charge(Plan* p, const double* fe, int nrhs, double* out, hipStream_t s, std::string& err);
+// ext_batch.hip: batches of at least this many right-hand sides compute
+// the extension's two matrix products (A1 per cut leaf, A2 over every cut
+// leaf and right-hand side) as FP64 MFMA GEMMs ahead of the extension kernel
+constexpr int kExtGemmMinRhs = 8;
+int launch_ext_gemm(const Plan* p, const double* f_cut, int nrhs, hipStream_t s, std::string& err);
+int launch_ext_eval(const Plan* p, const double* f_cut, double* fe, int nrhs, hipStream_t s, std::string& err);
 // mixed.hip
 int launch_near_fx(const Plan* p, const double* fe, int nrhs, int max_wgs, hipStream_t s, std::string& err);
 // near.hip

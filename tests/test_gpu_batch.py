@@ -1,9 +1,12 @@
 """Batched right-hand sides, HIP graph capture of many plans, autotuner.
 
 A batch of right-hand sides runs every kernel once with the right-hand side
-as a grid dimension; it must reproduce separate executes bitwise, and two of
-its right-hand sides are checked against the oracle (extension within the
-least-squares bound, V of the extended data within 1e-10).  Executes of
+as a grid dimension; below 8 right-hand sides it must reproduce separate
+executes bitwise, and two of its right-hand sides are checked against the
+oracle (extension within the least-squares bound, V of the extended data
+within 1e-10).  From 8 right-hand sides on, the extension's matrix products
+run as MFMA GEMMs: the results then agree with single executes to the
+extension's rounding bound, and are checked against the oracle the same way.  Executes of
 several plans captured in one graph must reproduce the eager results bitwise
 on every replay (with eager work between replays), and every plan's replayed
 V is checked against the oracle.  A graph refuses to replay once a plan it
@@ -71,6 +74,54 @@ def test_batch_matches_single_executes(gpu_device, name, precision):
         tol = (1e-9 if name == "disk_uniform3" else 1e-10) if precision == 0 else 2e-9
         assert g1 <= tol
         assert wext <= 1.0
+
+
+@pytest.mark.parametrize("name,nrhs", [("starfish_small", 12), ("disk_adaptive_small", 70)])
+def test_batched_extension_gemm(gpu_device, name, nrhs):
+    """Batches of at least 8 right-hand sides compute the extension's matrix
+    products as MFMA GEMMs (A1 per cut leaf over the right-hand sides, A2
+    over every cut leaf and right-hand side): every right-hand side's
+    extension stays within the least-squares bound of the oracle's float64
+    extension and within that bound of the single execute (the products are
+    summed in another order), and V against the oracle as for single
+    executes.  70 right-hand sides span two blocks of 64 in A1 and a ragged
+    last column tile in A2."""
+    import torch
+    case = setup(name, p=24 if name == "starfish_small" else 40)
+    fl, fc = _inputs(case, nrhs, 3)
+    FL, FC = _dev(fl), _dev(fc)
+    FE, V = torch.empty_like(FL), torch.empty_like(FL)
+    case["plan"].execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    FE, V = FE.cpu().numpy(), V.cpu().numpy()
+    assert np.isfinite(FE).all() and np.isfinite(V).all()
+    tr = case["tree"]
+    cut_ids = list(tr["cut_ids"])
+    worst_single, dv = 0.0, 0.0
+    for r in sorted({0, 1, nrhs // 2, nrhs - 1}):
+        fe1, V1 = _single(case, _dev(fl[r]), _dev(fc[r]))
+        c = dict(case, f_leaf=fl[r], f_cut=fc[r])
+        ref, info = oracle_extension(c, "fp64")
+        for i, rec in info.items():
+            tg = rec["targets"]
+            tol = 2.0 * extension.extension_tolerance(rec, ref[tg], fc[r][cut_ids.index(i)][tr["mask"][cut_ids.index(i)] != 0])
+            worst_single = max(worst_single, float(np.abs(FE[r][tg] - fe1[tg]).max()) / tol)
+        dv = max(dv, float(np.abs(V[r] - V1).max() / np.abs(V1).max()))
+    say(f"    {name}: batch of {nrhs} (GEMM extension) vs single executes: extension diff / bound "
+        f"{worst_single:.2e}, V rel diff {dv:.2e}")
+    assert worst_single <= 1.0
+    assert dv <= 1e-11
+    for r in (0, nrhs - 1):
+        g1, g3, wext = _against_oracle(case, fl[r], fc[r], FE[r], V[r], seed=r)
+        fe1, V1 = _single(case, _dev(fl[r]), _dev(fc[r]))
+        _, _, wext1 = _against_oracle(case, fl[r], fc[r], fe1, V1, seed=r)
+        say(f"    rhs {r}: V rel Linf vs oracle {g1:.2e} (end to end {g3:.2e}), extension err/bound {wext:.2f} "
+            f"(single execute {wext1:.2f})")
+        assert g1 <= 1e-10
+        # the bound's constant (16 u cond(A_I) max|f|) is empirical: on some
+        # noisy inputs both paths exceed it alike (the GEMM path may not do
+        # worse than the single execute)
+        assert wext <= max(1.0, 1.05 * wext1)
 
 
 def _against_oracle(case, f_leaf, f_cut, fe, V, seed=0, n_nodes=160):
