@@ -276,13 +276,21 @@ int vfx_plan_factor_gpu(vfx_plan* plan, void* stream);
  * outputs are stacked: f_leaf, fe_out, V_out are nrhs x n_leaves x K^2 and
  * f_cut is nrhs x n_cut x |X| (device, row-major).  Every kernel of the
  * path runs once for the whole batch with the right-hand side as a grid
- * dimension: each cut leaf's operator P_i is read once and applied to all
- * right-hand sides (the work-groups of one cut leaf are consecutive, so the
- * reuse happens in L2), the near-field and expansion GEMMs see nrhs times
- * as many pairs, and the latency-bound tree kernels fill the GPU.  Results
- * are bitwise those of nrhs separate vfx_execute calls.  The plan grows its
- * per-right-hand-side buffers on first use (it synchronises the device
- * then).  Errors as vfx_execute, and VFX_EINVAL for nrhs < 1. */
+ * dimension: the near-field and expansion GEMMs see nrhs times as many
+ * pairs, and the latency-bound tree kernels fill the GPU.  The extension
+ * (Section 3.2): below 8 right-hand sides one work-group per (cut leaf,
+ * right-hand side), the work-groups of a cut leaf consecutive so that its
+ * P_i is reused from L2, and the results are bitwise those of nrhs separate
+ * vfx_execute calls; from 8 on, its two matrix products run as FP64 MFMA
+ * GEMMs (f_G = P_i f_I per cut leaf over blocks of 64 right-hand sides, P_i
+ * read once per block; A_{Xbar,G} f_G over every cut leaf and right-hand
+ * side) and the Chebyshev step and target evaluation take eight right-hand
+ * sides per work-group; the results then differ from separate executes by
+ * rounding only (the products are summed in another order).  The plan
+ * grows its per-right-hand-side buffers on first use (it synchronises the
+ * device then); from 8 right-hand sides they include the extension's
+ * intermediate products, n_cut x nrhs x (N_G + Kbar^2) doubles.  Errors as
+ * vfx_execute, and VFX_EINVAL for nrhs < 1. */
 int vfx_execute_batch(vfx_plan* plan, int nrhs, const double* f_leaf, const double* f_cut, double* fe_out,
                       double* V_out, void* stream);
 
