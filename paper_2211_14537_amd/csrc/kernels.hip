@@ -56,28 +56,48 @@ __device__ __forceinline__ double box_side(double root, int level) { return ldex
 // work-group's critical path holds few memory round trips.
 constexpr int kExtTgtMax = 16;  // targets whose geometry is staged in LDS
 
-__global__ void __launch_bounds__(256) k_extension(
+// f^e of the leaves no extension list writes, 16-byte pieces e0, e0 +
+// step, ... below e1 (piece e: right-hand side e / half, element 2 (e mod
+// half)): f on regular leaves (fe_src 1), zero elsewhere (fe_src 0); list
+// targets (fe_src 2) are left to their cut leaf's work-group, so every
+// element has one writer.
+__device__ __forceinline__ void fe_init_range(long e0, long e1, long step, int n, long half,
+                                              const int8_t* __restrict__ fe_src, const double* __restrict__ f_leaf,
+                                              double* __restrict__ fe, long sfe) {
+  // four pieces per round, so their loads are in flight together
+  for (long e = e0; e < e1; e += 4 * step) {
+    long off[4];
+    int src[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const long ek = e + k * step;
+      const long r = ek / half, i = 2 * (ek - r * half);
+      off[k] = r * sfe + i;
+      src[k] = ek < e1 ? fe_src[i / n] : 2;
+    }
+    double2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = src[k] == 1 ? *(const double2*)(f_leaf + off[k]) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (src[k] != 2) *(double2*)(fe + off[k]) = v[k];
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_extension(
     int K, int Kb, int nX, int nG, const int* __restrict__ pinv_ptr, const uint16_t* __restrict__ pinv_idx,
     const double* __restrict__ pinv_val, const uint8_t* __restrict__ sbar_given, const int* __restrict__ ext_ptr,
     const int* __restrict__ ext_tgt, const double* __restrict__ ext_geo, const double* __restrict__ t,
     const double* __restrict__ AbarT, const double* __restrict__ cbar, const double* __restrict__ f_cut,
     double* __restrict__ fe, int nrhs, long sfc, long sfe, int ext_blocks, int L,
     const int8_t* __restrict__ fe_src, const double* __restrict__ f_leaf) {
+  const long half = (long)L * K * K / 2, pieces = half * nrhs;
   if ((int)blockIdx.x >= ext_blocks) {
-    // the work-groups past the cut leaves initialise every leaf no extension
-    // list writes: f on regular leaves (fe_src 1), zero elsewhere (fe_src
-    // 0); list targets (fe_src 2) are left to their cut leaf's work-group,
-    // so every element has one writer.  16-byte pieces, grid-stride.
-    const int n = K * K;
-    const long half = (long)L * n / 2, pieces = half * nrhs;
+    // the work-groups past the cut leaves initialise f^e of the other
+    // leaves, grid-stride (they take the slots the cut leaves free)
     const long nb = (long)(gridDim.x - ext_blocks) * blockDim.x;
-    for (long e = (long)(blockIdx.x - ext_blocks) * blockDim.x + threadIdx.x; e < pieces; e += nb) {
-      const long r = e / half, i = 2 * (e - r * half);
-      const int src = fe_src[i / n];
-      if (src == 2) continue;
-      const double2 v = src ? *(const double2*)(f_leaf + r * sfe + i) : make_double2(0.0, 0.0);
-      *(double2*)(fe + r * sfe + i) = v;
-    }
+    fe_init_range((long)(blockIdx.x - ext_blocks) * blockDim.x + threadIdx.x, pieces, nb, K * K, half, fe_src,
+                  f_leaf, fe, sfe);
     return;
   }
   // consecutive work-groups take the right-hand sides of one cut leaf, so
@@ -98,7 +118,8 @@ __global__ void __launch_bounds__(256) k_extension(
   __shared__ int s_tg[kExtTgtMax];
   __shared__ uint8_t s_given[kMaxKb * kMaxKb];
   const int c = blockIdx.x / nrhs;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: row indices in scalar registers
   const int n = K * K, Kb2 = Kb * Kb;
   const int off = pinv_ptr[c], ni = pinv_ptr[c + 1] - off;
   const int e0 = ext_ptr[c], ne = ext_ptr[c + 1] - e0;
@@ -125,36 +146,40 @@ __global__ void __launch_bounds__(256) k_extension(
   }
   __syncthreads();
   // A1: f_G = P_i f_I  (P_i: nG x ni row-major).  Wave w takes rows
-  // 16w..16w+15, lane l the columns l, l+64, ...; every load of a wave is
-  // 512 contiguous bytes of one row, and two column steps (32 loads) are in
-  // flight at once.  The 16 row partials are combined across the lanes by a
-  // recursive-halving reduce-scatter over lane bits 3..0 (lane l ends with
-  // row l & 15) and two plain butterfly steps over bits 4 and 5.  Rows >= 64
-  // (a stencil degree above 10) use wave sums.
+  // 16w..16w+15 in two passes of 8, lane l the columns l, l+64, ...; every
+  // load of a wave is 512 contiguous bytes of one row, and two column steps
+  // (16 loads) are in flight at once.  The 8 row partials are combined
+  // across the lanes by a recursive-halving reduce-scatter over lane bits
+  // 2..0 (lane l ends with row l & 7) and three plain butterfly steps over
+  // bits 3..5.  Rows >= 64 (a stencil degree above 10) use wave sums.  Few
+  // live registers keep six work-groups per CU resident, so the operators
+  // of all cut leaves stream at once.
   const double* P = pinv_val + (size_t)off * nG;
-  {
-    double acc[16];
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    double acc[8];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.0;
-    const int r0 = 16 * wave;
+    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+    const int r0 = 16 * wave + 8 * half;
+#pragma unroll 1
     for (int q = lane; q < ni; q += 128) {
       const bool q2 = q + 64 < ni;
       const double f0 = s_fI[q], f1 = q2 ? s_fI[q + 64] : 0.0;
-      double pa[16], pb[16];
+      double pa[8], pb[8];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < 8; ++r) {
         const int row = min(r0 + r, nG - 1);
         pa[r] = P[row * ni + q];
         pb[r] = q2 ? P[row * ni + q + 64] : 0.0;
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < 8; ++r) {
         const double m = (r0 + r < nG) ? 1.0 : 0.0;
         acc[r] += m * (pa[r] * f0 + pb[r] * f1);
       }
     }
 #pragma unroll
-    for (int s = 8; s >= 1; s >>= 1) {
+    for (int s = 4; s >= 1; s >>= 1) {
       const bool up = (lane & s) != 0;
 #pragma unroll
       for (int j = 0; j < s; ++j) {
@@ -163,9 +188,10 @@ __global__ void __launch_bounds__(256) k_extension(
         acc[j] = keep + __shfl_xor(send, s, 64);
       }
     }
+    acc[0] += __shfl_xor(acc[0], 8, 64);
     acc[0] += __shfl_xor(acc[0], 16, 64);
     acc[0] += __shfl_xor(acc[0], 32, 64);
-    if (lane < 16 && r0 + lane < nG) s_fG[r0 + lane] = acc[0];
+    if (lane < 8 && r0 + lane < nG) s_fG[r0 + lane] = acc[0];
   }
   for (int r = 64 + wave; r < nG; r += blockDim.x / 64) {
     double a = 0.0;
@@ -2019,8 +2045,7 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
   MARK(12, s);
   {
     // the extension of every cut leaf, and in the same launch the f^e
-    // initialisation of the other leaves (about 2 MB of copy per work-group
-    // at the wedge's size, spread over the extension's run)
+    // initialisation of the other leaves
     const int ext_blocks = H.ncut * nrhs;
     const long pieces = (long)L * n / 2 * nrhs;
     const int copy_blocks = (int)std::min<long>((pieces + 255) / 256, 1024);
