@@ -1043,27 +1043,22 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
   const double r = act ? ldexp(1.0, lt - ls) : 1.0;
   const double ww = w.x * w.x + w.y * w.y;
   const double2 q = make_double2(r * w.x / ww, -r * w.y / ww);  // r / w
-  double2 s[PM];
-  {
-    double2 pw = make_double2(1.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < PM; ++k) {
-      const double2 a = (act && k < P) ? mpole[(size_t)src * P + k] : make_double2(0.0, 0.0);
-      s[k] = cmul(pw, a);
-      pw = cmul(pw, q);
-    }
-  }
-  const double2 a0 = s[0];
   const int NC = (P + 7) / 8;
   // work-group z computes the outputs l = 8c .. 8c+7 (chunk c = blockIdx.z,
-  // a compile-time constant inside the matching branch)
+  // a compile-time constant inside the matching branch); the scaled source
+  // coefficients s_k = (r/w)^k a_k, k <= 8c+7, are formed on the fly (k
+  // outer) rather than held, which keeps the kernel at a few dozen registers
   static_for<0, (PM + 7) / 8>([&](auto cc) __attribute__((always_inline)) {
     constexpr int c = decltype(cc)::value;
+    constexpr int KH = (8 * c + 8 < PM) ? 8 * c + 8 : PM;  // k < KH
     if (c != (int)blockIdx.z || c >= NC) return;
     // w^(l-1) before output l: the same product sequence as a running power
     double2 wl = make_double2(1.0, 0.0);
 #pragma unroll
     for (int i = 1; i < 8 * c; ++i) wl = cmul(wl, w);
+    double2 pw = make_double2(1.0, 0.0);
+    const double2 a0 = cmul(pw, act ? mpole[(size_t)src * P] : make_double2(0.0, 0.0));
+    pw = cmul(pw, q);
     // the eight outputs of the chunk accumulate side by side (k outer)
     double ur[8], ui[8];
 #pragma unroll
@@ -1074,14 +1069,17 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
       ui[lc] = -a0.y * il;
     }
 #pragma unroll
-    for (int k = 1; k < PM; ++k) {
+    for (int k = 1; k < KH; ++k) {
+      const double2 a = (act && k < P) ? mpole[(size_t)src * P + k] : make_double2(0.0, 0.0);
+      const double2 sk = cmul(pw, a);
+      pw = cmul(pw, q);
 #pragma unroll
       for (int lc = 0; lc < 8; ++lc) {
         const int l = 8 * c + lc;
         if (k <= l && l < P) {
           const double cf = pasT[l * P + k];
-          ur[lc] += cf * s[k].x;
-          ui[lc] += cf * s[k].y;
+          ur[lc] += cf * sk.x;
+          ui[lc] += cf * sk.y;
         }
       }
     }
@@ -1174,18 +1172,11 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
   const double r = act ? ldexp(1.0, la - lb) : 1.0;
   const double ww = w.x * w.x + w.y * w.y;
   const double2 q = make_double2(r * w.x / ww, -r * w.y / ww);  // r / w
-  double2 s[PM];
-  {
-    double2 pw = make_double2(1.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < PM; ++k) {
-      const double2 a = (act && k < P) ? local[(size_t)A * P + k] : make_double2(0.0, 0.0);
-      s[k] = cmul(pw, a);
-      pw = cmul(pw, w);
-    }
-  }
   const int NC = (P + 7) / 8;
-  // work-group z computes the outputs l = 8c .. 8c+7 (chunk c = blockIdx.z)
+  // work-group z computes the outputs l = 8c .. 8c+7 (chunk c = blockIdx.z);
+  // the scaled ancestor coefficients s_k = w^k b_k, k >= 8c, are formed on
+  // the fly (k outer) rather than held, which keeps the kernel at a few
+  // dozen registers
   static_for<0, (PM + 7) / 8>([&](auto cc) __attribute__((always_inline)) {
     constexpr int c = decltype(cc)::value;
     if (c != (int)blockIdx.z || c >= NC) return;
@@ -1193,19 +1184,26 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
     double2 ql = make_double2(1.0, 0.0);
 #pragma unroll
     for (int i = 0; i < 8 * c; ++i) ql = cmul(ql, q);
+    // w^k from k = 0, the same product sequence as a running power
+    double2 pw = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 8 * c; ++k) pw = cmul(pw, w);
     // the eight outputs of the chunk accumulate side by side (k outer)
     double ur[8], ui[8];
 #pragma unroll
     for (int lc = 0; lc < 8; ++lc) ur[lc] = ui[lc] = 0.0;
 #pragma unroll
-    for (int k = 0; k < PM; ++k) {
+    for (int k = 8 * c; k < PM; ++k) {
+      const double2 a = (act && k < P) ? local[(size_t)A * P + k] : make_double2(0.0, 0.0);
+      const double2 sk = cmul(pw, a);
+      pw = cmul(pw, w);
 #pragma unroll
       for (int lc = 0; lc < 8; ++lc) {
         const int l = 8 * c + lc;
         if (k >= l && k < P) {
           const double cf = pasT[l * P + k];
-          ur[lc] += cf * s[k].x;
-          ui[lc] += cf * s[k].y;
+          ur[lc] += cf * sk.x;
+          ui[lc] += cf * sk.y;
         }
       }
     }
