@@ -297,6 +297,11 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
   return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
+// Per-output rows of the lane-per-pair kernels' LDS staging: 65 (not 64)
+// double2 apart, so the eight lanes of a segment that read the same entry
+// of eight outputs fall in different banks.
+constexpr int kSoStride = 65;
+
 // Sum of s[q] over q in [q0, q1) in a fixed order with four
 // interleaved partial sums (deterministic, and the LDS loads overlap).
 __device__ __forceinline__ double2 seg_sum(const double2* s, int q0, int q1) {
@@ -340,7 +345,7 @@ __global__ void __launch_bounds__(64) k_m2l_pairs(int P, double root_size, const
   mpole += blockIdx.y * smp;  // right-hand side blockIdx.y
   local += blockIdx.y * smp;
   p2l_y += blockIdx.y * spl;
-  __shared__ double2 s_o[8 * 64];
+  __shared__ double2 s_o[8 * kSoStride];
   const int g = blockIdx.x;
   const int b0 = grp[g], b1 = grp[g + 1];
   const int e0 = l2_ptr[b0], e1 = l2_ptr[b1];
@@ -399,12 +404,12 @@ __global__ void __launch_bounds__(64) k_m2l_pairs(int P, double root_size, const
     }
     __syncthreads();
 #pragma unroll
-    for (int lc = 0; lc < 8; ++lc) s_o[lc * 64 + lane] = outc[lc];
+    for (int lc = 0; lc < 8; ++lc) s_o[lc * kSoStride + lane] = outc[lc];
     __syncthreads();
     const int lc = lane & 7, seg = lane >> 3;
     const int bb = b0 + seg, l = 8 * c + lc;
     if (bb < b1 && l < P) {
-      const double2 sv = seg_sum(s_o + lc * 64, l2_ptr[bb] - e0, l2_ptr[bb + 1] - e0);
+      const double2 sv = seg_sum(s_o + lc * kSoStride, l2_ptr[bb] - e0, l2_ptr[bb + 1] - e0);
       double re = sv.x, im = sv.y;
       const double h = box_side(root_size, box_level[bb]);
       const double h2 = h * h;
@@ -443,7 +448,7 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
   mpole += blockIdx.y * smp;  // right-hand side blockIdx.y
   local += blockIdx.y * smp;
   p2l_y += blockIdx.y * spl;
-  __shared__ double2 s_o[8 * 64];
+  __shared__ double2 s_o[8 * kSoStride];
   const int g = blockIdx.x;
   const int b0 = grp[g], b1 = grp[g + 1];
   const int e0 = l2_ptr[b0], e1 = l2_ptr[b1];
@@ -536,12 +541,12 @@ __global__ void __launch_bounds__(64) k_m2l_lanes(double root_size, const int* _
         }
         tl = cmul(tl, t);
       }
-      s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
+      s_o[lc * kSoStride + lane] = act ? out : make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int l = 8 * c + lc;
     if (own && l < P) {
-      const double2 sv = seg_sum(s_o + lc * 64, r0, r1);
+      const double2 sv = seg_sum(s_o + lc * kSoStride, r0, r1);
       local[(size_t)bb * P + l] = make_double2(sv.x + p2r[c], sv.y + p2i[c]);
     }
   }
@@ -1028,7 +1033,7 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
   const int P = EXACT ? PM : Prt;
   mpole += blockIdx.y * smp;  // right-hand side blockIdx.y
   part += blockIdx.y * spart;
-  __shared__ double2 s_o[8 * 64];
+  __shared__ double2 s_o[8 * kSoStride];
   const int* gg = grp + 5 * blockIdx.x;
   const int u0 = gg[0], u1 = gg[1], e0 = gg[2], e1 = gg[3], slot = gg[4];
   const int lane = threadIdx.x;
@@ -1093,14 +1098,14 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
         wl = cmul(wl, w);
         out = cmul(wl, make_double2(ur[lc], ui[lc]));
       }
-      s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
+      s_o[lc * kSoStride + lane] = act ? out : make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int lc = lane & 7, seg = lane >> 3;
     const int uu = u0 + seg, l = 8 * c + lc;
     if (uu < u1 && l < P) {
       const int q0 = max(up_ptr[uu], e0), q1 = min(up_ptr[uu + 1], e1);
-      const double2 sv = seg_sum(s_o + lc * 64, q0 - e0, q1 - e0);
+      const double2 sv = seg_sum(s_o + lc * kSoStride, q0 - e0, q1 - e0);
       const double re = sv.x, im = sv.y;
       if (slot < 0)
         mpole[(size_t)up_box[uu] * P + l] = make_double2(re, im);
@@ -1157,7 +1162,7 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
   const int P = EXACT ? PM : Prt;
   local += blockIdx.y * smp;  // right-hand side blockIdx.y
   locf += blockIdx.y * slf;
-  __shared__ double2 s_o[8 * 64];
+  __shared__ double2 s_o[8 * kSoStride];
   const int f0 = grp[blockIdx.x], f1 = grp[blockIdx.x + 1];
   const int e0 = anc_ptr[f0], e1 = anc_ptr[f1];
   const int lane = threadIdx.x;
@@ -1215,7 +1220,7 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
         out = cmul(ql, make_double2(ur[lc], ui[lc]));
         ql = cmul(ql, q);
       }
-      s_o[lc * 64 + lane] = act ? out : make_double2(0.0, 0.0);
+      s_o[lc * kSoStride + lane] = act ? out : make_double2(0.0, 0.0);
     }
     __syncthreads();
     const int lc = lane & 7, seg = lane >> 3;
@@ -1224,7 +1229,7 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
       const int bf = leaf_box[f];
       double2 v = make_double2(0.0, 0.0);
       if (box_level[bf] >= 2) {
-        const double2 sv = seg_sum(s_o + lc * 64, anc_ptr[f] - e0, anc_ptr[f + 1] - e0);
+        const double2 sv = seg_sum(s_o + lc * kSoStride, anc_ptr[f] - e0, anc_ptr[f + 1] - e0);
         const double2 own = local[(size_t)bf * P + l];
         v = make_double2(own.x + sv.x, own.y + sv.y);
       }
