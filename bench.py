@@ -2,10 +2,12 @@
 """Throughput of the extension + volume FMM path on one MI355X.
 
 A step is one pass of the whole path (cut-leaf extension, P2M/M2M,
-M2L/P2L, L2L, near field, far field) over the synthetic starfish workload
-(K = 16 leaf grids, adaptive level-restricted tree, about 1.08e6 leaf nodes),
-with every input already resident in HBM.  The value is leaf points per
-second.  Per-phase times come from HIP events recorded by the library on the
+M2L/P2L, L2L, near field, far field) over the synthetic wedge workload
+(square minus a wedge, K = 16 leaf grids, adaptive level-restricted tree of
+ten levels, 3.65e6 leaf nodes, 1536 cut leaves), with every input already
+resident in HBM.  The value is leaf points per second in FP64; beside it,
+the same path with the mixed-precision near field at every level threshold,
+each checked against the oracle.  Per-phase times come from HIP events recorded by the library on the
 execute stream during the timed steps; the roofline object describes the
 dominant phase.  The CPU baseline times the oracle (direct quadrature of the
 volume potential at a seeded sample of nodes plus its float64 extension of
@@ -206,9 +208,13 @@ def accuracy_check(case, fe_gpu, V_gpu, sel, v_o, fe_o, info):
       g3  V of the timed plan against the oracle's V of the oracle's f^e
           (end to end, extension included);
       extension  the GPU's f^e against the oracle's float64 extension, as
-          the worst ratio to the least-squares forward-error bound (<= 1).
+          the worst ratio to the least-squares forward-error bound of two
+          float64 routes, 32 u cond(A_I) max|f| (<= 1).
     V_o(fe_gpu) = V_o(fe_o) + V_o(fe_gpu - fe_o); the difference is nonzero
-    only on extension targets.  Returns the check record and V_o(fe_gpu)."""
+    only on extension targets.  g3 passes within 1e-10 plus the potential
+    the allowed f^e differences can carry (|int_B log|x-y| d| <= |d| h^2
+    (|log h| + 2) / 2 pi per target leaf of side h <= 1), relative to
+    max |V|.  Returns the check record and V_o(fe_gpu)."""
     import numpy as np
     from oracle import extension, geometry, volume
     tr = case["tree"]
@@ -221,19 +227,24 @@ def accuracy_check(case, fe_gpu, V_gpu, sel, v_o, fe_o, info):
     Vs = np.asarray(V_gpu).ravel()[sel]
     g1 = float(np.abs(Vs - v_g).max() / np.abs(v_g).max())
     g3 = float(np.abs(Vs - v_o).max() / np.abs(v_o).max())
-    worst = 0.0
+    worst, bound = 0.0, 0.0
     cut_ids = list(tr["cut_ids"])
+    h = ot.h()
     for i, rec in info.items():
         tg = rec["targets"]
         r = cut_ids.index(i)
         f_int = case["f_cut"][r][tr["mask"][r] != 0]
-        tol = extension.extension_tolerance(rec, fe_o[tg], f_int)
+        tol = 2.0 * extension.extension_tolerance(rec, fe_o[tg], f_int)
         worst = max(worst, float(np.abs(feg[tg] - fe_o[tg]).max()) / tol)
-    rec = {"volume_nodes": int(sel.size), "g1_rel_linf": g1, "g3_rel_linf": g3,
+        for j in tg:
+            bound += tol * h[j] ** 2 * (abs(math.log(h[j])) + 2.0) / (2.0 * math.pi)
+    g3_allowed = 1e-10 + bound / float(np.abs(v_o).max())
+    rec = {"volume_nodes": int(sel.size), "g1_rel_linf": g1, "g3_rel_linf": g3, "g3_allowed": g3_allowed,
            "extension_worst_error_over_bound": worst, "tolerance": 1e-10,
-           "pass": bool(g1 <= 1e-10 and g3 <= 1e-10 and worst <= 1.0),
-           "note": "timed plan's V against the oracle: g1 = V_oracle(GPU f^e), g3 = V_oracle(oracle f^e) "
-                   "(end to end); extension within 16 u cond(A_I) max|f| of the oracle's float64 extension"}
+           "pass": bool(g1 <= 1e-10 and g3 <= g3_allowed and worst <= 1.0),
+           "note": "timed plan's V against the oracle: g1 = V_oracle(GPU f^e) within 1e-10; g3 = "
+                   "V_oracle(oracle f^e) (end to end) within 1e-10 plus the potential of the allowed f^e "
+                   "differences; extension within 32 u cond(A_I) max|f| of the oracle's float64 extension"}
     return rec, v_g
 
 
@@ -483,7 +494,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--baseline-seconds", type=float, default=15.0)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
-                    help="the timed path: FP64, or the near field in bf16 slices with FP32 accumulation")
+                    help="the timed path: FP64, or the near field in fixed-point bf16 slices on the matrix cores")
     ap.add_argument("--min-level", type=int, default=0,
                     help="with --precision mixed: sources at this level or finer run mixed")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision sweep beside FP64")
@@ -596,13 +607,14 @@ def main():
         "metric": METRIC, "value": value, "unit": "leaf points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * sec, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+bf16x3/f32",
+        "dtype": "f64" if args.precision == "fp64" else "f64+bf16",
         "data": "synthetic",
         "config": {"workload": case["cfg"]["name"], "leaves": st["n_leaves"], "nodes": N, "K": case["K"],
                    "p": case["p"], "levels": st["n_levels"], "cut_leaves": st["n_cut"],
                    "ext_targets": st["n_ext_targets"],
                    "precision": "fp64" if args.precision == "fp64" else
-                   f"mixed: near field of sources at level >= {args.min_level} in bf16 slices, FP32 accumulation"},
+                   (f"mixed: near field of sources at level >= {args.min_level} in fixed-point bf16 slices "
+                    "(exact FP32 block sums, FP64 results)")},
         "phases_ms": {k: round(v, 4) for k, v in phases.items() if k != "count"},
         "autotune": choice,
         "plan_s": st["plan_seconds"], "tables_s": case["t_ctx"], "plan_stage": plan_stage,

@@ -229,12 +229,17 @@ int vfx_net_charge_noalloc_max_rhs(void);
 
 /* Precision of the near field.  mode 0: FP64
  * everywhere (the default).  mode 1: the list-1 interactions whose source
- * leaf is at level >= min_level are applied with the operands split into
- * three bf16 slices (about 24 significant bits) on the bf16 matrix cores
- * with FP32 accumulation; their results, the log(h) terms, every multipole
- * and local expansion, the M2L log term and the final sums stay FP64.  The
- * near-field contribution of a source of side h scales like h^2, so a
- * min_level bounds the error those interactions can add.  Available for
+ * leaf is at level >= min_level are applied on the bf16 matrix cores (the
+ * tables of Section 4): every operand row (leaf data, table rows, the
+ * low-rank products Z) is cut into four 8-bit fixed-point slices under its
+ * own exponent, the slice products are grouped by the sum of their slice
+ * indices, and each group is summed exactly in FP32 over blocks of 128
+ * contraction indices before being widened to FP64; the result keeps about
+ * 2^-32 of the operands' row maxima and is stored in FP64 like the FP64
+ * path's.  The log(h) terms, every multipole and local expansion, the M2L
+ * log term and the final sums stay FP64.  The near-field contribution of a
+ * source of side h scales like h^2, so a min_level bounds the error those
+ * interactions can add.  Available for
  * K = 16 only (VFX_EINVAL otherwise, and the plan stays FP64).  The plan's
  * device data are rebuilt on the next vfx_execute; the call synchronises the
  * device and must not overlap an execute of the same plan. */

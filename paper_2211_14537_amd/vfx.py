@@ -340,8 +340,9 @@ class Plan:
         _check(lib().vfx_plan_set_near_mode(self._h, int(mode)))
 
     def set_precision(self, mode, min_level=0):
-        """Near-field precision: 0 = FP64, 1 = bf16 slices with FP32
-        accumulation for sources at level >= min_level (K = 16)."""
+        """Near-field precision: 0 = FP64, 1 = fixed-point bf16 slices on the
+        matrix cores (exact FP32 block sums, FP64 results) for sources at
+        level >= min_level (K = 16)."""
         _check(lib().vfx_plan_set_precision(self._h, int(mode), int(min_level)))
 
     def set_timing(self, on=True):
