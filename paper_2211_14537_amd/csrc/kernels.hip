@@ -1115,7 +1115,10 @@ __global__ void __launch_bounds__(64) k_up(int Prt, double root_size, const int*
   });
 }
 
-// Multipoles of the split boxes: slices added in slice order.
+// Multipoles of the split boxes: the slices' partial sums added in a fixed
+// order (eight running sums, slice j into sum j mod 8, then combined
+// pairwise), eight loads in flight per round rather than one round trip per
+// slice.
 __global__ void __launch_bounds__(64) k_up_sum(int P, const int* __restrict__ split, const double2* __restrict__ part,
                                                double2* __restrict__ mpole, long spart, long smp) {
   part += blockIdx.y * spart;  // right-hand side blockIdx.y
@@ -1123,13 +1126,24 @@ __global__ void __launch_bounds__(64) k_up_sum(int P, const int* __restrict__ sp
   const int* sp = split + 3 * blockIdx.x;
   const int l = threadIdx.x;
   if (l >= P) return;
-  double re = 0.0, im = 0.0;
-  for (int j = 0; j < sp[2]; ++j) {
-    const double2 v = part[(size_t)(sp[1] + j) * P + l];
-    re += v.x;
-    im += v.y;
+  const int first = sp[1], ns = sp[2];
+  double re[8], im[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) re[u] = im[u] = 0.0;
+  for (int j = 0; j < ns; j += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = j + u < ns ? part[(size_t)(first + j + u) * P + l] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      re[u] += v[u].x;
+      im[u] += v[u].y;
+    }
   }
-  mpole[(size_t)sp[0] * P + l] = make_double2(re, im);
+  const double r = ((re[0] + re[1]) + (re[2] + re[3])) + ((re[4] + re[5]) + (re[6] + re[7]));
+  const double i = ((im[0] + im[1]) + (im[2] + im[3])) + ((im[4] + im[5]) + (im[6] + im[7]));
+  mpole[(size_t)sp[0] * P + l] = make_double2(r, i);
 }
 
 __device__ __forceinline__ double2 cpow(double2 z, int k) {
