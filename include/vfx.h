@@ -143,8 +143,8 @@ int vfx_plan_ext_owner(const vfx_plan* plan, int32_t* owner);
  *                            leaf (exterior entries are not read)
  *   fe_out  n_leaves x K^2   extended data f^e (written)
  *   V_out   n_leaves x K^2   V[f^e] at every leaf node (written)
- * f_leaf and fe_out must be 16-byte aligned (they are accessed in 16-byte
- * pieces).
+ * f_leaf, fe_out and V_out must be 16-byte aligned (they are accessed in
+ * 16-byte pieces).
  * The arrays carry no sizes: the caller guarantees the extents above.
  * Inputs are not scanned: a NaN or Inf in a value that is read propagates
  * through IEEE arithmetic into f^e and V (the far field spreads it to every

@@ -251,8 +251,9 @@ static int execute_checked(vfx_plan* plan, int nrhs, const double* f_leaf, const
                            double* V_out, void* stream, const char* who) {
   if (!plan || !f_leaf || !fe_out || !V_out || nrhs < 1)
     return fail(VFX_EINVAL, std::string(who) + ": null argument or nrhs < 1");
-  if (reinterpret_cast<uintptr_t>(fe_out) % 16 || reinterpret_cast<uintptr_t>(f_leaf) % 16)
-    return fail(VFX_EINVAL, std::string(who) + ": f_leaf and fe_out must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(fe_out) % 16 || reinterpret_cast<uintptr_t>(f_leaf) % 16 ||
+      reinterpret_cast<uintptr_t>(V_out) % 16)
+    return fail(VFX_EINVAL, std::string(who) + ": f_leaf, fe_out and V_out must be 16-byte aligned");
   if (plan->p.H.ncut > 0 && !f_cut)
     return fail(VFX_EINVAL, std::string(who) + ": f_cut is null but the tree has cut leaves");
   vfx::Plan& p = plan->p;

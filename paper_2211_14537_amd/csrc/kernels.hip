@@ -1300,11 +1300,14 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
   const int my_slot3 = lane < n3 ? l3_slot[f0 + lane] : 0;
   const double my_b0 = lane < n3 ? mpole[(size_t)l3_src[f0 + lane] * P].x : 0.0;
   const double2 my_c = (lev >= 2 && lane < P) ? locf[(size_t)leaf * P + lane] : double2{0.0, 0.0};
+  // lane l holds nodes 4l .. 4l+3 when K^2 = 256 (rows of the per-pair
+  // products are read with two 16-byte loads per lane), else l + 64j
   int node[NPL];
   double tx[NPL], ty[NPL], acc[NPL];
 #pragma unroll
   for (int j = 0; j < NPL; ++j) {
-    node[j] = lane + 64 * j < n ? lane + 64 * j : 0;
+    const int nd = NPL == 4 ? 4 * lane + j : lane + 64 * j;
+    node[j] = nd < n ? nd : 0;
     tx[j] = 0.5 * t[node[j] / K];
     ty[j] = 0.5 * t[node[j] % K];
   }
@@ -1322,16 +1325,32 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
 #pragma unroll 4
       for (int e = 0; e < n1; ++e) {
         const double* y = Y + (size_t)__builtin_amdgcn_readlane(my_slot, e) * n;
+        if constexpr (NPL == 4) {
+          const double2 u0 = *(const double2*)(y + 4 * lane), u1 = *(const double2*)(y + 4 * lane + 2);
+          yn[0] += u0.x;
+          yn[1] += u0.y;
+          yn[2] += u1.x;
+          yn[3] += u1.y;
+        } else {
 #pragma unroll
-        for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
+          for (int j = 0; j < NPL; ++j) yn[j] += y[node[j]];
+        }
         lg += readlane_d(my_a0, e);
       }
     }
 #pragma unroll 4
     for (int q = 0; q < n3; ++q) {
       const double* y = Y3 + (size_t)__builtin_amdgcn_readlane(my_slot3, q) * n;
+      if constexpr (NPL == 4) {
+        const double2 u0 = *(const double2*)(y + 4 * lane), u1 = *(const double2*)(y + 4 * lane + 2);
+        y3[0] += u0.x;
+        y3[1] += u0.y;
+        y3[2] += u1.x;
+        y3[3] += u1.y;
+      } else {
 #pragma unroll
-      for (int j = 0; j < NPL; ++j) y3[j] += y[node[j]];
+        for (int j = 0; j < NPL; ++j) y3[j] += y[node[j]];
+      }
       lg3 += readlane_d(my_b0, q);
     }
     const double lh = log(h);
@@ -1363,9 +1382,14 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
 #pragma unroll
     for (int j = 0; j < NPL; ++j) acc[j] += ur[j];
   }
+  if constexpr (NPL == 4) {
+    *(double2*)(V + (size_t)leaf * n + 4 * lane) = make_double2(kInv2Pi * acc[0], kInv2Pi * acc[1]);
+    *(double2*)(V + (size_t)leaf * n + 4 * lane + 2) = make_double2(kInv2Pi * acc[2], kInv2Pi * acc[3]);
+  } else {
 #pragma unroll
-  for (int j = 0; j < NPL; ++j)
-    if (lane + 64 * j < n) V[(size_t)leaf * n + lane + 64 * j] = kInv2Pi * acc[j];
+    for (int j = 0; j < NPL; ++j)
+      if (lane + 64 * j < n) V[(size_t)leaf * n + lane + 64 * j] = kInv2Pi * acc[j];
+  }
 }
 
 // -------------------------------------------------------------------------

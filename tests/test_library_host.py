@@ -222,6 +222,13 @@ def test_rejects_invalid_input():
     with pytest.raises(vfx.VfxError) as e:
         vfx.Plan(ctx, [0], [0], [0], [5])
     assert e.value.code == vfx.VFX_EINVAL
+    # misaligned buffers are refused before anything is read (the pointers
+    # below are never dereferenced: the check is on their values)
+    plan = vfx.Plan(ctx, [0], [0], [0], [1])
+    for f_leaf, fe_out, V_out in ((8, 16, 16), (16, 8, 16), (16, 16, 8)):
+        rc = vfx.lib().vfx_execute(plan._h, f_leaf, 0, fe_out, V_out, None)
+        assert rc == vfx.VFX_EINVAL
+        assert "16-byte aligned" in vfx.lib().vfx_last_error().decode()
 
 
 def test_near_lowrank_factors_match_oracle_quadrature():
