@@ -6,8 +6,10 @@ M2L/P2L, L2L, near field, far field) over the synthetic wedge workload
 (square minus a wedge, K = 16 leaf grids, adaptive level-restricted tree of
 ten levels, 3.65e6 leaf nodes, 1536 cut leaves), with every input already
 resident in HBM.  The value is leaf points per second in FP64; beside it,
-the same path with the mixed-precision near field at every level threshold,
-each checked against the oracle.  Per-phase times come from HIP events recorded by the library on the
+the same path with the mixed-precision near field (five fixed-point int8
+slices per operand row on the int8 matrix cores, exact int32 sums, FP64
+results) at every level threshold, each checked against the oracle, and the
+four-slice bf16 form of the same products for comparison.  Per-phase times come from HIP events recorded by the library on the
 execute stream during the timed steps; the roofline object describes the
 dominant phase.  The CPU baseline times the oracle (direct quadrature of the
 volume potential at a seeded sample of nodes plus its float64 extension of
@@ -444,26 +446,37 @@ def run_steps(plan, fl, fc, fe, V, stream, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+MIXED_MODES = {"mixed": 2, "mixed-bf16": 1}
+MIXED_SETTING = {
+    2: "five fixed-point int8 slices per operand row on the int8 matrix cores (exact int32 sums, FP64 results)",
+    1: "four fixed-point bf16 slices per operand row on the bf16 matrix cores (exact FP32 block sums, FP64 results)",
+}
+
+
 def mixed_sweep(case, plan, fl, fc, fe, V, stream, args, V64, sel=None, v_g=None):
-    """The near field in mixed precision for every level threshold (sources
-    at level >= min_level mixed; 0 = all), each timed like the FP64 path and
-    checked: against the oracle's V of the GPU's f^e at the sampled nodes
-    when there is an oracle sample (g1), else against the FP64 GPU result.
-    The reported setting is the widest mixing (smallest threshold) whose
-    error meets 1e-10."""
+    """The near field in mixed precision (int8 slices) for every level
+    threshold (sources at level >= min_level mixed; 0 = all), each timed
+    like the FP64 path and checked: against the oracle's V of the GPU's f^e
+    at the sampled nodes when there is an oracle sample (g1), else against
+    the FP64 GPU result.  The reported setting is the widest mixing
+    (smallest threshold) whose error meets 1e-10; the bf16-slice form is
+    timed and checked at every threshold too, for comparison."""
     import numpy as np
     import torch
     nlev = int(np.max(case["tree"]["level"]))
-    rows = []
-    for lmin in range(0, nlev + 1):
-        plan.set_precision(1, lmin)
+
+    def run(mode, lmin):
+        plan.set_precision(mode, lmin)
         sec = run_steps(plan, fl, fc, fe, V, stream, args.steps, args.warmup)
         Vm = V.cpu().numpy()
         if v_g is not None:
             err = float(np.abs(Vm.ravel()[sel] - v_g).max() / np.abs(v_g).max())
         else:
             err = float(np.abs(Vm - V64).max() / np.abs(V64).max())
-        rows.append({"min_level": lmin, "ms_per_step": 1e3 * sec, "rel_linf": err})
+        return {"min_level": lmin, "ms_per_step": 1e3 * sec, "rel_linf": err}
+
+    rows = [run(2, lmin) for lmin in range(0, nlev + 1)]
+    rows_bf16 = [run(1, lmin) for lmin in range(0, nlev + 1)]
     plan.set_precision(0)
     torch.cuda.synchronize()
     N = case["tree"]["level"].size * case["K"] ** 2
@@ -472,10 +485,10 @@ def mixed_sweep(case, plan, fl, fc, fe, V, stream, args, V64, sel=None, v_g=None
     out = {"error_against": "oracle V of the GPU's f^e at the sampled nodes" if v_g is not None
            else "FP64 GPU path (no oracle sample in this run)",
            "tolerance": 1e-10,
-           "sweep": [dict(r, value=N / (1e-3 * r["ms_per_step"])) for r in rows]}
+           "sweep": [dict(r, value=N / (1e-3 * r["ms_per_step"])) for r in rows],
+           "sweep_bf16_slices": [dict(r, value=N / (1e-3 * r["ms_per_step"])) for r in rows_bf16]}
     if best is not None:
-        out.update({"setting": f"near field of sources at level >= {best['min_level']} on the bf16 matrix "
-                               "cores in four fixed-point slices (exact FP32 block sums, FP64 results); "
+        out.update({"setting": f"near field of sources at level >= {best['min_level']} in {MIXED_SETTING[2]}; "
                                "everything else FP64",
                     "min_level": best["min_level"], "value": N / (1e-3 * best["ms_per_step"]),
                     "ms_per_step": best["ms_per_step"], "rel_linf": best["rel_linf"]})
@@ -493,8 +506,9 @@ def main():
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--baseline-seconds", type=float, default=15.0)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
-                    help="the timed path: FP64, or the near field in fixed-point bf16 slices on the matrix cores")
+    ap.add_argument("--precision", choices=("fp64", "mixed", "mixed-bf16"), default="fp64",
+                    help="the timed path: FP64, or the near field in fixed-point int8 (mixed) or bf16 "
+                         "(mixed-bf16) slices on the matrix cores")
     ap.add_argument("--min-level", type=int, default=0,
                     help="with --precision mixed: sources at this level or finer run mixed")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision sweep beside FP64")
@@ -530,8 +544,8 @@ def main():
     plan = case["plan"]
     if args.near_mode:
         plan.set_near_mode(args.near_mode)
-    if args.precision == "mixed":
-        plan.set_precision(1, args.min_level)
+    if args.precision != "fp64":
+        plan.set_precision(MIXED_MODES[args.precision], args.min_level)
     st = plan.stats()
     fl = torch.tensor(case["f_leaf"], dtype=torch.float64, device=dev)
     fc = torch.tensor(case["f_cut"], dtype=torch.float64, device=dev)
@@ -577,7 +591,7 @@ def main():
     rows = []
     for k, (fl_, by_, stream_) in work.items():
         if args.precision != "fp64" and k in ("near_lowrank", "near_dense"):
-            continue  # bf16 kernels: not an FP64 roofline
+            continue  # int8 or bf16 kernels: not an FP64 roofline
         t_roof = max(fl_ / (FP64_PEAK_TFLOPS * 1e12), by_ / (HBM_PEAK_GBS * 1e9))
         ms = phases.get(k)
         rows.append({"phase": k, "kernel": kernels[k][0], "stream": stream_, "flops": fl_, "bytes": by_,
@@ -607,14 +621,14 @@ def main():
         "metric": METRIC, "value": value, "unit": "leaf points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * sec, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f64+bf16",
+        "dtype": {"fp64": "f64", "mixed": "f64+i8", "mixed-bf16": "f64+bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": case["cfg"]["name"], "leaves": st["n_leaves"], "nodes": N, "K": case["K"],
                    "p": case["p"], "levels": st["n_levels"], "cut_leaves": st["n_cut"],
                    "ext_targets": st["n_ext_targets"],
                    "precision": "fp64" if args.precision == "fp64" else
-                   (f"mixed: near field of sources at level >= {args.min_level} in fixed-point bf16 slices "
-                    "(exact FP32 block sums, FP64 results)")},
+                   (f"mixed: near field of sources at level >= {args.min_level} in "
+                    f"{MIXED_SETTING[MIXED_MODES[args.precision]]}")},
         "phases_ms": {k: round(v, 4) for k, v in phases.items() if k != "count"},
         "autotune": choice,
         "plan_s": st["plan_seconds"], "tables_s": case["t_ctx"], "plan_stage": plan_stage,

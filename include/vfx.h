@@ -227,8 +227,8 @@ int vfx_net_charge(vfx_plan* plan, const double* fe, int nrhs, double* out, void
 int vfx_net_charge_noalloc(vfx_plan* plan, const double* fe, int nrhs, double* out, void* stream);
 int vfx_net_charge_noalloc_max_rhs(void);
 
-/* Precision of the near field.  mode 0: FP64
- * everywhere (the default).  mode 1: the list-1 interactions whose source
+/* Precision of the near field (mode 0, 1 or 2; VFX_EINVAL otherwise).
+ * mode 0: FP64 everywhere (the default).  mode 1: the list-1 interactions whose source
  * leaf is at level >= min_level are applied on the bf16 matrix cores (the
  * tables of Section 4): every operand row (leaf data, table rows, the
  * low-rank products Z) is cut into four 8-bit fixed-point slices under its
@@ -236,7 +236,13 @@ int vfx_net_charge_noalloc_max_rhs(void);
  * indices, and each group is summed exactly in FP32 over blocks of 128
  * contraction indices before being widened to FP64; the result keeps about
  * 2^-32 of the operands' row maxima and is stored in FP64 like the FP64
- * path's.  The log(h) terms, every multipole and local expansion, the M2L
+ * path's.  mode 2: the same interactions on the int8 matrix cores: every
+ * operand row is cut into five 7-bit fixed-point slices (the leading one
+ * 6 bits plus sign, each a signed integer of magnitude <= 64), the slice
+ * pairs whose index sum is below 5 are multiplied and each group is summed
+ * exactly in int32 over the whole contraction; the result keeps about
+ * 2^-34 of the operands' row maxima (FP64 results as in mode 1).  In both
+ * modes the log(h) terms, every multipole and local expansion, the M2L
  * log term and the final sums stay FP64.  The near-field contribution of a
  * source of side h scales like h^2, so a min_level bounds the error those
  * interactions can add.  Available for

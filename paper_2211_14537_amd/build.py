@@ -16,8 +16,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["api.cpp", "tables.cpp", "stencil.cpp", "plan.cpp", "kernels.hip", "near.hip", "mixed.hip", "ext_batch.hip",
-           "mlp.hip", "factor.hip"]
+SOURCES = ["api.cpp", "tables.cpp", "stencil.cpp", "plan.cpp", "kernels.hip", "near.hip", "mixed.hip", "mixed8.hip",
+           "ext_batch.hip", "mlp.hip", "factor.hip"]
 HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
 OUT = os.path.join(HERE, "lib", "libvfx.so")
 BUILD_DIR = os.path.join(HERE, "_build")

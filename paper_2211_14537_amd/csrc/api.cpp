@@ -414,11 +414,11 @@ int vfx_graph_destroy(vfx_graph* g) {
 }
 
 int vfx_plan_set_precision(vfx_plan* plan, int mode, int min_level) {
-  if (!plan || (mode != 0 && mode != 1)) return fail(VFX_EINVAL, "vfx_plan_set_precision: mode must be 0 or 1");
+  if (!plan || mode < 0 || mode > 2) return fail(VFX_EINVAL, "vfx_plan_set_precision: mode must be 0, 1 or 2");
   vfx::Plan& p = plan->p;
   try {
     std::string err;
-    int rc = vfx::build_near_tiles(p.ctx->T, p.H, mode, mode == 1 ? min_level : 0, err);
+    int rc = vfx::build_near_tiles(p.ctx->T, p.H, mode, mode >= 1 ? min_level : 0, err);
     if (rc) {
       vfx::build_near_tiles(p.ctx->T, p.H, 0, 0, err);
       return fail(rc, "vfx_plan_set_precision: " + err);

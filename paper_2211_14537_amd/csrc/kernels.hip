@@ -1676,6 +1676,12 @@ int upload_tables(Context* c, std::string& err) {
   UP(D.fx_Qexp, T.fx_Qexp);
   UP(D.fx_A, T.fx_A);
   UP(D.fx_Aexp, T.fx_Aexp);
+  UP(D.f8_W, T.f8_W);
+  UP(D.f8_Wexp, T.f8_Wexp);
+  UP(D.f8_Q, T.f8_Q);
+  UP(D.f8_Qexp, T.f8_Qexp);
+  UP(D.f8_A, T.f8_A);
+  UP(D.f8_Aexp, T.f8_Aexp);
   UP(D.p2l_gemm, T.p2l_gemm);
   UP(D.m2p_gemm, T.m2p_gemm);
   UP(D.p2m_gemm, T.p2m_gemm);
@@ -1724,7 +1730,7 @@ void free_tables_device(Context* c) {
                   D.pas_m2l,  D.pas_m2m,  D.pas_l2l,  D.m2l_logd, D.p2l_gemm, D.m2p_gemm, D.m2l_tpow, D.m2l_tneg, D.p2m_gemm,
                   D.m2m_in,   D.m2m_out,  D.l2l_in,   D.l2l_out,  D.pas_m2l_t, D.pas_m2m_t, D.pas_l2l_t,
                   D.lr_R,     D.lr_W,     D.lr_Q,     D.fx_W,     D.fx_Q,     D.fx_A,     D.fx_Wexp,
-                  D.fx_Qexp,  D.fx_Aexp,
+                  D.fx_Qexp,  D.fx_Aexp,  D.f8_W,     D.f8_Q,     D.f8_A,     D.f8_Wexp,  D.f8_Qexp,  D.f8_Aexp,
                   D.cls_R,    D.lr_Wp,    D.cls_QT,   D.self_T};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -1761,7 +1767,7 @@ int ensure_rhs_capacity(Plan* p, int nrhs, std::string& err) {
   if (!H.p3_src.empty()) VFX_HIP(hipMalloc((void**)&D.m2p_y, sizeof(double) * H.p3_src.size() * T.n * R));
   if (H.up_slots > 0) VFX_HIP(hipMalloc((void**)&D.up_part, sizeof(double2) * (size_t)H.up_slots * P * R));
   VFX_HIP(hipMalloc((void**)&D.locf, sizeof(double2) * (size_t)H.L * P * R));
-  if (H.precision == 1 && !H.ts) {
+  if (H.precision >= 1 && !H.ts) {  // bf16 slices (mode 1) or int8 slices (mode 2, 5/8 of the size)
     VFX_HIP(hipMalloc((void**)&D.xs, sizeof(uint16_t) * 4 * (size_t)H.L * T.n * R));
     VFX_HIP(hipMalloc((void**)&D.xs_exp, sizeof(int) * (size_t)H.L * R));
   }
@@ -2144,10 +2150,12 @@ int launch_execute(Plan* p, int nrhs, const double* f_leaf, const double* f_cut,
                          D.nl_cfg, D.nl_first, D.nl_count, D.np_src, DT.lr_R, DT.lr_W, DT.lr_Q, fe, D.near_y, sFL,
                          sNY);
     }
-    if (H.precision == 1) {
-      // pairs in mixed precision: fixed-point bf16 slices of the leaf data,
-      // then their low-rank and self products (FP64 results, same buffer)
-      int rc = launch_near_fx(p, fe, nrhs, p->tune.near_wgs, p->side, err);
+    if (H.precision >= 1) {
+      // pairs in mixed precision: fixed-point bf16 (mode 1) or int8 (mode 2)
+      // slices of the leaf data, then their low-rank and self products (FP64
+      // results, same buffer)
+      int rc = H.precision == 2 ? launch_near_f8(p, fe, nrhs, p->tune.near_wgs, p->side, err)
+                                : launch_near_fx(p, fe, nrhs, p->tune.near_wgs, p->side, err);
       if (rc) return rc;
     }
     VFX_HIP(hipGetLastError());

@@ -52,7 +52,7 @@ inline bool touch(int la, int ax, int ay, int lb, int bx, int by) {
 }  // namespace
 
 // List-1 pairs grouped for the near-field kernels: configuration-major, and
-// inside a configuration by precision class (mode 1: sources at level >=
+// inside a configuration by precision class (modes 1, 2: sources at level >=
 // min_level are applied in mixed precision: the self operator densely, the
 // other configurations in their low-rank form, so a configuration without
 // one stays in FP64), then by target.  Tiles of <= 64
@@ -62,13 +62,13 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
   const int L = H.L;
   const int N1 = H.l1_ptr[L];
   const bool k16 = T.n == 256 && !T.lr_R.empty();
-  if (mode == 1 && !k16) {
+  if (mode >= 1 && !k16) {
     err = "mixed precision is available for K = 16 only";
     return VFX_EINVAL;
   }
   auto mixed = [&](int e) {
     const int c = H.l1_cfg[e];
-    return mode == 1 && H.box_level[H.leaf_box[H.l1_src[e]]] >= min_level && (c == kNearSelf || T.lr_R[c] > 0);
+    return mode >= 1 && H.box_level[H.leaf_box[H.l1_src[e]]] >= min_level && (c == kNearSelf || T.lr_R[c] > 0);
   };
   // counting sort on (configuration, class)
   std::vector<int> cnt(2 * kNearConfigs + 1, 0);
@@ -89,7 +89,7 @@ int build_near_tiles(const Tables& T, HostPlan& H, int mode, int min_level, std:
                   &H.mt_first, &H.mt_count, &H.ml_cfg, &H.ml_first, &H.ml_count})
     v->clear();
   // With the target-stationary near field selected (near_mode 1), FP64 at
-  // K = 16 (also precision mode 1 when no pair is mixed) takes that path: every non-self pair's factor product by the
+  // K = 16 (also precision modes 1, 2 when no pair is mixed) takes that path: every non-self pair's factor product by the
   // table GEMM (configuration-major tiles of 64), then the per-target-group
   // kernel; the self pairs only there
   bool any_mixed = false;

@@ -92,6 +92,10 @@ struct Tables {
   // (v = 2^e sum_s q_s 2^(-8(s+1)), q_s integers of magnitude <= 256)
   std::vector<uint16_t> fx_W, fx_Q, fx_A;
   std::vector<int> fx_Wexp, fx_Qexp, fx_Aexp;
+  // the same operands as five int8 slices for the int8 matrix cores
+  // (v = 2^e sum_s q_s 2^(-6-7s), q_s integers of magnitude <= 64)
+  std::vector<int8_t> f8_W, f8_Q, f8_A;
+  std::vector<int> f8_Wexp, f8_Qexp, f8_Aexp;
   std::vector<double> p2m;             // (p+1) x n complex, [k][j] (re,im)
   std::vector<double> l2p;             // n x (p+1) complex, [i][l]
   std::vector<double> m2m;             // 4 x (p+1) x (p+1) complex, [q][k][l]
@@ -155,6 +159,8 @@ struct DeviceTables {
   double *lr_W = nullptr, *lr_Q = nullptr;
   uint16_t *fx_W = nullptr, *fx_Q = nullptr, *fx_A = nullptr;
   int *fx_Wexp = nullptr, *fx_Qexp = nullptr, *fx_Aexp = nullptr;
+  int8_t *f8_W = nullptr, *f8_Q = nullptr, *f8_A = nullptr;
+  int *f8_Wexp = nullptr, *f8_Qexp = nullptr, *f8_Aexp = nullptr;
   double2 *p2m = nullptr, *l2p = nullptr, *m2m = nullptr, *l2l = nullptr, *m2l = nullptr, *p2l = nullptr;
   double* p2l_area = nullptr;
   double *pas_m2l = nullptr, *pas_m2m = nullptr, *pas_l2l = nullptr, *m2l_logd = nullptr, *p2l_gemm = nullptr;
@@ -257,7 +263,7 @@ struct DevicePlan {
   int *nl_cfg = nullptr, *nl_first = nullptr, *nl_count = nullptr;
   int *mt_cfg = nullptr, *mt_first = nullptr, *mt_count = nullptr, *ml_cfg = nullptr, *ml_first = nullptr,
       *ml_count = nullptr;
-  uint16_t* xs = nullptr;  // fixed-point bf16 slices of the leaf data, 4 x L x n
+  uint16_t* xs = nullptr;  // fixed-point slices of the leaf data: 4 x L x n bf16 (or 5 x L x n int8)
   int* xs_exp = nullptr;   // their exponent per leaf, L
   int cap = 0;             // right-hand sides the per-RHS buffers hold
   bool factored = false;   // pinv_val holds the P_i
@@ -331,6 +337,7 @@ int launch_ext_gemm(const Plan* p, const double* f_cut, int nrhs, hipStream_t s,
 int launch_ext_eval(const Plan* p, const double* f_cut, double* fe, int nrhs, hipStream_t s, std::string& err);
 // mixed.hip
 int launch_near_fx(const Plan* p, const double* fe, int nrhs, int max_wgs, hipStream_t s, std::string& err);
+int launch_near_f8(const Plan* p, const double* fe, int nrhs, int max_wgs, hipStream_t s, std::string& err);
 // near.hip
 int launch_near_ts(const Plan* p, const double* fe, double* V, int nrhs, int max_wgs, hipStream_t s,
                    std::string& err);

@@ -340,9 +340,11 @@ class Plan:
         _check(lib().vfx_plan_set_near_mode(self._h, int(mode)))
 
     def set_precision(self, mode, min_level=0):
-        """Near-field precision: 0 = FP64, 1 = fixed-point bf16 slices on the
-        matrix cores (exact FP32 block sums, FP64 results) for sources at
-        level >= min_level (K = 16)."""
+        """Near-field precision for sources at level >= min_level (K = 16):
+        0 = FP64; 1 = four fixed-point bf16 slices per operand row on the
+        bf16 matrix cores (exact FP32 block sums, FP64 results); 2 = five
+        fixed-point int8 slices on the int8 matrix cores (exact int32 sums,
+        FP64 results)."""
         _check(lib().vfx_plan_set_precision(self._h, int(mode), int(min_level)))
 
     def set_timing(self, on=True):

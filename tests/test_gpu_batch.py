@@ -46,12 +46,13 @@ def _single(case, fl, fc):
     return fe.cpu().numpy(), V.cpu().numpy()
 
 
-@pytest.mark.parametrize("name,precision", [("starfish_small", 0), ("starfish_small", 1), ("disk_uniform3", 0)])
+@pytest.mark.parametrize("name,precision", [("starfish_small", 0), ("starfish_small", 1), ("starfish_small", 2),
+                                            ("disk_uniform3", 0)])
 def test_batch_matches_single_executes(gpu_device, name, precision):
     import torch
     case = setup(name, p=24 if name == "starfish_small" else 20)
     if precision:
-        case["plan"].set_precision(1, 0)
+        case["plan"].set_precision(precision, 0)
     nrhs = 5
     fl, fc = _inputs(case, nrhs, 1)
     singles = [_single(case, _dev(fl[r]), _dev(fc[r])) for r in range(nrhs)]

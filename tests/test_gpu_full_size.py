@@ -106,10 +106,11 @@ def test_full_size_starfish(gpu_device):
     assert rel3 <= 1e-10
 
 
-# The mixed-precision setting bench.py reports beside FP64 on this workload,
-# and its gate on G1: 10x the 8.4e-13 measured over these nodes (the FP64
-# path: 4.5e-13).
-WEDGE_MIXED = dict(min_level=0, gate=8.5e-12)
+# The mixed-precision setting bench.py reports beside FP64 on this workload
+# (int8 slices, mode 2; the bf16 slices of mode 1 are checked too), and the
+# gate on G1 of both: 10x the 8.4e-13 the bf16 slices gave over these nodes
+# (the FP64 path: 4.5e-13).
+WEDGE_MIXED = dict(min_level=0, modes=(2, 1), gate=8.5e-12)
 
 
 def test_full_size_wedge(gpu_device):
@@ -127,9 +128,10 @@ def test_full_size_wedge(gpu_device):
         f"(allowed {1e-10 + bound / np.abs(v_o).max():.3e})")
     assert g1 <= 1e-10
     assert g3 * np.abs(v_o).max() <= 1e-10 * np.abs(v_o).max() + bound
-    case["plan"].set_precision(1, WEDGE_MIXED["min_level"])
-    fe_mx, Vmx = run_gpu(case)
-    assert np.array_equal(fe_mx, fe)  # the extension is FP64 in both modes
-    g1m, g3m, _ = volume_checks(case, fe, Vmx, sel, tx, ty, ref)
-    say(f"    mixed (sources at level >= {WEDGE_MIXED['min_level']}): G1 {g1m:.3e}, G3 {g3m:.3e}")
-    assert g1m <= WEDGE_MIXED["gate"]
+    for mode in WEDGE_MIXED["modes"]:
+        case["plan"].set_precision(mode, WEDGE_MIXED["min_level"])
+        fe_mx, Vmx = run_gpu(case)
+        assert np.array_equal(fe_mx, fe)  # the extension is FP64 in every mode
+        g1m, g3m, _ = volume_checks(case, fe, Vmx, sel, tx, ty, ref)
+        say(f"    mixed mode {mode} (sources at level >= {WEDGE_MIXED['min_level']}): G1 {g1m:.3e}, G3 {g3m:.3e}")
+        assert g1m <= WEDGE_MIXED["gate"]

@@ -1,9 +1,10 @@
 """Mixed-precision near field against the oracle and the FP64 path.
 
-The list-1 interactions of sources at level >= min_level run on the bf16
-matrix cores (four fixed-point bf16 slices per operand row, exact FP32 sums
-per block of 128 contraction indices, FP64 results); everything else stays
-FP64.  The tests state the error of V against the oracle's direct
+The list-1 interactions of sources at level >= min_level run on the matrix
+cores in fixed-point slices: mode 1 four bf16 slices per operand row (exact
+FP32 sums per block of 128 contraction indices), mode 2 five int8 slices
+(exact int32 sums over the whole contraction); FP64 results in both, and
+everything else stays FP64.  The tests state the error of V against the oracle's direct
 quadrature per setting, bound it, and check that raising min_level (fewer
 mixed interactions, each with a smaller h^2 weight excluded) does not make
 it worse than the all-mixed setting."""
@@ -19,7 +20,8 @@ def _rel(case, V, sel, vo):
     return float(np.abs(V.ravel()[sel] - vo).max() / np.abs(vo).max())
 
 
-def test_mixed_volume_against_oracle(gpu_device):
+@pytest.mark.parametrize("mode", [1, 2], ids=["bf16", "int8"])
+def test_mixed_volume_against_oracle(gpu_device, mode):
     case = setup("starfish_small", p=24, all_regular=True)
     sel, tx, ty = sample_targets(case, 400, leaves=(0, case["otree"].n - 1))
     vo = oracle_potential(case, case["f_leaf"], tx, ty)
@@ -27,11 +29,11 @@ def test_mixed_volume_against_oracle(gpu_device):
     e64 = _rel(case, V64, sel, vo)
     errs = {}
     for lmin in (0, 3, 4):  # the tree's leaves reach level 4
-        case["plan"].set_precision(1, lmin)
+        case["plan"].set_precision(mode, lmin)
         fe, V = run_gpu(case)
         assert np.array_equal(fe, case["f_leaf"])
         errs[lmin] = _rel(case, V, sel, vo)
-        say(f"    mixed (sources at level >= {lmin}): rel Linf vs oracle {errs[lmin]:.3e}  (FP64 path {e64:.3e})")
+        say(f"    mixed mode {mode} (sources at level >= {lmin}): rel Linf vs oracle {errs[lmin]:.3e}  (FP64 path {e64:.3e})")
     case["plan"].set_precision(0)
     _, Vb = run_gpu(case)
     assert np.array_equal(Vb, V64)  # back to FP64: bitwise the FP64 result
@@ -45,44 +47,47 @@ def test_mixed_volume_against_oracle(gpu_device):
         assert e64 < errs[lmin] <= errs[0] * 1.01 + 1e-15
 
 
-def test_mixed_mode_with_no_mixed_pair_is_bitwise_fp64(gpu_device):
-    """Mode 1 with a level threshold above every leaf mixes no list-1 pair:
-    the pairs keep the FP64 tiles and kernels and the result is the FP64
-    plan's, bit for bit; with the threshold at the finest level the two
+@pytest.mark.parametrize("mode", [1, 2], ids=["bf16", "int8"])
+def test_mixed_mode_with_no_mixed_pair_is_bitwise_fp64(gpu_device, mode):
+    """A mixed mode with a level threshold above every leaf mixes no list-1
+    pair: the pairs keep the FP64 tiles and kernels and the result is the
+    FP64 plan's, bit for bit; with the threshold at the finest level the two
     paths differ, by about the slices' truncation (2^-32 of the row maxima
-    of the operands)."""
+    of the operands with bf16 slices, 2^-34 with int8 slices)."""
     case = setup("starfish_small", p=24, all_regular=True)
     lv = int(np.max(case["tree"]["level"]))
     _, V64 = run_gpu(case)
-    case["plan"].set_precision(1, lv + 1)
+    case["plan"].set_precision(mode, lv + 1)
     _, V = run_gpu(case)
     assert np.array_equal(V, V64)
-    case["plan"].set_precision(1, lv)
+    case["plan"].set_precision(mode, lv)
     _, Vf = run_gpu(case)
     d = float(np.abs(Vf - V64).max() / np.abs(V64).max())
-    say(f"    mixed only at level {lv}: rel Linf vs FP64 path {d:.3e}")
-    assert 0 < d <= 3e-9  # measured 7.3e-10
+    say(f"    mixed mode {mode} only at level {lv}: rel Linf vs FP64 path {d:.3e}")
+    assert 0 < d <= 3e-9  # measured 7.3e-10 with bf16 slices
 
 
-def test_mixed_end_to_end(gpu_device):
+@pytest.mark.parametrize("mode", [1, 2], ids=["bf16", "int8"])
+def test_mixed_end_to_end(gpu_device, mode):
     """Extension + volume with the mixed near field: V of the extended data
     against the oracle's V of the oracle's extension stays within the FP64
     path's error plus the mixed bound."""
     case = setup("starfish_small", p=24)
     sel, tx, ty = sample_targets(case, 300)
     fe64, V64 = run_gpu(case)
-    case["plan"].set_precision(1, 0)
+    case["plan"].set_precision(mode, 0)
     fe, V = run_gpu(case)
     assert np.array_equal(fe, fe64)  # the extension is FP64 in both modes
     d = float(np.abs(V - V64).max() / np.abs(V64).max())
-    say(f"    mixed vs FP64 path, end to end: rel Linf {d:.3e}")
-    assert d <= 8e-9  # measured 1.7e-9
+    say(f"    mixed mode {mode} vs FP64 path, end to end: rel Linf {d:.3e}")
+    assert d <= 8e-9  # measured 1.7e-9 with bf16 slices
 
 
 def test_mixed_rejects_other_grid_sizes(gpu_device):
     from paper_2211_14537_amd import vfx
     case = setup("disk_uniform3", p=20, all_regular=True)
-    with pytest.raises(vfx.VfxError):
-        case["plan"].set_precision(1, 0)
+    for mode in (1, 2):
+        with pytest.raises(vfx.VfxError):
+            case["plan"].set_precision(mode, 0)
     fe, V = run_gpu(case)  # the plan stays FP64 and usable
     assert np.isfinite(V).all()

@@ -229,6 +229,13 @@ def test_rejects_invalid_input():
         rc = vfx.lib().vfx_execute(plan._h, f_leaf, 0, fe_out, V_out, None)
         assert rc == vfx.VFX_EINVAL
         assert "16-byte aligned" in vfx.lib().vfx_last_error().decode()
+    # precision modes are 0, 1, 2; the mixed modes need K = 16
+    for mode in (-1, 3):
+        with pytest.raises(vfx.VfxError):
+            plan.set_precision(mode, 0)
+    for mode in (1, 2):
+        with pytest.raises(vfx.VfxError):
+            plan.set_precision(mode, 0)
 
 
 def test_near_lowrank_factors_match_oracle_quadrature():
