@@ -146,40 +146,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
   }
   __syncthreads();
   // A1: f_G = P_i f_I  (P_i: nG x ni row-major).  Wave w takes rows
-  // 16w..16w+15 in two passes of 8, lane l the columns l, l+64, ...; every
-  // load of a wave is 512 contiguous bytes of one row, and two column steps
-  // (16 loads) are in flight at once.  The 8 row partials are combined
-  // across the lanes by a recursive-halving reduce-scatter over lane bits
-  // 2..0 (lane l ends with row l & 7) and three plain butterfly steps over
-  // bits 3..5.  Rows >= 64 (a stencil degree above 10) use wave sums.  Few
-  // live registers keep six work-groups per CU resident, so the operators
-  // of all cut leaves stream at once.
+  // 16w..16w+15 in four passes of 4, lane l the columns l, l + 64, l + 128,
+  // l + 192 (then l + 256, ... for ni > 256): one pass reads four whole rows
+  // (ni <= 256), every load of a wave 512 contiguous bytes, 16 loads in
+  // flight at once.  The 4 row partials are combined across the lanes by a
+  // recursive-halving reduce-scatter over lane bits 1..0 (lane l ends with
+  // row l & 3) and four plain butterfly steps over bits 2..5.  Rows >= 64
+  // (a stencil degree above 10) use wave sums.  Few live registers keep six
+  // work-groups per CU resident, so the operators of all cut leaves stream
+  // at once.
   const double* P = pinv_val + (size_t)off * nG;
 #pragma unroll 1
-  for (int half = 0; half < 2; ++half) {
-    double acc[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-    const int r0 = 16 * wave + 8 * half;
+  for (int pass = 0; pass < 4; ++pass) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int r0 = 16 * wave + 4 * pass;
 #pragma unroll 1
-    for (int q = lane; q < ni; q += 128) {
-      const bool q2 = q + 64 < ni;
-      const double f0 = s_fI[q], f1 = q2 ? s_fI[q + 64] : 0.0;
-      double pa[8], pb[8];
+    for (int q = lane; q < ni; q += 256) {
+      double f[4], p[4][4];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
+      for (int j = 0; j < 4; ++j) f[j] = q + 64 * j < ni ? s_fI[q + 64 * j] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
         const int row = min(r0 + r, nG - 1);
-        pa[r] = P[row * ni + q];
-        pb[r] = q2 ? P[row * ni + q + 64] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[r][j] = q + 64 * j < ni ? P[row * ni + q + 64 * j] : 0.0;
       }
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
+      for (int r = 0; r < 4; ++r) {
         const double m = (r0 + r < nG) ? 1.0 : 0.0;
-        acc[r] += m * (pa[r] * f0 + pb[r] * f1);
+        acc[r] += m * (p[r][0] * f[0] + p[r][1] * f[1] + p[r][2] * f[2] + p[r][3] * f[3]);
       }
     }
 #pragma unroll
-    for (int s = 4; s >= 1; s >>= 1) {
+    for (int s = 2; s >= 1; s >>= 1) {
       const bool up = (lane & s) != 0;
 #pragma unroll
       for (int j = 0; j < s; ++j) {
@@ -188,10 +187,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
         acc[j] = keep + __shfl_xor(send, s, 64);
       }
     }
-    acc[0] += __shfl_xor(acc[0], 8, 64);
-    acc[0] += __shfl_xor(acc[0], 16, 64);
-    acc[0] += __shfl_xor(acc[0], 32, 64);
-    if (lane < 8 && r0 + lane < nG) s_fG[r0 + lane] = acc[0];
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1) acc[0] += __shfl_xor(acc[0], o, 64);
+    if (lane < 4 && r0 + lane < nG) s_fG[r0 + lane] = acc[0];
   }
   for (int r = 64 + wave; r < nG; r += blockDim.x / 64) {
     double a = 0.0;
