@@ -169,145 +169,171 @@ __device__ __forceinline__ void f8_phase1(const int8_t* __restrict__ xrow, long 
 // pairs 16w..16w+15).  LR: Z = X W^T (R_c ranks) in FP64, kept in LDS, cut
 // into slices per pair, then Y = Z Q^T; dense (self operator): Y = X A^T for
 // one block of 64 target rows (four row blocks per tile).  Results (FP64,
-// exponents applied) go to the per-pair products Y.  Persistent, XCD-aware
-// item order (items are configuration-major).
+// exponents applied) go to the per-pair products Y.
 template <bool LR>
+__device__ __forceinline__ void f8_item(int item, int nrb, const int* __restrict__ t_cfg,
+                                        const int* __restrict__ t_first, const int* __restrict__ t_count,
+                                        const int* __restrict__ src, const int* __restrict__ lr_R,
+                                        const int8_t* __restrict__ Wb, const int* __restrict__ Wexp,
+                                        const int8_t* __restrict__ Qb, const int* __restrict__ Qexp,
+                                        const int8_t* __restrict__ xs, const int* __restrict__ xe, long xs_slice,
+                                        double* __restrict__ Y, int8_t* sbuf, double* sZ, int* s_ez) {
+  constexpr int n = kF8N, LM = kNearLrMax;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tile = item / nrb, rb = item - tile * nrb;
+  const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
+  const int ent = 16 * w + li;  // this lane's A-operand pair
+  const int leaf = src[p0 + (ent < np ? ent : 0)];
+  const int8_t* xrow = xs + (size_t)leaf * n + 16 * lk;
+  const int my_ex = xe[leaf];
+  // exponents of the output rows this lane holds: pairs 16w + 4lk + e
+  int ex_out[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) ex_out[e] = __shfl(my_ex, 4 * lk + e, 16);
+  const int MT1 = LR ? lr_R[c] / 16 : 4;
+  const size_t wslice = LR ? (size_t)LM * n : (size_t)n * n;
+  const int8_t* wbase = LR ? Wb + (size_t)c * kF8S * wslice : Wb;
+  const int* wexp = LR ? Wexp + (size_t)c * LM : Wexp;
+  const int row0 = LR ? 0 : 64 * rb;
+  f8_v4 t[4][kF8S];
+  // padded ranks are 48 or 64 at K = 16; a smaller one takes the 48-row
+  // product (the table rows past the rank are zero)
+  if (MT1 <= 3)
+    f8_phase1<3>(xrow, xs_slice, wbase, wslice, row0, sbuf, t);
+  else
+    f8_phase1<4>(xrow, xs_slice, wbase, wslice, row0, sbuf, t);
+  if (!LR) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 64 * rb + 16 * r + li;
+      const int ei = wexp[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pe = 16 * w + 4 * lk + e;
+        if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(f8_value(t[r], e), ex_out[e] + ei - 12);
+      }
+    }
+    return;
+  }
+  // Z (FP64) of this wave's pairs to LDS (ranks >= R zero) and the
+  // exponent of every pair's row of Z: the maximum over the row is taken
+  // over r and over the 16 lanes li that hold it
+  int ez_out[4];
+  {
+    double m[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 16 * r + li;
+      const int ea = r < MT1 ? wexp[a] : 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double z = r < MT1 ? ldexp(f8_value(t[r], e), ex_out[e] + ea - 12) : 0.0;
+        sZ[(16 * w + 4 * lk + e) * kF8LDZ + a] = z;
+        m[e] = fmax(m[e], fabs(z));
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) m[e] = fmax(m[e], __shfl_xor(m[e], o, 16));
+      int ee = 0;
+      if (m[e] > 0.0) frexp(m[e], &ee);
+      ez_out[e] = ee;
+      if (li == 0) s_ez[16 * w + 4 * lk + e] = ee;
+    }
+  }
+  // phase 2: Y = Z Q^T over the target rows in four chunks of 64 (stage g:
+  // Q rows 64 g .. + 63, all 64 ranks, five slices), loaded two stages
+  // ahead into registers and stored one stage ahead into the other buffer
+  const int8_t* qbase = Qb + (size_t)c * kF8S * LM * n;
+  const int* qexp = Qexp + (size_t)c * n;
+  F8Stage st[2];
+  f8_gload(st[0], qbase, (size_t)LM * n, LM, 0, 0, 64);
+  f8_gload(st[1], qbase, (size_t)LM * n, LM, 64, 0, 64);
+  f8_lstore(st[0], sbuf);  // the last phase-1 barrier freed sbuf
+  f8_gload(st[0], qbase, (size_t)LM * n, LM, 128, 0, 64);
+  __syncthreads();  // Z, its exponents and stage 0 are in LDS
+  // A fragments of Z: this lane's pair 16w + li, ranks 16 lk + 0..15,
+  // five slices packed four bytes to a register
+  const int myez = s_ez[16 * w + li];
+  f8_v4 za[kF8S];
+  {
+    const double* zr = sZ + (16 * w + li) * kF8LDZ + 16 * lk;
+#pragma unroll
+    for (int s = 0; s < kF8S; ++s) za[s] = f8_v4{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      double r = ldexp(zr[k], 6 - myez);
+#pragma unroll
+      for (int s = 0; s < kF8S; ++s) {
+        if (s) r *= 128.0;
+        const double qv = rint(r);
+        za[s][k >> 2] |= ((int)qv & 0xff) << (8 * (k & 3));
+        r -= qv;
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int8_t* sb = sbuf + (g & 1) * kF8Buf;
+    if (g + 1 < 4) f8_lstore(st[(g + 1) & 1], sbuf + ((g + 1) & 1) * kF8Buf);
+    if (g + 3 < 4) f8_gload(st[(g + 1) & 1], qbase, (size_t)LM * n, LM, 64 * (g + 3), 0, 64);
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4) {  // one 16-row tile at a time: its products, then its outputs
+      f8_v4 t2[kF8S], b[kF8S];
+      f8_bfrag(sb, r4, b);
+      f8_zero(t2);
+      f8_block(za, b, t2);
+      const int i = 64 * g + 16 * r4 + li;
+      const int ei = qexp[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pe = 16 * w + 4 * lk + e;
+        if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(f8_value(t2, e), ez_out[e] + ei - 12);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The tiles of one configuration list: work items (tiles x row blocks),
+// row blocks per tile, the tile arrays and the phase-1 table.
+struct F8List {
+  int nitems, nrb;
+  const int *cfg, *first, *count;
+  const int8_t* W;
+  const int* Wexp;
+};
+
+// Both item kinds in one persistent launch: each XCD takes an even share of
+// the low-rank items (the heavier ones) and then an even share of the
+// self-operator items, so the lighter items fill the tail of the heavier
+// ones.  Items are configuration-major inside each kind, so an XCD's L2
+// holds the slices of the few configurations it works on.
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_near_f8(int nitems, int nrb, const int* __restrict__ t_cfg, const int* __restrict__ t_first,
-          const int* __restrict__ t_count, const int* __restrict__ src, const int* __restrict__ lr_R,
-          const int8_t* __restrict__ Wb, const int* __restrict__ Wexp, const int8_t* __restrict__ Qb,
-          const int* __restrict__ Qexp, const int8_t* __restrict__ xs, const int* __restrict__ xe, long xs_slice,
-          int L, double* __restrict__ Y, long sy) {
+k_near_f8(F8List lr, F8List dn, const int* __restrict__ src, const int* __restrict__ lr_R,
+          const int8_t* __restrict__ Qb, const int* __restrict__ Qexp, const int8_t* __restrict__ xs,
+          const int* __restrict__ xe, long xs_slice, int L, double* __restrict__ Y, long sy) {
   xs += blockIdx.y * kF8S * xs_slice;  // right-hand side blockIdx.y
   xe += blockIdx.y * L;
   Y += blockIdx.y * sy;
-  constexpr int n = kF8N, LM = kNearLrMax;
   __shared__ __attribute__((aligned(16))) int8_t sbuf[2 * kF8Buf];
-  __shared__ double sZ[LR ? 64 * kF8LDZ : 1];
+  __shared__ double sZ[64 * kF8LDZ];
   __shared__ int s_ez[64];
   const int nb = gridDim.x, bb = blockIdx.x;
   const int x = bb & 7;
-  const int q = nitems >> 3, rr = nitems & 7;
-  const int xfirst = x * q + min(x, rr), xcount = q + (x < rr ? 1 : 0);
+  const int qa = lr.nitems >> 3, ra = lr.nitems & 7, qb = dn.nitems >> 3, rb = dn.nitems & 7;
+  const int firstA = x * qa + min(x, ra), countA = qa + (x < ra ? 1 : 0);
+  const int firstB = x * qb + min(x, rb), countB = qb + (x < rb ? 1 : 0);
   const int xwgs = (nb - x + 7) >> 3;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  for (int j = bb >> 3; j < xcount; j += xwgs) {
-    const int item = xfirst + j;
-    const int tile = item / nrb, rb = item - tile * nrb;
-    const int c = t_cfg[tile], p0 = t_first[tile], np = t_count[tile];
-    const int ent = 16 * w + li;  // this lane's A-operand pair
-    const int leaf = src[p0 + (ent < np ? ent : 0)];
-    const int8_t* xrow = xs + (size_t)leaf * n + 16 * lk;
-    const int my_ex = xe[leaf];
-    // exponents of the output rows this lane holds: pairs 16w + 4lk + e
-    int ex_out[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) ex_out[e] = __shfl(my_ex, 4 * lk + e, 16);
-    const int MT1 = LR ? lr_R[c] / 16 : 4;
-    const size_t wslice = LR ? (size_t)LM * n : (size_t)n * n;
-    const int8_t* wbase = LR ? Wb + (size_t)c * kF8S * wslice : Wb;
-    const int* wexp = LR ? Wexp + (size_t)c * LM : Wexp;
-    const int row0 = LR ? 0 : 64 * rb;
-    f8_v4 t[4][kF8S];
-    // padded ranks are 48 or 64 at K = 16; a smaller one takes the 48-row
-    // product (the table rows past the rank are zero)
-    if (MT1 <= 3)
-      f8_phase1<3>(xrow, xs_slice, wbase, wslice, row0, sbuf, t);
+  for (int j = bb >> 3; j < countA + countB; j += xwgs) {
+    if (j < countA)
+      f8_item<true>(firstA + j, lr.nrb, lr.cfg, lr.first, lr.count, src, lr_R, lr.W, lr.Wexp, Qb, Qexp, xs, xe,
+                    xs_slice, Y, sbuf, sZ, s_ez);
     else
-      f8_phase1<4>(xrow, xs_slice, wbase, wslice, row0, sbuf, t);
-    if (!LR) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 64 * rb + 16 * r + li;
-        const int ei = wexp[i];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int pe = 16 * w + 4 * lk + e;
-          if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(f8_value(t[r], e), ex_out[e] + ei - 12);
-        }
-      }
-      continue;
-    }
-    // Z (FP64) of this wave's pairs to LDS (ranks >= R zero) and the
-    // exponent of every pair's row of Z: the maximum over the row is taken
-    // over r and over the 16 lanes li that hold it
-    int ez_out[4];
-    {
-      double m[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = 16 * r + li;
-        const int ea = r < MT1 ? wexp[a] : 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double z = r < MT1 ? ldexp(f8_value(t[r], e), ex_out[e] + ea - 12) : 0.0;
-          sZ[(16 * w + 4 * lk + e) * kF8LDZ + a] = z;
-          m[e] = fmax(m[e], fabs(z));
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-#pragma unroll
-        for (int o = 1; o < 16; o <<= 1) m[e] = fmax(m[e], __shfl_xor(m[e], o, 16));
-        int ee = 0;
-        if (m[e] > 0.0) frexp(m[e], &ee);
-        ez_out[e] = ee;
-        if (li == 0) s_ez[16 * w + 4 * lk + e] = ee;
-      }
-    }
-    // phase 2: Y = Z Q^T over the target rows in four chunks of 64 (stage g:
-    // Q rows 64 g .. + 63, all 64 ranks, five slices), loaded two stages
-    // ahead into registers and stored one stage ahead into the other buffer
-    const int8_t* qbase = Qb + (size_t)c * kF8S * LM * n;
-    const int* qexp = Qexp + (size_t)c * n;
-    F8Stage st[2];
-    f8_gload(st[0], qbase, (size_t)LM * n, LM, 0, 0, 64);
-    f8_gload(st[1], qbase, (size_t)LM * n, LM, 64, 0, 64);
-    f8_lstore(st[0], sbuf);  // the last phase-1 barrier freed sbuf
-    f8_gload(st[0], qbase, (size_t)LM * n, LM, 128, 0, 64);
-    __syncthreads();  // Z, its exponents and stage 0 are in LDS
-    // A fragments of Z: this lane's pair 16w + li, ranks 16 lk + 0..15,
-    // five slices packed four bytes to a register
-    const int myez = s_ez[16 * w + li];
-    f8_v4 za[kF8S];
-    {
-      const double* zr = sZ + (16 * w + li) * kF8LDZ + 16 * lk;
-#pragma unroll
-      for (int s = 0; s < kF8S; ++s) za[s] = f8_v4{0, 0, 0, 0};
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        double r = ldexp(zr[k], 6 - myez);
-#pragma unroll
-        for (int s = 0; s < kF8S; ++s) {
-          if (s) r *= 128.0;
-          const double qv = rint(r);
-          za[s][k >> 2] |= ((int)qv & 0xff) << (8 * (k & 3));
-          r -= qv;
-        }
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int8_t* sb = sbuf + (g & 1) * kF8Buf;
-      if (g + 1 < 4) f8_lstore(st[(g + 1) & 1], sbuf + ((g + 1) & 1) * kF8Buf);
-      if (g + 3 < 4) f8_gload(st[(g + 1) & 1], qbase, (size_t)LM * n, LM, 64 * (g + 3), 0, 64);
-#pragma unroll
-      for (int r4 = 0; r4 < 4; ++r4) {  // one 16-row tile at a time: its products, then its outputs
-        f8_v4 t2[kF8S], b[kF8S];
-        f8_bfrag(sb, r4, b);
-        f8_zero(t2);
-        f8_block(za, b, t2);
-        const int i = 64 * g + 16 * r4 + li;
-        const int ei = qexp[i];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int pe = 16 * w + 4 * lk + e;
-          if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(f8_value(t2, e), ez_out[e] + ei - 12);
-        }
-      }
-      __syncthreads();
-    }
+      f8_item<false>(firstB + j - countA, dn.nrb, dn.cfg, dn.first, dn.count, src, lr_R, dn.W, dn.Wexp, Qb, Qexp, xs,
+                     xe, xs_slice, Y, sbuf, sZ, s_ez);
   }
 }
 
@@ -325,18 +351,12 @@ int launch_near_f8(const Plan* p, const double* fe, int nrhs, int max_wgs, hipSt
   const long total = (long)H.L * kF8N, sNY = (long)H.np_src.size() * kF8N;
   int8_t* xs = (int8_t*)D.xs;  // 5 x L x n bytes per right-hand side fit the 4 x L x n bf16 slices' buffer
   hipLaunchKernelGGL(k_split5, dim3((H.L + 3) / 4, nrhs), dim3(256), 0, s, H.L, fe, xs, D.xs_exp);
-  if (!H.ml_cfg.empty()) {
-    const int items = (int)H.ml_cfg.size();
-    hipLaunchKernelGGL(k_near_f8<true>, dim3(persistent_grid_f8(items, max_wgs), nrhs), dim3(256), 0, s, items, 1,
-                       D.ml_cfg, D.ml_first, D.ml_count, D.np_src, DT.lr_R, DT.f8_W, DT.f8_Wexp, DT.f8_Q,
-                       DT.f8_Qexp, xs, D.xs_exp, total, H.L, D.near_y, sNY);
-  }
-  if (!H.mt_cfg.empty()) {
-    const int items = 4 * (int)H.mt_cfg.size();
-    hipLaunchKernelGGL(k_near_f8<false>, dim3(persistent_grid_f8(items, max_wgs), nrhs), dim3(256), 0, s, items, 4,
-                       D.mt_cfg, D.mt_first, D.mt_count, D.np_src, DT.lr_R, DT.f8_A, DT.f8_Aexp, DT.f8_Q,
-                       DT.f8_Qexp, xs, D.xs_exp, total, H.L, D.near_y, sNY);
-  }
+  const F8List lr{(int)H.ml_cfg.size(), 1, D.ml_cfg, D.ml_first, D.ml_count, DT.f8_W, DT.f8_Wexp};
+  const F8List dn{4 * (int)H.mt_cfg.size(), 4, D.mt_cfg, D.mt_first, D.mt_count, DT.f8_A, DT.f8_Aexp};
+  const int items = lr.nitems + dn.nitems;
+  if (items > 0)
+    hipLaunchKernelGGL(k_near_f8, dim3(persistent_grid_f8(items, max_wgs), nrhs), dim3(256), 0, s, lr, dn, D.np_src,
+                       DT.lr_R, DT.f8_Q, DT.f8_Qexp, xs, D.xs_exp, total, H.L, D.near_y, sNY);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     err = std::string("mixed near field (int8): ") + hipGetErrorString(e);
