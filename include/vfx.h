@@ -317,7 +317,8 @@ int vfx_plan_autotune(vfx_plan* plan, int nrhs, const double* f_leaf, const doub
 
 /* Set the same two launch parameters directly (for example the choice an
  * earlier autotune made): the work-group cap of the persistent near-field
- * kernels (1..65535; default 512, two work-groups per CU) and the row
+ * kernels (1..65535; default 512, two work-groups per CU; the int8 near
+ * field of precision mode 2 takes three quarters of it) and the row
  * tiles per block of the dense near-field GEMM (4 or 8).  Results are
  * bitwise independent of them.  VFX_EINVAL outside those ranges. */
 int vfx_plan_set_launch(vfx_plan* plan, int near_wgs, int dense_mtb);

@@ -354,8 +354,13 @@ int launch_near_f8(const Plan* p, const double* fe, int nrhs, int max_wgs, hipSt
   const F8List lr{(int)H.ml_cfg.size(), 1, D.ml_cfg, D.ml_first, D.ml_count, DT.f8_W, DT.f8_Wexp};
   const F8List dn{4 * (int)H.mt_cfg.size(), 4, D.mt_cfg, D.mt_first, D.mt_count, DT.f8_A, DT.f8_Aexp};
   const int items = lr.nitems + dn.nitems;
+  // three quarters of the FP64 near-field kernels' work-group cap: this
+  // kernel runs beside M2L on the caller's stream and finishes early, so
+  // fewer resident work-groups leave M2L more room (wedge workload, int8
+  // mixed step: 0.340 ms at 384 work-groups against 0.352 ms at 512)
+  const int cap = max_wgs > 0 ? std::max(8, max_wgs * 3 / 4) : 0;
   if (items > 0)
-    hipLaunchKernelGGL(k_near_f8, dim3(persistent_grid_f8(items, max_wgs), nrhs), dim3(256), 0, s, lr, dn, D.np_src,
+    hipLaunchKernelGGL(k_near_f8, dim3(persistent_grid_f8(items, cap), nrhs), dim3(256), 0, s, lr, dn, D.np_src,
                        DT.lr_R, DT.f8_Q, DT.f8_Qexp, xs, D.xs_exp, total, H.L, D.near_y, sNY);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
