@@ -70,9 +70,10 @@ def test_batch_matches_single_executes(gpu_device, name, precision):
         g1, g3, wext = _against_oracle(case, fl[r], fc[r], FE[r], V[r], seed=r)
         say(f"    rhs {r}: V rel Linf vs oracle {g1:.2e} (end to end {g3:.2e}), extension err/bound {wext:.2f}")
         # FP64: the method's 1e-10 (1e-9 at p = 20, the order the disk
-        # workload states, whose truncation error is ~1e-9); mixed: 5x the
-        # 3.7e-10 measured on these noisy inputs
-        tol = (1e-9 if name == "disk_uniform3" else 1e-10) if precision == 0 else 2e-9
+        # workload states, whose truncation error is ~1e-9); mixed: about 5x
+        # the 3.7e-10 (bf16 slices) and 2.3e-10 (int8 slices) measured on
+        # these noisy inputs
+        tol = (1e-9 if name == "disk_uniform3" else 1e-10) if precision == 0 else {1: 2e-9, 2: 1.5e-9}[precision]
         assert g1 <= tol
         assert wext <= 1.0
 
