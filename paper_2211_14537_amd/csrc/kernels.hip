@@ -154,7 +154,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
   // row l & 3) and four plain butterfly steps over bits 2..5.  Rows >= 64
   // (a stencil degree above 10) use wave sums.  Few live registers keep six
   // work-groups per CU resident, so the operators of all cut leaves stream
-  // at once.
+  // at once; P_i is read once per execute, so its loads are non-temporal
+  // (they do not displace the data the later kernels reuse).
   const double* P = pinv_val + (size_t)off * nG;
 #pragma unroll 1
   for (int pass = 0; pass < 4; ++pass) {
@@ -169,7 +170,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
       for (int r = 0; r < 4; ++r) {
         const int row = min(r0 + r, nG - 1);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) p[r][j] = q + 64 * j < ni ? P[row * ni + q + 64 * j] : 0.0;
+        for (int j = 0; j < 4; ++j)
+          p[r][j] = q + 64 * j < ni ? __builtin_nontemporal_load(P + row * ni + q + 64 * j) : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -808,7 +810,8 @@ __global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __
       if (en >= np) continue;
       if constexpr (EPI == 0) {
 #pragma unroll
-        for (int r = 0; r < MTB; ++r) Y[(size_t)(p0 + en) * R + row0 + 16 * r + li] = acc[r][e];
+        for (int r = 0; r < MTB; ++r)
+          __builtin_nontemporal_store(acc[r][e], &Y[(size_t)(p0 + en) * R + row0 + 16 * r + li]);
       } else {
         const int b = leaf_box[src[p0 + en]];
         const double h = box_side(root_size, box_level[b]);
@@ -968,7 +971,7 @@ __device__ __forceinline__ void near_lr_item(const double* __restrict__ xrow, co
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ent = 16 * pg + lk + 4 * e;
-      if (ent < np) Yp[(size_t)ent * KD + HK * hf + 16 * r + li] = acc2[r][e];
+      if (ent < np) __builtin_nontemporal_store(acc2[r][e], &Yp[(size_t)ent * KD + HK * hf + 16 * r + li]);
     }
 }
 
@@ -1260,6 +1263,9 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
 // expansion, the list slots) comes in with one vector load, lane k holding
 // item k, and is broadcast with readlane, so no step waits on a chain of
 // scalar loads.  One wave per leaf keeps the whole grid resident at once.
+// Each row of the per-pair and M2P products is read once, by its target's
+// wave: those loads are non-temporal, as are the stores that write them.
+typedef double vfx_d2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long u = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)u, l);
@@ -1324,7 +1330,8 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
       for (int e = 0; e < n1; ++e) {
         const double* y = Y + (size_t)__builtin_amdgcn_readlane(my_slot, e) * n;
         if constexpr (NPL == 4) {
-          const double2 u0 = *(const double2*)(y + 4 * lane), u1 = *(const double2*)(y + 4 * lane + 2);
+          const vfx_d2 u0 = __builtin_nontemporal_load((const vfx_d2*)(y + 4 * lane)),
+                       u1 = __builtin_nontemporal_load((const vfx_d2*)(y + 4 * lane + 2));
           yn[0] += u0.x;
           yn[1] += u0.y;
           yn[2] += u1.x;
@@ -1340,7 +1347,8 @@ __global__ void __launch_bounds__(64) k_far(int K, int Prt, double root_size, co
     for (int q = 0; q < n3; ++q) {
       const double* y = Y3 + (size_t)__builtin_amdgcn_readlane(my_slot3, q) * n;
       if constexpr (NPL == 4) {
-        const double2 u0 = *(const double2*)(y + 4 * lane), u1 = *(const double2*)(y + 4 * lane + 2);
+        const vfx_d2 u0 = __builtin_nontemporal_load((const vfx_d2*)(y + 4 * lane)),
+                     u1 = __builtin_nontemporal_load((const vfx_d2*)(y + 4 * lane + 2));
         y3[0] += u0.x;
         y3[1] += u0.y;
         y3[2] += u1.x;
