@@ -810,8 +810,7 @@ __global__ void __launch_bounds__(256) k_tgemm(int nitems, int MT, const int* __
       if (en >= np) continue;
       if constexpr (EPI == 0) {
 #pragma unroll
-        for (int r = 0; r < MTB; ++r)
-          __builtin_nontemporal_store(acc[r][e], &Y[(size_t)(p0 + en) * R + row0 + 16 * r + li]);
+        for (int r = 0; r < MTB; ++r) Y[(size_t)(p0 + en) * R + row0 + 16 * r + li] = acc[r][e];
       } else {
         const int b = leaf_box[src[p0 + en]];
         const double h = box_side(root_size, box_level[b]);
@@ -971,7 +970,7 @@ __device__ __forceinline__ void near_lr_item(const double* __restrict__ xrow, co
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ent = 16 * pg + lk + 4 * e;
-      if (ent < np) __builtin_nontemporal_store(acc2[r][e], &Yp[(size_t)ent * KD + HK * hf + 16 * r + li]);
+      if (ent < np) Yp[(size_t)ent * KD + HK * hf + 16 * r + li] = acc2[r][e];
     }
 }
 
@@ -1264,7 +1263,9 @@ __global__ void __launch_bounds__(64) k_down(int Prt, double root_size, const in
 // item k, and is broadcast with readlane, so no step waits on a chain of
 // scalar loads.  One wave per leaf keeps the whole grid resident at once.
 // Each row of the per-pair and M2P products is read once, by its target's
-// wave: those loads are non-temporal, as are the stores that write them.
+// wave: those loads are non-temporal.  (The kernels that write the rows use
+// plain stores, so that part of them is still in the last-level cache when
+// this kernel runs; non-temporal stores there measured slower.)
 typedef double vfx_d2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double readlane_d(double v, int l) {
   const long long u = __double_as_longlong(v);

@@ -169,8 +169,7 @@ __device__ __forceinline__ void f8_phase1(const int8_t* __restrict__ xrow, long 
 // pairs 16w..16w+15).  LR: Z = X W^T (R_c ranks) in FP64, kept in LDS, cut
 // into slices per pair, then Y = Z Q^T; dense (self operator): Y = X A^T for
 // one block of 64 target rows (four row blocks per tile).  Results (FP64,
-// exponents applied) go to the per-pair products Y (non-temporal stores:
-// each row is read once, by the far-field kernel).
+// exponents applied) go to the per-pair products Y.
 template <bool LR>
 __device__ __forceinline__ void f8_item(int item, int nrb, const int* __restrict__ t_cfg,
                                         const int* __restrict__ t_first, const int* __restrict__ t_count,
@@ -212,8 +211,7 @@ __device__ __forceinline__ void f8_item(int item, int nrb, const int* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int pe = 16 * w + 4 * lk + e;
-        if (pe < np)
-          __builtin_nontemporal_store(ldexp(f8_value(t[r], e), ex_out[e] + ei - 12), &Y[(size_t)(p0 + pe) * n + i]);
+        if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(f8_value(t[r], e), ex_out[e] + ei - 12);
       }
     }
     return;
@@ -292,8 +290,7 @@ __device__ __forceinline__ void f8_item(int item, int nrb, const int* __restrict
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int pe = 16 * w + 4 * lk + e;
-        if (pe < np)
-          __builtin_nontemporal_store(ldexp(f8_value(t2, e), ez_out[e] + ei - 12), &Y[(size_t)(p0 + pe) * n + i]);
+        if (pe < np) Y[(size_t)(p0 + pe) * n + i] = ldexp(f8_value(t2, e), ez_out[e] + ei - 12);
       }
     }
     __syncthreads();
