@@ -418,6 +418,12 @@ int vfx_plan_timings(vfx_plan* plan, double* ms, int n_out);
  *            (a, b) of the K x K grid: (A, B) = swapped ? (b, a) : (a, b),
  *            a' = (g & 2) ? K-1-A : A, b' = (g & 4) ? K-1-B : B
  *            (all -1 when K != 16)
+ *        25, 27 (K = 16, `index` = configuration): the fixed-point slices
+ *            of the mixed-precision kernels (25 int8, five slices; 27
+ *            bf16, four slices; as doubles): W slices [s][a][j], 64 W
+ *            exponents, Q slices [s][i][a], n Q exponents (64 ranks,
+ *            padded); 26, 28 (`index` ignored): the self table's slices
+ *            [s][i][j] and its n row exponents
  * VFX_EINVAL if `which`, `index` or `count` does not match. */
 int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64_t count);
 /* Interaction list `which` (1..4) of a plan as CSR arrays (host):

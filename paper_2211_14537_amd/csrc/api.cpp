@@ -647,6 +647,43 @@ int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64
       size = (int64_t)v.size();
       break;
     }
+    case 25:
+    case 26:
+    case 27:
+    case 28: {
+      // fixed-point slices of the near-field operators as doubles: 25/27 the
+      // low-rank factors of configuration `index` (W slices [s][a][j], W
+      // exponents [a], Q slices [s][i][a], Q exponents [i]), 26/28 the self
+      // table (slices [s][i][j], exponents [i]); 25/26 int8, 27/28 bf16
+      static thread_local std::vector<double> v;
+      v.clear();
+      const bool i8 = which == 25 || which == 26, self = which == 26 || which == 28;
+      const int ns = i8 ? 5 : 4;
+      if (T.f8_W.empty() || (!self && (index < 0 || index >= vfx::kNearConfigs))) break;
+      auto bf = [](uint16_t h) {
+        const uint32_t u = (uint32_t)h << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return (double)f;
+      };
+      const size_t SW = (size_t)vfx::kNearLrMax * n;
+      if (self) {
+        for (size_t k = 0; k < (size_t)ns * n * n; ++k) v.push_back(i8 ? (double)T.f8_A[k] : bf(T.fx_A[k]));
+        for (int64_t i = 0; i < n; ++i) v.push_back(i8 ? T.f8_Aexp[i] : T.fx_Aexp[i]);
+      } else {
+        const size_t c = (size_t)index;
+        for (size_t k = 0; k < (size_t)ns * SW; ++k)
+          v.push_back(i8 ? (double)T.f8_W[c * ns * SW + k] : bf(T.fx_W[c * ns * SW + k]));
+        for (int a = 0; a < vfx::kNearLrMax; ++a)
+          v.push_back(i8 ? T.f8_Wexp[c * vfx::kNearLrMax + a] : T.fx_Wexp[c * vfx::kNearLrMax + a]);
+        for (size_t k = 0; k < (size_t)ns * SW; ++k)
+          v.push_back(i8 ? (double)T.f8_Q[c * ns * SW + k] : bf(T.fx_Q[c * ns * SW + k]));
+        for (int64_t i = 0; i < n; ++i) v.push_back(i8 ? T.f8_Qexp[c * n + i] : T.fx_Qexp[c * n + i]);
+      }
+      src = v.data();
+      size = (int64_t)v.size();
+      break;
+    }
     case 23:
       if (index < 0 || index >= vfx::kP2LSlots) break;
       src = T.m2p_gemm.data() + (size_t)index * T.p2l_rows * n;

@@ -359,3 +359,53 @@ def test_near_symmetry_classes():
         m = node_map(g[c])
         worst = max(worst, np.abs(Tc[np.ix_(m, m)] - Tb).max() / np.abs(Tb).max())
     assert worst <= 1e-13
+
+
+@pytest.mark.parametrize("i8", [True, False], ids=["int8", "bf16"])
+def test_fixed_point_slices_reconstruct_the_near_tables(i8):
+    """The fixed-point slices the mixed-precision kernels multiply: every
+    operand row v is 2^e sum_s q_s w_s up to the stated residual, with e
+    the exponent of max|v| (max|v| < 2^e) and the slices integers in their
+    range (int8: five slices, w_s = 2^(-6-7s), |q_s| <= 64, residual
+    2^(e-35); bf16: four slices, w_s = 2^(-8(s+1)), |q_0| <= 256, |q_s| <=
+    128, residual 2^(e-33)).  Rebuilt here from that definition and compared
+    with the FP64 tables the library applies (W, Q of the low-rank
+    operators, and the self table)."""
+    ctx = vfx.Context(16, 24)
+    n, LM = 256, 64
+    ns = 5 if i8 else 4
+    w = np.array([2.0 ** (-6 - 7 * s) for s in range(5)] if i8 else [2.0 ** (-8 * (s + 1)) for s in range(4)])
+    qmax = np.array([64.0] * 5 if i8 else [256.0, 128.0, 128.0, 128.0])
+    resid = 35 if i8 else 33
+
+    def check(rows, slices, exps):
+        # rows: m x len, slices: ns x m x len, exps: m
+        assert np.array_equal(slices, np.rint(slices))
+        assert np.all(np.abs(slices) <= qmax[:, None, None])
+        m = np.abs(rows).max(axis=1)
+        nz = m > 0
+        assert np.all(m[nz] < np.ldexp(1.0, exps[nz].astype(int)))
+        assert np.all(m[nz] >= np.ldexp(0.5, exps[nz].astype(int)))
+        assert np.all(slices[:, ~nz, :] == 0)
+        rebuilt = np.ldexp(np.tensordot(w, slices, axes=(0, 0)), exps.astype(int)[:, None])
+        bound = np.ldexp(1.0, exps.astype(int) - resid)[:, None]
+        assert np.all(np.abs(rebuilt - rows) <= bound)
+
+    which = 25 if i8 else 27
+    rk = ctx.debug_table(22, 0, 66)
+    for c in (0, 5, 12, 30):
+        if rk[c] == 0:
+            continue
+        t = ctx.debug_table(which, c, 2 * ns * LM * n + LM + n)
+        o = 0
+        Ws = t[o:o + ns * LM * n].reshape(ns, LM, n); o += ns * LM * n
+        We = t[o:o + LM]; o += LM
+        Qs = t[o:o + ns * n * LM].reshape(ns, n, LM); o += ns * n * LM
+        Qe = t[o:o + n]
+        W = ctx.debug_table(20, c, n * LM).reshape(n, LM).T  # rows a, along j
+        Q = ctx.debug_table(21, c, n * LM).reshape(LM, n).T  # rows i, along a
+        check(W, Ws, We)
+        check(Q, Qs, Qe)
+    t = ctx.debug_table(which + 1, 0, ns * n * n + n)
+    A = ctx.debug_table(0, 4, n * n).reshape(n, n).T  # self table, row i (target), column j
+    check(A, t[:ns * n * n].reshape(ns, n, n), t[ns * n * n:])
