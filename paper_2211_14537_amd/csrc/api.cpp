@@ -658,7 +658,7 @@ int vfx_debug_table(const vfx_ctx* ctx, int which, int index, double* out, int64
       static thread_local std::vector<double> v;
       v.clear();
       const bool i8 = which == 25 || which == 26, self = which == 26 || which == 28;
-      const int ns = i8 ? 5 : 4;
+      const int ns = i8 ? vfx::kF8Slices : 4;
       if (T.f8_W.empty() || (!self && (index < 0 || index >= vfx::kNearConfigs))) break;
       auto bf = [](uint16_t h) {
         const uint32_t u = (uint32_t)h << 16;

@@ -394,7 +394,7 @@ static uint16_t bf16_of_int(double q) {
   std::memcpy(&u, &f, 4);
   return (uint16_t)(u >> 16);
 }
-// The same cut into five int8 slices for the int8 matrix cores:
+// The same cut into kF8Slices = 5 int8 slices for the int8 matrix cores:
 // v_k = 2^e sum_{s<5} q_s[k] 2^(-6-7s) up to 2^(e-35), |q_s[k]| <= 64, so a
 // slice product is at most 2^12 and int32 sums over the whole contraction
 // stay exact.
@@ -405,7 +405,7 @@ static int f8_split(const double* v, int count, long stride, int8_t* out, long s
   if (m > 0.0) std::frexp(m, &e);
   for (int k = 0; k < count; ++k) {
     double r = std::ldexp(v[k * stride], 6 - e);
-    for (int sl = 0; sl < 5; ++sl) {
+    for (int sl = 0; sl < kF8Slices; ++sl) {
       if (sl) r *= 128.0;
       const double q = std::nearbyint(r);
       out[sl * slice_stride + k * out_stride] = (int8_t)(int)q;
@@ -551,10 +551,10 @@ static void build_near_lowrank(Tables& T) {
   }
   for (int i = 0; i < n; ++i)  // fx_A[s][i][j] = T_self[i][j] = near[self][j][i]
     T.fx_Aexp[i] = fx_split(&T.near[(size_t)kNearSelf * n * n + i], n, n, &T.fx_A[(size_t)i * n], (long)n * n, 1);
-  // int8 slices, same layouts with five slices
-  T.f8_W.assign((size_t)kNearConfigs * 5 * SW, 0);
-  T.f8_Q.assign((size_t)kNearConfigs * 5 * SW, 0);
-  T.f8_A.assign((size_t)5 * n * n, 0);
+  // int8 slices, same layouts with kF8Slices slices
+  T.f8_W.assign((size_t)kNearConfigs * kF8Slices * SW, 0);
+  T.f8_Q.assign((size_t)kNearConfigs * kF8Slices * SW, 0);
+  T.f8_A.assign((size_t)kF8Slices * n * n, 0);
   T.f8_Wexp.assign((size_t)kNearConfigs * kNearLrMax, 0);
   T.f8_Qexp.assign((size_t)kNearConfigs * n, 0);
   T.f8_Aexp.assign(n, 0);
@@ -562,11 +562,11 @@ static void build_near_lowrank(Tables& T) {
     for (int a = 0; a < kNearLrMax; ++a)
       T.f8_Wexp[(size_t)c * kNearLrMax + a] =
           f8_split(&T.lr_W[(size_t)c * n * kNearLrMax + a], n, kNearLrMax,
-                   &T.f8_W[(size_t)c * 5 * SW + (size_t)a * n], (long)SW, 1);
+                   &T.f8_W[(size_t)c * kF8Slices * SW + (size_t)a * n], (long)SW, 1);
     for (int i = 0; i < n; ++i)
       T.f8_Qexp[(size_t)c * n + i] =
           f8_split(&T.lr_Q[(size_t)c * kNearLrMax * n + i], kNearLrMax, n,
-                   &T.f8_Q[(size_t)c * 5 * SW + (size_t)i * kNearLrMax], (long)SW, 1);
+                   &T.f8_Q[(size_t)c * kF8Slices * SW + (size_t)i * kNearLrMax], (long)SW, 1);
   }
   for (int i = 0; i < n; ++i)
     T.f8_Aexp[i] = f8_split(&T.near[(size_t)kNearSelf * n * n + i], n, n, &T.f8_A[(size_t)i * n], (long)n * n, 1);

@@ -92,7 +92,7 @@ struct Tables {
   // (v = 2^e sum_s q_s 2^(-8(s+1)), q_s integers of magnitude <= 256)
   std::vector<uint16_t> fx_W, fx_Q, fx_A;
   std::vector<int> fx_Wexp, fx_Qexp, fx_Aexp;
-  // the same operands as five int8 slices for the int8 matrix cores
+  // the same operands as kF8Slices int8 slices for the int8 matrix cores
   // (v = 2^e sum_s q_s 2^(-6-7s), q_s integers of magnitude <= 64)
   std::vector<int8_t> f8_W, f8_Q, f8_A;
   std::vector<int> f8_Wexp, f8_Qexp, f8_Aexp;
@@ -337,6 +337,8 @@ int launch_ext_gemm(const Plan* p, const double* f_cut, int nrhs, hipStream_t s,
 int launch_ext_eval(const Plan* p, const double* f_cut, double* fe, int nrhs, hipStream_t s, std::string& err);
 // mixed.hip
 int launch_near_fx(const Plan* p, const double* fe, int nrhs, int max_wgs, hipStream_t s, std::string& err);
+// int8 slices per operand row of the mixed-precision near field (mode 2)
+constexpr int kF8Slices = 5;
 int launch_near_f8(const Plan* p, const double* fe, int nrhs, int max_wgs, hipStream_t s, std::string& err);
 // near.hip
 int launch_near_ts(const Plan* p, const double* fe, double* V, int nrhs, int max_wgs, hipStream_t s,
