@@ -148,9 +148,12 @@ def _against_oracle(case, f_leaf, f_cut, fe, V, seed=0, n_nodes=160):
     return g1, g3, worst
 
 
-def test_graph_of_several_plans_replays_bitwise(gpu_device):
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "int8_near"])
+def test_graph_of_several_plans_replays_bitwise(gpu_device, mixed):
     import torch
     cases = [setup("starfish_small", p=24), setup("disk_uniform3", p=20), setup("disk_adaptive_small", p=40)]
+    if mixed:  # the K = 16 plan with the int8 near field (split and near kernels inside the graph)
+        cases[0]["plan"].set_precision(2, 0)
     bufs = []
     for i, c in enumerate(cases):
         fl, fc = _inputs(c, 2, 10 + i)
@@ -180,13 +183,17 @@ def test_graph_of_several_plans_replays_bitwise(gpu_device):
             assert np.array_equal(V.cpu().numpy(), V0)
         _ = (torch.ones(1000, device="cuda:0") * rep).sum().item()  # eager work between replays
     g.close()
-    say("    graph of 3 plans x 2 right-hand sides: 3 replays bitwise equal to eager")
+    say(f"    graph of 3 plans x 2 right-hand sides{' (int8 near field in plan 0)' if mixed else ''}: "
+        "3 replays bitwise equal to eager")
     # every plan's replayed result (second right-hand side) against the oracle
     for i, (c, (FL, FC, FE, V)) in enumerate(zip(cases, bufs)):
         g1, g3, wext = _against_oracle(c, FL[1].cpu().numpy(), FC[1].cpu().numpy(), FE[1].cpu().numpy(),
                                        V[1].cpu().numpy(), seed=i)
         say(f"    plan {i}: V rel Linf vs oracle {g1:.2e} (end to end {g3:.2e}), extension err/bound {wext:.2f}")
-        assert g1 <= (1e-9 if i == 1 else 1e-10) and wext <= 1.0  # plan 1: disk workload at p = 20
+        # plan 1: disk workload at p = 20; plan 0 with the int8 near field:
+        # the batch test's gate for these noisy inputs
+        tol = 1e-9 if i == 1 else (1.5e-9 if mixed and i == 0 else 1e-10)
+        assert g1 <= tol and wext <= 1.0
 
 
 def test_graph_refuses_stale_plans_and_foreign_captures(gpu_device):
