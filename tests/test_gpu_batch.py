@@ -345,3 +345,33 @@ def test_autotune_keeps_results(gpu_device):
         torch.cuda.synchronize()
         assert np.array_equal(V.cpu().numpy(), V0), (w, m)
     say(f"    autotune choice {ch}; results unchanged")
+
+
+def test_batched_gemm_extension_with_int8_near_field(gpu_device):
+    """A batch of 12 right-hand sides (the extension's products as GEMMs)
+    with the int8 near field: the first and the last right-hand side against
+    the oracle's V of the batch's own f^e, and every right-hand side against
+    the same batch in FP64 (the extension is FP64 in both, so f^e is
+    bitwise the same and V differs by the slices' truncation only)."""
+    import torch
+    case = setup("starfish_small", p=24)
+    nrhs = 12
+    fl, fc = _inputs(case, nrhs, 5)
+    FL, FC = _dev(fl), _dev(fc)
+    FE, V = torch.empty_like(FL), torch.empty_like(FL)
+    case["plan"].execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    FE64, V64 = FE.cpu().numpy(), V.cpu().numpy()
+    case["plan"].set_precision(2, 0)
+    case["plan"].execute_batch(nrhs, FL, FC, FE, V)
+    torch.cuda.synchronize()
+    FEm, Vm = FE.cpu().numpy(), V.cpu().numpy()
+    case["plan"].set_precision(0)
+    assert np.array_equal(FEm, FE64)
+    d = max(float(np.abs(Vm[r] - V64[r]).max() / np.abs(V64[r]).max()) for r in range(nrhs))
+    say(f"    batch of {nrhs}, int8 near field against FP64: rel Linf {d:.3e}")
+    assert 0 < d <= 4e-9  # measured 1.2e-9
+    for r in (0, nrhs - 1):
+        g1, g3, wext = _against_oracle(case, fl[r], fc[r], FEm[r], Vm[r], seed=r)
+        say(f"    rhs {r}: V rel Linf vs oracle {g1:.2e} (end to end {g3:.2e}), extension err/bound {wext:.2f}")
+        assert g1 <= 1.5e-9  # the batch test's gate for int8 slices on these noisy inputs
